@@ -1,0 +1,238 @@
+"""Seeded synthetic interferometer workloads.
+
+Everything here produces *inputs* to gridding: antenna positions, baseline
+vectors, Earth-rotation (u, v, w) tracks in wavelengths, complex visibility
+samples and weights.  The scale factors that make the tracks fit a grid
+(cell size, w range) are chosen here too, because they are properties of the
+synthetic observation, not of the gridding method.
+
+The uvw transform is the textbook one (Thompson, Moran & Swenson,
+"Interferometry and Synthesis in Radio Astronomy", ch. 4): a local
+East-North-Up baseline is rotated into the equatorial (X, Y, Z) frame at the
+site latitude, then projected onto (u, v, w) for hour angle H and declination
+delta.
+
+The paper's own data set (a simulated MeerKAT observation, Section 5) is not
+available; these tracks stand in for it with the same structure: baselines of
+an array observed over Earth rotation, visibilities ordered by baseline and
+then time.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+C_LIGHT = 299792458.0
+
+
+def antenna_enu(rng: np.random.Generator, n_ant: int, radius_m: float) -> np.ndarray:
+    """East/North positions uniform in a disk of ``radius_m``; Up = 0.  Shape [n_ant, 3]."""
+    r = radius_m * np.sqrt(rng.random(n_ant))
+    th = 2.0 * math.pi * rng.random(n_ant)
+    enu = np.zeros((n_ant, 3), dtype=np.float64)
+    enu[:, 0] = r * np.cos(th)
+    enu[:, 1] = r * np.sin(th)
+    return enu
+
+
+def baseline_pairs(n_ant: int) -> np.ndarray:
+    """All pairs p < q in p-major order, shape [n_bl, 2]."""
+    p, q = np.triu_indices(n_ant, k=1)
+    return np.stack([p, q], axis=1)
+
+
+def enu_baselines_to_uvw(b_enu: np.ndarray, lat_rad: float, dec_rad: float,
+                         hour_angles: np.ndarray, freqs_hz: np.ndarray) -> np.ndarray:
+    """Baselines [n_bl, 3] (metres, ENU) -> uvw [n_bl, n_t, n_ch, 3] in wavelengths."""
+    e, n, up = b_enu[:, 0], b_enu[:, 1], b_enu[:, 2]
+    sl, cl = math.sin(lat_rad), math.cos(lat_rad)
+    x = -sl * n + cl * up
+    y = e
+    z = cl * n + sl * up
+    sd, cd = math.sin(dec_rad), math.cos(dec_rad)
+    sh = np.sin(hour_angles)[None, :]
+    ch = np.cos(hour_angles)[None, :]
+    x, y, z = x[:, None], y[:, None], z[:, None]
+    u = sh * x + ch * y
+    v = -sd * ch * x + sd * sh * y + cd * z
+    w = cd * ch * x - cd * sh * y + sd * z
+    uvw_m = np.stack([u, v, w], axis=-1)                      # [n_bl, n_t, 3]
+    inv_lambda = (freqs_hz / C_LIGHT)[None, None, :, None]     # [1, 1, n_ch, 1]
+    return uvw_m[:, :, None, :] * inv_lambda                   # [n_bl, n_t, n_ch, 3]
+
+
+def _hour_angles(span_h: float, n_t: int) -> np.ndarray:
+    """Midpoints of ``n_t`` equal intervals over ``span_h`` hours, centred on transit."""
+    step = span_h / n_t
+    hours = (np.arange(n_t) + 0.5) * step - span_h / 2.0
+    return hours * (2.0 * math.pi / 24.0)
+
+
+@dataclasses.dataclass
+class Workload:
+    """One gridding problem: inputs plus the scale parameters of the observation."""
+    name: str
+    uvw: np.ndarray                 # float64 [N, 3], wavelengths
+    vis: np.ndarray                 # complex64 [N, P]
+    weights: Optional[np.ndarray]   # float32 [N, P] or None (all ones)
+    height: int
+    width: int
+    support: int
+    oversample: int
+    inv_cell_u: float               # pixels per wavelength
+    inv_cell_v: float
+    n_planes: int = 1
+    w_min: float = 0.0              # plane = rint((w - w_min) * inv_dw)
+    inv_dw: float = 0.0
+    w_hat_scale: float = 0.0        # w (wavelengths) -> w in pixel units for the W kernel
+    beta: float = 8.6               # Kaiser-Bessel shape
+    support_aa: int = 8             # anti-aliasing kernel width inside the W kernel
+    kernel: str = "kb"              # "kb" (real separable) or "wsep" (complex separable W)
+    meta: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def n_vis(self) -> int:
+        return int(self.uvw.shape[0])
+
+    @property
+    def n_pol(self) -> int:
+        return int(self.vis.shape[1])
+
+    def plane_w_hat(self) -> np.ndarray:
+        """w (pixel units) at the centre of each plane."""
+        if self.n_planes <= 1 or self.inv_dw == 0.0:
+            return np.zeros(max(self.n_planes, 1))
+        k = np.arange(self.n_planes, dtype=np.float64)
+        return (self.w_min + k / self.inv_dw) * self.w_hat_scale
+
+
+def _fit_scale(uvw: np.ndarray, height: int, width: int, support: int) -> float:
+    """Pixels per wavelength so that max(|u|, |v|) lands S/2 + 2 pixels inside the edge."""
+    umax = float(np.max(np.abs(uvw[:, 0])))
+    vmax = float(np.max(np.abs(uvw[:, 1])))
+    half = min(height, width) // 2 - support // 2 - 2
+    return half / max(umax, vmax)
+
+
+def _w_planes(uvw: np.ndarray, n_planes: int, w_hat_max: float):
+    """Symmetric linear plane spacing over [-max|w|, +max|w|]."""
+    wmax = float(np.max(np.abs(uvw[:, 2])))
+    w_min = -wmax
+    inv_dw = (n_planes - 1) / (2.0 * wmax)
+    return w_min, inv_dw, w_hat_max / wmax
+
+
+def _draw_vis(rng: np.random.Generator, n: int, n_pol: int) -> np.ndarray:
+    re = rng.standard_normal((n, n_pol), dtype=np.float32)
+    im = rng.standard_normal((n, n_pol), dtype=np.float32)
+    return (re + 1j * im).astype(np.complex64)
+
+
+def tiny_kb_workload(seed: int = 0) -> Workload:
+    """8 antennas (28 baselines), 1 channel at 1.4 GHz, 256 dumps over 1 h,
+    512x512 grid, one polarisation, real Kaiser-Bessel kernel S=8, O=8."""
+    rng = np.random.default_rng(seed)
+    enu = antenna_enu(rng, 8, 1000.0)
+    pairs = baseline_pairs(8)
+    b = enu[pairs[:, 1]] - enu[pairs[:, 0]]
+    uvw = enu_baselines_to_uvw(b, math.radians(-30.7), math.radians(-30.0),
+                               _hour_angles(1.0, 256), np.array([1.4e9]))
+    uvw = uvw.reshape(-1, 3)
+    vis = _draw_vis(rng, uvw.shape[0], 1)
+    s = _fit_scale(uvw, 512, 512, 8)
+    return Workload("tiny-kb-512", uvw, vis, None, 512, 512, 8, 8, s, s,
+                    kernel="kb", beta=8.6)
+
+
+def full_shape_workload(support: int, seed: int = 0, n_baselines: Optional[int] = None,
+                        n_times: int = 1024, n_chan: int = 16, grid: int = 4096,
+                        n_planes: int = 32, n_pol: int = 4, n_ant: int = 64) -> Workload:
+    """64 antennas (2016 baselines) x 1024 dumps over 8 h x 16 channels across
+    1.4 GHz +/- 5 %, four polarisations, 4096^2 grid, complex separable W
+    kernel with ``support`` taps, 32 w-planes, oversampling 8.  Visibilities are
+    ordered by baseline, then time, then channel.
+
+    ``n_baselines`` keeps only the first baselines (same tracks, fewer rows) for
+    tests that need the real geometry at a smaller size; the scale factors are
+    always those of the full array so positions do not change.
+    """
+    rng = np.random.default_rng(seed)
+    enu = antenna_enu(rng, n_ant, 1000.0)
+    pairs = baseline_pairs(n_ant)
+    b = enu[pairs[:, 1]] - enu[pairs[:, 0]]
+    freqs = np.linspace(1.4e9 * 0.95, 1.4e9 * 1.05, n_chan)
+    uvw_full = enu_baselines_to_uvw(b, math.radians(-30.7), math.radians(-30.0),
+                                    _hour_angles(8.0, n_times), freqs)
+    flat = uvw_full.reshape(-1, 3)
+    s = _fit_scale(flat, grid, grid, support)
+    w_min, inv_dw, w_hat_scale = _w_planes(flat, n_planes, float(support - 8))
+    if n_baselines is not None:
+        flat = uvw_full[:n_baselines].reshape(-1, 3)
+    flat = np.ascontiguousarray(flat)
+    vis = _draw_vis(rng, flat.shape[0], n_pol)
+    return Workload(f"full-shape-S{support}", flat, vis, None, grid, grid, support, 8, s, s,
+                    n_planes=n_planes, w_min=w_min, inv_dw=inv_dw, w_hat_scale=w_hat_scale,
+                    kernel="wsep", beta=8.6, support_aa=8)
+
+
+def batch_workload(seed: int = 0, n_instances: int = 32):
+    """Uneven batch: per instance N ~ lognormal over 1e4..1e6 (clipped), grid side
+    in {1024, 2048, 4096}, support in {8, 16, 32}, P in {1, 4}; each instance is
+    a single-channel stream of a 64-antenna array (baselines then time)."""
+    rng = np.random.default_rng(seed)
+    enu = antenna_enu(rng, 64, 1000.0)
+    pairs = baseline_pairs(64)
+    b = enu[pairs[:, 1]] - enu[pairs[:, 0]]
+    out = []
+    for i in range(n_instances):
+        n_i = int(np.clip(round(math.exp(rng.normal(math.log(1e5), 1.1513))), 1e4, 1e6))
+        side = int(rng.choice([1024, 2048, 4096]))
+        sup = int(rng.choice([8, 16, 32]))
+        npol = int(rng.choice([1, 4]))
+        freq = 1.4e9 * (0.95 + 0.1 * rng.random())
+        n_t = -(-n_i // len(pairs))
+        uvw = enu_baselines_to_uvw(b, math.radians(-30.7), math.radians(-30.0),
+                                   _hour_angles(8.0, n_t), np.array([freq]))
+        flat = np.ascontiguousarray(uvw.reshape(-1, 3)[:n_i])
+        s = _fit_scale(flat, side, side, sup)
+        n_planes = 32 if sup > 8 else 1
+        if n_planes > 1:
+            w_min, inv_dw, whs = _w_planes(flat, n_planes, float(sup - 8))
+            kern = "wsep"
+        else:
+            w_min, inv_dw, whs = 0.0, 0.0, 0.0
+            kern = "kb"
+        vis = _draw_vis(rng, n_i, npol)
+        out.append(Workload(f"batch{i}", flat, vis, None, side, side, sup, 8, s, s,
+                            n_planes=n_planes, w_min=w_min, inv_dw=inv_dw, w_hat_scale=whs,
+                            kernel=kern))
+    return out
+
+
+def random_point_workload(n_vis: int, n_pol: int, height: int, width: int, support: int,
+                          oversample: int, seed: int, n_planes: int = 1,
+                          margin: int = 0, weights: bool = False,
+                          kernel: str = "kb") -> Workload:
+    """Uniformly scattered (u, v, w) points: no track structure.  Used for small
+    parity and edge-case tests.  ``margin`` pixels beyond the grid edge are
+    allowed so that some footprints fall off the grid and get dropped."""
+    rng = np.random.default_rng(seed)
+    inv_cell = 1.0
+    half_u = width / 2 - support / 2 - 1 + margin
+    half_v = height / 2 - support / 2 - 1 + margin
+    u = rng.uniform(-half_u, half_u, n_vis)
+    v = rng.uniform(-half_v, half_v, n_vis)
+    w = rng.uniform(-100.0, 100.0, n_vis)
+    uvw = np.stack([u, v, w], axis=1)
+    vis = _draw_vis(rng, n_vis, n_pol)
+    wts = rng.uniform(0.5, 2.0, (n_vis, n_pol)).astype(np.float32) if weights else None
+    if n_planes > 1:
+        w_min, inv_dw, whs = -100.0, (n_planes - 1) / 200.0, float(max(support - 8, 0)) / 100.0
+    else:
+        w_min, inv_dw, whs = 0.0, 0.0, 0.0
+    return Workload(f"points-{n_vis}", uvw, vis, wts, height, width, support, oversample,
+                    inv_cell, inv_cell, n_planes=n_planes, w_min=w_min, inv_dw=inv_dw,
+                    w_hat_scale=whs, kernel=kernel)
