@@ -1,0 +1,158 @@
+/*
+ * gridder.h -- C ABI of the MI355X (gfx950) convolutional gridding library.
+ *
+ * Method: B. Merry, "Faster GPU-based convolutional gridding via thread
+ * coarsening" (Astronomy and Computing, 2016; arXiv:1605.07023).
+ *
+ * Conventions shared by every entry point
+ *   - Pointers named dev_* or described as "device" are device (HBM) pointers
+ *     owned by the caller; the library keeps no reference after the call
+ *     returns, allocates no device memory, and never synchronises the device.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is only enqueued on it.
+ *   - Every argument is validated on the host before anything is enqueued.
+ *     A non-OK status means nothing was enqueued (except GR_EDEVICE, which
+ *     reports a failed launch).  gr_last_error() returns a thread-local
+ *     message for the last non-OK status.  The library never aborts.
+ *   - complex64 is interleaved (re, im) float32, the layout of torch.complex64.
+ *   - Grid layout: complex64 [P][H][W], row-major; cell (y, x) with uv = 0 at
+ *     (H/2, W/2), u along x (columns), v along y (rows).
+ */
+#ifndef GRIDDER_H
+#define GRIDDER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GR_OK = 0,
+  GR_EINVAL = -1,       /* invalid argument (null pointer, bad size, ...) */
+  GR_ENOMEM = -2,       /* workspace too small */
+  GR_EDEVICE = -3,      /* HIP launch or runtime error */
+  GR_EUNSUPPORTED = -4  /* valid but not supported by this build (e.g. table too large) */
+} gr_status;
+
+typedef enum { GR_F32 = 0, GR_F16 = 1, GR_BF16 = 2, GR_F64 = 3 } gr_dtype;
+
+typedef enum { GR_SEPARABLE = 0, GR_TABLE2D = 1 } gr_kernel_kind;
+
+/* Gridding convolution function (GCF) description (Section 2.2: precomputed
+ * tables sampled at `oversample` times the grid resolution; Section 4: a
+ * separable GCF, G_ij = G^u_i G^v_j, the same for every polarisation).
+ *
+ * A visibility at pixel position p = ix + s/O (see gr_preprocess) has footprint
+ * cells ix - S/2 + 1 ... ix + S/2 on each axis; tap k of phase s multiplies
+ * cell ix - S/2 + 1 + k and samples the GCF at k - S/2 + 1 - s/O.
+ *
+ * taps (device):
+ *   GR_SEPARABLE: [n_planes][O][S] elements, used along u and along v;
+ *   GR_TABLE2D:   [n_planes][O][O][S][S] indexed [plane][s_v][s_u][k_v][k_u].
+ * Element type `tap_dtype` (GR_F32, GR_F16 or GR_BF16); complex taps are
+ * (re, im) pairs of that type. */
+typedef struct {
+  int32_t kind;          /* gr_kernel_kind */
+  int32_t tap_dtype;     /* gr_dtype of each tap component */
+  int32_t taps_complex;  /* 1: complex taps, 0: real taps */
+  int32_t support;       /* S: even, 2..64 */
+  int32_t oversample;    /* O: power of two, 1..128 */
+  int32_t n_planes;      /* >= 1; plane index selected from w when > 1 */
+  double w_min;          /* plane = rint((w - w_min) * inv_dw) in FP64 */
+  double inv_dw;
+  const void* taps;      /* device */
+} gr_kernel;
+
+/* Work-decomposition parameters (Sections 3-4 and the autotuning of
+ * Section 4).  Any field <= 0 selects the library default for it.
+ *   cu, cv      thread-coarsening factors: each work-item owns a cu x cv block
+ *               of cells (Section 3); 1, 2, 4 or 8
+ *   wg_u, wg_v  tile shape in blocks handled by one wave (Section 2.2 tiles)
+ *   vis_per_wg  visibilities per work-group (Section 4 uses 1024)
+ *   variant     0 = library choice, 1 = VALU work-item kernel, 2 = MFMA kernel */
+typedef struct {
+  int32_t cu, cv, wg_u, wg_v, vis_per_wg, variant;
+} gr_tuning;
+
+/* Preprocess (Section 4: integer grid coordinates, sub-grid coordinates for
+ * indexing the GCF, the w-plane index and the pre-weighted visibility are
+ * prepared once, before gridding).  Per visibility n, in FP64:
+ *   fx = rint(u * (inv_cell_u * O)) + (W/2) O   (round half to even)
+ *   ix = fx >> log2 O, sx = fx & (O - 1), x0 = ix - S/2 + 1   (likewise v, y)
+ *   plane = rint((w - w_min) * inv_dw), or 0 when n_planes == 1.
+ * A visibility is dropped (record marked invalid, counted) when any of its
+ * u, v, w, visibility or weight values is not finite, its plane is outside
+ * [0, n_planes), or its footprint leaves the H x W grid.
+ *
+ *   uvw       device f64 [n_vis][3], wavelengths
+ *   vis       device [n_vis][n_pol] complex: vis_dtype GR_F32 = complex64;
+ *             GR_F16 = (re, im) float16 pairs scaled by vis_scale[n / 256]
+ *   vis_scale device f32 [ceil(n_vis / 256)] (GR_F16 only, else NULL)
+ *   weights   device f32 [n_vis][n_pol] or NULL (all ones)
+ *   records   device out, 8 bytes per visibility: two uint32,
+ *             {x0 | y0 << 16} and {sx | sy << 8 | plane << 16 | valid << 31}
+ *   wvis      device out, complex64 [n_vis][n_pol] weighted visibilities
+ *   dev_stats device int64 [2] or NULL: {gridded, dropped} are ADDED to it */
+gr_status gr_preprocess(const double* uvw, const void* vis, int32_t vis_dtype,
+                        const float* vis_scale, const float* weights, int64_t n_vis,
+                        int32_t n_pol, const gr_kernel* kernel, double inv_cell_u,
+                        double inv_cell_v, int32_t height, int32_t width, void* records,
+                        void* wvis, int64_t* dev_stats, void* stream);
+
+/* Grid preprocessed visibilities (records/wvis from gr_preprocess, in the same
+ * order as the input) onto grid, complex64 [n_pol][height][width], which is
+ * ACCUMULATED into (+=).  This is the Romein work distribution with thread
+ * coarsening (Sections 2.2-4): work-groups take fixed chunks of consecutive
+ * visibilities x tiles of the bin; each work-item keeps a register block of
+ * cu x cv cells per polarisation and flushes it with atomic adds when the
+ * block leaves the bounding box, and at the end of the chunk.
+ * tuning may be NULL (defaults). */
+gr_status gr_grid_records(const void* records, const void* wvis, int64_t n_vis, int32_t n_pol,
+                          const gr_kernel* kernel, void* grid, int32_t height, int32_t width,
+                          const gr_tuning* tuning, void* stream);
+
+/* Bytes of workspace gr_grid needs for n_vis visibilities of n_pol polarisations. */
+size_t gr_grid_workspace_bytes(int64_t n_vis, int32_t n_pol);
+
+/* The whole hot path: gr_preprocess into `workspace`, then gr_grid_records.
+ * Same arguments and semantics as those two calls. */
+gr_status gr_grid(const double* uvw, const void* vis, int32_t vis_dtype, const float* vis_scale,
+                  const float* weights, int64_t n_vis, int32_t n_pol, const gr_kernel* kernel,
+                  double inv_cell_u, double inv_cell_v, void* grid, int32_t height,
+                  int32_t width, const gr_tuning* tuning, void* workspace,
+                  size_t workspace_bytes, int64_t* dev_stats, void* stream);
+
+/* Kaiser-Bessel taps (real, one plane), evaluated in FP64 on the device and
+ * stored as out_dtype (GR_F64, GR_F32, GR_F16 or GR_BF16), layout [O][S]:
+ *   tap[s][k] = I0(beta sqrt(1 - (2 d / S)^2)) / I0(beta) for |d| < S/2 else 0,
+ *   d = k - S/2 + 1 - s/O.
+ * (Section 2.2: an anti-aliasing GCF tabulated with oversampling.) */
+gr_status gr_make_kb_table(double beta, int32_t support, int32_t oversample, int32_t out_dtype,
+                           void* out, void* stream);
+
+/* Separable W-projection taps (Section 2.2 treats the w term as a
+ * convolution; Section 4 uses a separable approximation), complex, evaluated
+ * in FP64 on the device, layout [n_planes][O][S] of (re, im) out_dtype pairs:
+ *   g(d) = c * sum_{j<M} t(nu_j) exp(-i pi w_hat nu_j^2) exp(-2 pi i d nu_j)
+ * with nu_j = (j + 1/2)/M - 1/2, t the image response of a Kaiser-Bessel
+ * window of width support_aa and shape beta, w_hat = w_hat_first + plane *
+ * w_hat_step (w in pixel units), M = n_samples (<= 0: 4 S), c normalising the
+ * w = 0, s = 0 taps to unit sum, and g = 0 where |d| >= S/2. */
+gr_status gr_make_wkernel_table(int32_t support, int32_t oversample, int32_t n_planes,
+                                double w_hat_first, double w_hat_step, int32_t support_aa,
+                                double beta, int32_t n_samples, int32_t out_dtype, void* out,
+                                void* stream);
+
+/* Thread-local description of the last non-OK status ("" if none). */
+const char* gr_last_error(void);
+
+/* Library ABI version (increments on incompatible changes). */
+int32_t gr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRIDDER_H */

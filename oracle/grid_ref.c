@@ -105,6 +105,11 @@ int64_t oracle_grid_sep(int64_t n, int P, const float* vis, const float* weights
 #pragma omp parallel for schedule(static) reduction(+ : dropped)
   for (int64_t i = 0; i < n; ++i) {
     pixel_coords_one(uvw + 3 * i, inv_cell_u, inv_cell_v, O, S, H, W, n_planes, w_min, inv_dw, cs + i);
+    /* a visibility with a non-finite value or weight is dropped too */
+    for (int p = 0; p < P && cs[i].valid; ++p) {
+      if (!isfinite(vis[(i * P + p) * 2]) || !isfinite(vis[(i * P + p) * 2 + 1])) cs[i].valid = 0;
+      if (weights && !isfinite(weights[i * P + p])) cs[i].valid = 0;
+    }
     dropped += !cs[i].valid;
   }
   if (rows == NULL) {

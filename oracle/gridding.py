@@ -214,6 +214,16 @@ def pixel_coords(uvw: np.ndarray, inv_cell_u: float, inv_cell_v: float, oversamp
     return dict(x0=x0, y0=y0, sx=sx, sy=sy, plane=plane, valid=valid, fx=fx, fy=fy)
 
 
+def finite_values(vis: np.ndarray, weights: Optional[np.ndarray]) -> np.ndarray:
+    """True per visibility when all its visibility and weight values are finite.
+    Reading (paper silent): such a visibility is dropped like one with bad uvw."""
+    ok = np.all(np.isfinite(np.asarray(vis).view(np.float32 if np.asarray(vis).dtype == np.complex64
+                                                  else np.float64)), axis=1)
+    if weights is not None:
+        ok &= np.all(np.isfinite(np.asarray(weights)), axis=1)
+    return ok
+
+
 def weighted_vis(vis: np.ndarray, weights: Optional[np.ndarray]) -> np.ndarray:
     """Pre-weighted visibilities (Section 4), complex128 [N][P]; weights default to 1."""
     v = np.asarray(vis).astype(np.complex128)
@@ -243,6 +253,7 @@ def grid_separable(vis: np.ndarray, uvw: np.ndarray, weights: Optional[np.ndarra
     n_pol = vis.shape[1]
     pc = pixel_coords(uvw, inv_cell_u, inv_cell_v, oversample, support, height, width,
                       n_planes, w_min, inv_dw)
+    pc["valid"] = pc["valid"] & finite_values(vis, weights)
     wv = weighted_vis(vis, weights)
     out = np.zeros((n_pol, height, width), np.complex128) if grid is None \
         else np.array(grid, dtype=np.complex128, copy=True)
@@ -276,6 +287,7 @@ def grid_table2d(vis: np.ndarray, uvw: np.ndarray, weights: Optional[np.ndarray]
     n_pol = vis.shape[1]
     pc = pixel_coords(uvw, inv_cell_u, inv_cell_v, oversample, support, height, width,
                       n_planes, w_min, inv_dw)
+    pc["valid"] = pc["valid"] & finite_values(vis, weights)
     wv = weighted_vis(vis, weights)
     out = np.zeros((n_pol, height, width), np.complex128) if grid is None \
         else np.array(grid, dtype=np.complex128, copy=True)

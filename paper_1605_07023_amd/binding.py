@@ -1,0 +1,160 @@
+"""ctypes binding to libgridder.so: argument marshalling only.
+
+Every function has the name and argument order of the C entry point in
+include/gridder.h.  Device buffers are torch tensors (their data pointers are
+passed through); ``stream=None`` means torch's current stream on the
+tensor's device.  A non-OK status raises :class:`GridderError` carrying the
+library's message.  Nothing here computes any part of gridding.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libgridder.so")
+_lib = None
+
+GR_OK, GR_EINVAL, GR_ENOMEM, GR_EDEVICE, GR_EUNSUPPORTED = 0, -1, -2, -3, -4
+GR_F32, GR_F16, GR_BF16, GR_F64 = 0, 1, 2, 3
+GR_SEPARABLE, GR_TABLE2D = 0, 1
+_STATUS = {GR_EINVAL: "EINVAL", GR_ENOMEM: "ENOMEM", GR_EDEVICE: "EDEVICE", GR_EUNSUPPORTED: "EUNSUPPORTED"}
+
+
+class GridderError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class GrKernel(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("tap_dtype", ctypes.c_int32),
+                ("taps_complex", ctypes.c_int32), ("support", ctypes.c_int32),
+                ("oversample", ctypes.c_int32), ("n_planes", ctypes.c_int32),
+                ("w_min", ctypes.c_double), ("inv_dw", ctypes.c_double),
+                ("taps", ctypes.c_void_p)]
+
+
+class GrTuning(ctypes.Structure):
+    _fields_ = [("cu", ctypes.c_int32), ("cv", ctypes.c_int32), ("wg_u", ctypes.c_int32),
+                ("wg_v", ctypes.c_int32), ("vis_per_wg", ctypes.c_int32),
+                ("variant", ctypes.c_int32)]
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load_library():
+    """Load libgridder.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise GridderError(GR_EDEVICE, f"{_LIB_PATH} is missing: run __graft_entry__.build() "
+                                       "(there is no CPU fallback)")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P, I32, I64, D, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    KP, TP = ctypes.POINTER(GrKernel), ctypes.POINTER(GrTuning)
+    sigs = {
+        "gr_preprocess": [P, P, I32, P, P, I64, I32, KP, D, D, I32, I32, P, P, P, P],
+        "gr_grid_records": [P, P, I64, I32, KP, P, I32, I32, TP, P],
+        "gr_grid": [P, P, I32, P, P, I64, I32, KP, D, D, P, I32, I32, TP, P, SZ, P, P],
+        "gr_make_kb_table": [D, I32, I32, I32, P, P],
+        "gr_make_wkernel_table": [I32, I32, I32, D, D, I32, D, I32, I32, P, P],
+    }
+    for name, args in sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.gr_grid_workspace_bytes.argtypes = [I64, I32]
+    lib.gr_grid_workspace_bytes.restype = SZ
+    lib.gr_last_error.argtypes = []
+    lib.gr_last_error.restype = ctypes.c_char_p
+    lib.gr_version.argtypes = []
+    lib.gr_version.restype = I32
+    _lib = lib
+    return lib
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream, *tensors):
+    if stream is not None:
+        return stream if isinstance(stream, int) else stream.cuda_stream
+    import torch
+    dev = next((t.device for t in tensors if t is not None and hasattr(t, "device")), None)
+    return torch.cuda.current_stream(dev).cuda_stream
+
+
+def _check(st: int) -> None:
+    if st != GR_OK:
+        raise GridderError(st, load_library().gr_last_error().decode())
+
+
+def gr_version() -> int:
+    return int(load_library().gr_version())
+
+
+def gr_last_error() -> str:
+    return load_library().gr_last_error().decode()
+
+
+def gr_grid_workspace_bytes(n_vis: int, n_pol: int) -> int:
+    return int(load_library().gr_grid_workspace_bytes(n_vis, n_pol))
+
+
+def make_kernel(taps, support: int, oversample: int, n_planes: int = 1, taps_complex: bool = True,
+                tap_dtype: int = GR_F32, w_min: float = 0.0, inv_dw: float = 0.0,
+                kind: int = GR_SEPARABLE) -> GrKernel:
+    """Fill a gr_kernel descriptor; ``taps`` is a device tensor (kept alive by the caller)."""
+    return GrKernel(kind, tap_dtype, 1 if taps_complex else 0, support, oversample, n_planes,
+                    w_min, inv_dw, _ptr(taps))
+
+
+def gr_preprocess(uvw, vis, vis_dtype, vis_scale, weights, n_vis, n_pol, kernel: GrKernel,
+                  inv_cell_u, inv_cell_v, height, width, records, wvis, dev_stats, stream=None):
+    lib = load_library()
+    _check(lib.gr_preprocess(_ptr(uvw), _ptr(vis), vis_dtype, _ptr(vis_scale), _ptr(weights),
+                             n_vis, n_pol, ctypes.byref(kernel), inv_cell_u, inv_cell_v, height,
+                             width, _ptr(records), _ptr(wvis), _ptr(dev_stats),
+                             _stream(stream, uvw, vis, records)))
+
+
+def gr_grid_records(records, wvis, n_vis, n_pol, kernel: GrKernel, grid, height, width,
+                    tuning: Optional[GrTuning] = None, stream=None):
+    lib = load_library()
+    _check(lib.gr_grid_records(_ptr(records), _ptr(wvis), n_vis, n_pol, ctypes.byref(kernel),
+                               _ptr(grid), height, width,
+                               ctypes.byref(tuning) if tuning is not None else None,
+                               _stream(stream, grid)))
+
+
+def gr_grid(uvw, vis, vis_dtype, vis_scale, weights, n_vis, n_pol, kernel: GrKernel, inv_cell_u,
+            inv_cell_v, grid, height, width, tuning: Optional[GrTuning], workspace,
+            workspace_bytes, dev_stats, stream=None):
+    lib = load_library()
+    _check(lib.gr_grid(_ptr(uvw), _ptr(vis), vis_dtype, _ptr(vis_scale), _ptr(weights), n_vis,
+                       n_pol, ctypes.byref(kernel), inv_cell_u, inv_cell_v, _ptr(grid), height,
+                       width, ctypes.byref(tuning) if tuning is not None else None,
+                       _ptr(workspace), workspace_bytes, _ptr(dev_stats),
+                       _stream(stream, grid, uvw)))
+
+
+def gr_make_kb_table(beta, support, oversample, out_dtype, out, stream=None):
+    _check(load_library().gr_make_kb_table(beta, support, oversample, out_dtype, _ptr(out),
+                                           _stream(stream, out)))
+
+
+def gr_make_wkernel_table(support, oversample, n_planes, w_hat_first, w_hat_step, support_aa,
+                          beta, n_samples, out_dtype, out, stream=None):
+    _check(load_library().gr_make_wkernel_table(support, oversample, n_planes, w_hat_first,
+                                                w_hat_step, support_aa, beta, n_samples,
+                                                out_dtype, _ptr(out), _stream(stream, out)))

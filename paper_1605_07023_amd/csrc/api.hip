@@ -1,0 +1,137 @@
+// C-ABI entry points: host-side validation, workspace layout, dispatch.
+#include <cmath>
+#include <string>
+
+#include "internal.h"
+
+namespace gr {
+
+namespace {
+thread_local std::string g_last_error;
+bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+gr_status fail(gr_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+gr_status check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(GR_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  return GR_OK;
+}
+
+gr_status validate_kernel(const gr_kernel* k, bool need_taps) {
+  if (k == nullptr) return fail(GR_EINVAL, "kernel descriptor is NULL");
+  if (k->kind != GR_SEPARABLE) return fail(GR_EUNSUPPORTED, "only GR_SEPARABLE kernels are supported");
+  if (k->support < 2 || k->support > 64 || (k->support & 1))
+    return fail(GR_EINVAL, "kernel.support must be even, 2..64");
+  if (!pow2(k->oversample) || k->oversample > kMaxOversample)
+    return fail(GR_EINVAL, "kernel.oversample must be a power of two <= 128");
+  if (k->n_planes < 1 || k->n_planes > kMaxPlanes)
+    return fail(GR_EINVAL, "kernel.n_planes must be in 1..32767");
+  if (k->n_planes > 1 && (!std::isfinite(k->w_min) || !std::isfinite(k->inv_dw)))
+    return fail(GR_EINVAL, "kernel.w_min / inv_dw must be finite");
+  if (k->tap_dtype != GR_F32 && k->tap_dtype != GR_F16 && k->tap_dtype != GR_BF16)
+    return fail(GR_EINVAL, "kernel.tap_dtype must be GR_F32, GR_F16 or GR_BF16");
+  if (need_taps && k->taps == nullptr) return fail(GR_EINVAL, "kernel.taps is NULL");
+  return GR_OK;
+}
+
+namespace {
+
+gr_status validate_grid(int n_pol, int height, int width, int support) {
+  if (n_pol != 1 && n_pol != 4) return fail(GR_EINVAL, "n_pol must be 1 or 4");
+  if (height < support || width < support || height > kMaxGrid || width > kMaxGrid)
+    return fail(GR_EINVAL, "grid height/width must be in [support, 32768]");
+  return GR_OK;
+}
+
+}  // namespace
+
+}  // namespace gr
+
+using namespace gr;
+
+extern "C" const char* gr_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" int32_t gr_version(void) { return 1; }
+
+extern "C" size_t gr_grid_workspace_bytes(int64_t n_vis, int32_t n_pol) {
+  if (n_vis < 0 || n_pol < 1) return 0;
+  return align256(sizeof(Record) * (size_t)n_vis) + align256(sizeof(float2) * (size_t)n_vis * n_pol);
+}
+
+extern "C" gr_status gr_preprocess(const double* uvw, const void* vis, int32_t vis_dtype,
+                                   const float* vis_scale, const float* weights, int64_t n_vis,
+                                   int32_t n_pol, const gr_kernel* kernel, double inv_cell_u,
+                                   double inv_cell_v, int32_t height, int32_t width,
+                                   void* records, void* wvis, int64_t* dev_stats, void* stream) {
+  gr_status st = validate_kernel(kernel, false);
+  if (st != GR_OK) return st;
+  if ((st = validate_grid(n_pol, height, width, kernel->support)) != GR_OK) return st;
+  if (n_vis < 0) return fail(GR_EINVAL, "n_vis must be >= 0");
+  if (n_vis > 0 && (uvw == nullptr || vis == nullptr || records == nullptr || wvis == nullptr))
+    return fail(GR_EINVAL, "gr_preprocess: uvw, vis, records and wvis must be non-NULL");
+  if (vis_dtype != GR_F32 && vis_dtype != GR_F16)
+    return fail(GR_EINVAL, "vis_dtype must be GR_F32 (complex64) or GR_F16 (scaled half pairs)");
+  if (vis_dtype == GR_F16 && n_vis > 0 && vis_scale == nullptr)
+    return fail(GR_EINVAL, "GR_F16 visibilities need vis_scale");
+  if (!std::isfinite(inv_cell_u) || !std::isfinite(inv_cell_v) || inv_cell_u <= 0 || inv_cell_v <= 0)
+    return fail(GR_EINVAL, "inv_cell_u / inv_cell_v must be finite and > 0");
+  return launch_preprocess(uvw, vis, vis_dtype, vis_scale, weights, n_vis, n_pol, *kernel, inv_cell_u,
+                           inv_cell_v, height, width, reinterpret_cast<Record*>(records),
+                           reinterpret_cast<float2*>(wvis), dev_stats, (hipStream_t)stream);
+}
+
+extern "C" gr_status gr_grid_records(const void* records, const void* wvis, int64_t n_vis,
+                                     int32_t n_pol, const gr_kernel* kernel, void* grid,
+                                     int32_t height, int32_t width, const gr_tuning* tuning,
+                                     void* stream) {
+  gr_status st = validate_kernel(kernel, true);
+  if (st != GR_OK) return st;
+  if ((st = validate_grid(n_pol, height, width, kernel->support)) != GR_OK) return st;
+  if (n_vis < 0) return fail(GR_EINVAL, "n_vis must be >= 0");
+  if (grid == nullptr) return fail(GR_EINVAL, "grid is NULL");
+  if (n_vis > 0 && (records == nullptr || wvis == nullptr))
+    return fail(GR_EINVAL, "records and wvis must be non-NULL");
+  if (tuning && tuning->variant != 0 && tuning->variant != 1)
+    return fail(GR_EUNSUPPORTED, "tuning.variant not available in this build");
+  RomeinPlan plan;
+  if ((st = plan_romein(*kernel, n_pol, tuning, &plan)) != GR_OK) return st;
+  return launch_romein(reinterpret_cast<const Record*>(records), reinterpret_cast<const float2*>(wvis),
+                       n_vis, n_pol, *kernel, reinterpret_cast<float2*>(grid), height, width, plan,
+                       (hipStream_t)stream);
+}
+
+extern "C" gr_status gr_grid(const double* uvw, const void* vis, int32_t vis_dtype,
+                             const float* vis_scale, const float* weights, int64_t n_vis,
+                             int32_t n_pol, const gr_kernel* kernel, double inv_cell_u,
+                             double inv_cell_v, void* grid, int32_t height, int32_t width,
+                             const gr_tuning* tuning, void* workspace, size_t workspace_bytes,
+                             int64_t* dev_stats, void* stream) {
+  gr_status st = validate_kernel(kernel, true);
+  if (st != GR_OK) return st;
+  if ((st = validate_grid(n_pol, height, width, kernel->support)) != GR_OK) return st;
+  if (n_vis < 0) return fail(GR_EINVAL, "n_vis must be >= 0");
+  if (grid == nullptr) return fail(GR_EINVAL, "grid is NULL");
+  const size_t need = gr_grid_workspace_bytes(n_vis, n_pol);
+  if (n_vis > 0 && workspace == nullptr) return fail(GR_EINVAL, "workspace is NULL");
+  if (workspace_bytes < need) return fail(GR_ENOMEM, "workspace too small (see gr_grid_workspace_bytes)");
+  RomeinPlan plan;
+  if ((st = plan_romein(*kernel, n_pol, tuning, &plan)) != GR_OK) return st;
+  if (tuning && tuning->variant != 0 && tuning->variant != 1)
+    return fail(GR_EUNSUPPORTED, "tuning.variant not available in this build");
+  auto* rec = reinterpret_cast<Record*>(workspace);
+  auto* wv = reinterpret_cast<float2*>(reinterpret_cast<char*>(workspace) +
+                                       align256(sizeof(Record) * (size_t)n_vis));
+  st = gr_preprocess(uvw, vis, vis_dtype, vis_scale, weights, n_vis, n_pol, kernel, inv_cell_u,
+                     inv_cell_v, height, width, rec, wv, dev_stats, stream);
+  if (st != GR_OK) return st;
+  return launch_romein(rec, wv, n_vis, n_pol, *kernel, reinterpret_cast<float2*>(grid), height, width,
+                       plan, (hipStream_t)stream);
+}

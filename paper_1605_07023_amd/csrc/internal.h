@@ -1,0 +1,63 @@
+// Internal declarations shared by the gridding library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "gridder.h"
+
+namespace gr {
+
+// Thread-local error message for gr_last_error().
+void set_error(const std::string& msg);
+gr_status fail(gr_status st, const std::string& msg);
+gr_status check_launch(const char* what);
+
+// Packed per-visibility record written by the preprocess kernel.
+//   x = x0 | y0 << 16            (footprint origin, cells)
+//   y = sx | sy << 8 | plane << 16 | valid << 31
+struct Record {
+  uint32_t x, y;
+};
+static_assert(sizeof(Record) == 8, "record must be 8 bytes");
+
+constexpr uint32_t kValidBit = 0x80000000u;
+constexpr int kMaxGrid = 32768;   // x0, y0 fit in 16 bits
+constexpr int kMaxPlanes = 32767; // 15 bits
+constexpr int kMaxOversample = 128;
+
+__host__ __device__ inline int rec_x0(Record r) { return (int)(r.x & 0xffffu); }
+__host__ __device__ inline int rec_y0(Record r) { return (int)(r.x >> 16); }
+__host__ __device__ inline int rec_sx(Record r) { return (int)(r.y & 0xffu); }
+__host__ __device__ inline int rec_sy(Record r) { return (int)((r.y >> 8) & 0xffu); }
+__host__ __device__ inline int rec_plane(Record r) { return (int)((r.y >> 16) & 0x7fffu); }
+__host__ __device__ inline bool rec_valid(Record r) { return (r.y & kValidBit) != 0; }
+
+// Host-side validation of a kernel descriptor (shared by preprocess and grid).
+gr_status validate_kernel(const gr_kernel* k, bool need_taps);
+
+// Preprocess launcher (preprocess.hip).
+gr_status launch_preprocess(const double* uvw, const void* vis, int vis_dtype, const float* vis_scale,
+                            const float* weights, int64_t n_vis, int n_pol, const gr_kernel& k,
+                            double inv_cell_u, double inv_cell_v, int height, int width,
+                            Record* records, float2* wvis, int64_t* dev_stats, hipStream_t stream);
+
+// Romein / thread-coarsening VALU gridder (grid_romein.hip).
+struct RomeinPlan {
+  int cu, cv;          // coarsening (cells per block, per axis)
+  int nu, nv;          // blocks per bin, per axis (bin = c * n >= S + c - 1)
+  int wgu, wgv;        // blocks per tile (one tile per wave)
+  int tiles_u, tiles_v;
+  int waves_per_block;
+  int vis_per_wg;
+  int lpad, pad_off;   // padded tap row length and offset in LDS
+  size_t lds_bytes;
+};
+gr_status plan_romein(const gr_kernel& k, int n_pol, const gr_tuning* t, RomeinPlan* plan);
+gr_status launch_romein(const Record* rec, const float2* wvis, int64_t n_vis, int n_pol,
+                        const gr_kernel& k, float2* grid, int height, int width,
+                        const RomeinPlan& plan, hipStream_t stream);
+
+}  // namespace gr

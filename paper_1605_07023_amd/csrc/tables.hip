@@ -1,0 +1,166 @@
+// GCF table generation on the device, in FP64 (Section 2.2: the GCF is
+// precomputed numerically and sampled at `oversample` times the grid
+// resolution; Section 4: separable, polarisation-independent).
+//
+// Tap k of oversampled phase s samples the kernel at d = k - S/2 + 1 - s/O;
+// every table is zero where |d| >= S/2.
+#include <cmath>
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include "internal.h"
+
+namespace gr {
+
+namespace {
+
+// Modified Bessel function I0 from its power series sum_m ((x/2)^m / m!)^2,
+// summed until the terms no longer change the FP64 result.
+__device__ double bessel_i0(double x) {
+  const double q = 0.25 * x * x;
+  double term = 1.0, sum = 1.0;
+  for (int m = 1; m < 500; ++m) {
+    term *= q / ((double)m * (double)m);
+    sum += term;
+    if (term < 1e-17 * sum) break;
+  }
+  return sum;
+}
+
+__device__ inline void store_elem(void* out, int64_t idx, int dtype, double v) {
+  switch (dtype) {
+    case GR_F64: reinterpret_cast<double*>(out)[idx] = v; break;
+    case GR_F32: reinterpret_cast<float*>(out)[idx] = (float)v; break;
+    case GR_F16: reinterpret_cast<__half*>(out)[idx] = __float2half((float)v); break;
+    default: reinterpret_cast<__hip_bfloat16*>(out)[idx] = __float2bfloat16((float)v); break;
+  }
+}
+
+__global__ void kb_table_kernel(double beta, int S, int O, int dtype, void* out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= S * O) return;
+  const int s = t / S, k = t % S;
+  const double d = (double)(k - S / 2 + 1) - (double)s / (double)O;
+  double v = 0.0;
+  if (fabs(d) < 0.5 * S) {
+    const double x = 2.0 * d / (double)S;
+    v = bessel_i0(beta * sqrt(1.0 - x * x)) / bessel_i0(beta);
+  }
+  store_elem(out, t, dtype, v);
+}
+
+// Image response of a Kaiser-Bessel window of width `aa` at image coordinate nu.
+__device__ double kb_taper(double nu, int aa, double beta) {
+  const double a = M_PI * (double)aa * nu;
+  const double r = beta * beta - a * a;
+  if (r > 0.0) {
+    const double s = sqrt(r);
+    return sinh(s) / s;
+  }
+  if (r < 0.0) {
+    const double s = sqrt(-r);
+    return sin(s) / s;
+  }
+  return 1.0;
+}
+
+// One block per (plane, s) row; blockDim 256; dynamic LDS: M doubles of taper.
+__global__ void __launch_bounds__(256)
+wkernel_table_kernel(int S, int O, int n_planes, double wh0, double whs, int aa, double beta, int M,
+                     int dtype, void* out) {
+  extern __shared__ double sh[];      // [M] taper, then [256] reduction scratch
+  double* taper = sh;
+  double* red = sh + M;
+  const int row = blockIdx.x;         // plane * O + s
+  const int plane = row / O, s = row % O;
+  for (int j = threadIdx.x; j < M; j += blockDim.x) {
+    const double nu = ((double)j + 0.5) / (double)M - 0.5;
+    taper[j] = kb_taper(nu, aa, beta);
+  }
+  __syncthreads();
+  // normalisation: real part of the w = 0, s = 0 taps, summed over the support
+  double part = 0.0;
+  for (int q = threadIdx.x; q < S * M; q += blockDim.x) {
+    const int k = q / M, j = q % M;
+    const double d = (double)(k - S / 2 + 1);
+    if (fabs(d) < 0.5 * S) {
+      const double nu = ((double)j + 0.5) / (double)M - 0.5;
+      part += taper[j] * cospi(2.0 * d * nu);
+    }
+  }
+  red[threadIdx.x] = part;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double c = 1.0 / red[0];
+  const double wh = wh0 + (double)plane * whs;
+  for (int k = threadIdx.x; k < S; k += blockDim.x) {
+    const double d = (double)(k - S / 2 + 1) - (double)s / (double)O;
+    double re = 0.0, im = 0.0;
+    if (fabs(d) < 0.5 * S) {
+      for (int j = 0; j < M; ++j) {
+        const double nu = ((double)j + 0.5) / (double)M - 0.5;
+        double sn, cs;
+        sincospi(wh * nu * nu + 2.0 * d * nu, &sn, &cs);   // exp(-i pi a) = cos - i sin
+        re += taper[j] * cs;
+        im -= taper[j] * sn;
+      }
+      re *= c;
+      im *= c;
+    }
+    const int64_t idx = ((int64_t)row * S + k) * 2;
+    store_elem(out, idx, dtype, re);
+    store_elem(out, idx + 1, dtype, im);
+  }
+}
+
+bool dtype_ok(int d) { return d == GR_F64 || d == GR_F32 || d == GR_F16 || d == GR_BF16; }
+bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+}  // namespace
+
+}  // namespace gr
+
+using namespace gr;
+
+extern "C" gr_status gr_make_kb_table(double beta, int32_t support, int32_t oversample,
+                                      int32_t out_dtype, void* out, void* stream) {
+  if (out == nullptr) return fail(GR_EINVAL, "gr_make_kb_table: out is NULL");
+  if (support < 2 || support > 64 || (support & 1))
+    return fail(GR_EINVAL, "gr_make_kb_table: support must be even, 2..64");
+  if (!pow2(oversample) || oversample > kMaxOversample)
+    return fail(GR_EINVAL, "gr_make_kb_table: oversample must be a power of two <= 128");
+  if (!dtype_ok(out_dtype)) return fail(GR_EINVAL, "gr_make_kb_table: bad out_dtype");
+  if (!(beta >= 0.0) || !std::isfinite(beta)) return fail(GR_EINVAL, "gr_make_kb_table: bad beta");
+  const int n = support * oversample;
+  kb_table_kernel<<<(n + 255) / 256, 256, 0, (hipStream_t)stream>>>(beta, support, oversample,
+                                                                     out_dtype, out);
+  return check_launch("gr_make_kb_table");
+}
+
+extern "C" gr_status gr_make_wkernel_table(int32_t support, int32_t oversample, int32_t n_planes,
+                                           double w_hat_first, double w_hat_step,
+                                           int32_t support_aa, double beta, int32_t n_samples,
+                                           int32_t out_dtype, void* out, void* stream) {
+  if (out == nullptr) return fail(GR_EINVAL, "gr_make_wkernel_table: out is NULL");
+  if (support < 2 || support > 64 || (support & 1))
+    return fail(GR_EINVAL, "gr_make_wkernel_table: support must be even, 2..64");
+  if (!pow2(oversample) || oversample > kMaxOversample)
+    return fail(GR_EINVAL, "gr_make_wkernel_table: oversample must be a power of two <= 128");
+  if (n_planes < 1 || n_planes > kMaxPlanes)
+    return fail(GR_EINVAL, "gr_make_wkernel_table: n_planes out of range");
+  if (support_aa < 1 || support_aa > support)
+    return fail(GR_EINVAL, "gr_make_wkernel_table: support_aa must be in 1..support");
+  if (!std::isfinite(w_hat_first) || !std::isfinite(w_hat_step) || !std::isfinite(beta) || beta < 0.0)
+    return fail(GR_EINVAL, "gr_make_wkernel_table: non-finite parameter");
+  if (!dtype_ok(out_dtype)) return fail(GR_EINVAL, "gr_make_wkernel_table: bad out_dtype");
+  const int M = n_samples > 0 ? n_samples : 4 * support;
+  if (M > 8192) return fail(GR_EINVAL, "gr_make_wkernel_table: n_samples must be <= 8192");
+  const size_t lds = sizeof(double) * (size_t)(M + 256);
+  wkernel_table_kernel<<<n_planes * oversample, 256, lds, (hipStream_t)stream>>>(
+      support, oversample, n_planes, w_hat_first, w_hat_step, support_aa, beta, M, out_dtype, out);
+  return check_launch("gr_make_wkernel_table");
+}

@@ -1,0 +1,108 @@
+"""Device-side driver for a synthetic workload: upload inputs, build the kernel
+table on the GPU (FP64 generation, cast to the tap dtype), and call the C ABI.
+
+Used by the tests, the smoke check and the benchmark.  All arithmetic happens
+in libgridder.so; this module only allocates torch tensors and passes pointers.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+_TAP_TORCH = {B.GR_F32: torch.float32, B.GR_F16: torch.float16, B.GR_BF16: torch.bfloat16,
+              B.GR_F64: torch.float64}
+
+
+def make_taps(wl, device, tap_dtype: int = B.GR_F32, stream=None) -> torch.Tensor:
+    """Kernel table for a workload, generated on the device (gr_make_*_table)."""
+    S, O = wl.support, wl.oversample
+    dt = _TAP_TORCH[tap_dtype]
+    if wl.kernel == "kb":
+        out = torch.empty((1, O, S), dtype=dt, device=device)
+        B.gr_make_kb_table(wl.beta, S, O, tap_dtype, out, stream)
+    elif wl.kernel == "wsep":
+        out = torch.empty((wl.n_planes, O, S, 2), dtype=dt, device=device)
+        whs = wl.plane_w_hat()
+        step = (whs[1] - whs[0]) if wl.n_planes > 1 else 0.0
+        B.gr_make_wkernel_table(S, O, wl.n_planes, float(whs[0]), float(step), wl.support_aa,
+                                wl.beta, 0, tap_dtype, out, stream)
+    else:
+        raise ValueError(f"unknown kernel kind {wl.kernel}")
+    return out
+
+
+@dataclasses.dataclass
+class DeviceWorkload:
+    wl: object
+    uvw: torch.Tensor
+    vis: torch.Tensor
+    weights: Optional[torch.Tensor]
+    taps: torch.Tensor
+    kernel: B.GrKernel
+    tap_dtype: int
+
+    @property
+    def n_vis(self):
+        return self.wl.n_vis
+
+    @property
+    def n_pol(self):
+        return self.wl.n_pol
+
+
+def upload(wl, device="cuda:0", tap_dtype: int = B.GR_F32, taps: Optional[torch.Tensor] = None,
+           stream=None) -> DeviceWorkload:
+    uvw = torch.from_numpy(np.ascontiguousarray(wl.uvw)).to(device)
+    vis = torch.from_numpy(np.ascontiguousarray(wl.vis)).to(device)
+    w = None if wl.weights is None else torch.from_numpy(np.ascontiguousarray(wl.weights)).to(device)
+    if taps is None:
+        taps = make_taps(wl, device, tap_dtype, stream)
+    k = B.make_kernel(taps, wl.support, wl.oversample, wl.n_planes,
+                      taps_complex=(wl.kernel != "kb"), tap_dtype=tap_dtype,
+                      w_min=wl.w_min, inv_dw=wl.inv_dw)
+    return DeviceWorkload(wl, uvw, vis, w, taps, k, tap_dtype)
+
+
+def tuning(cu=0, cv=0, wg_u=0, wg_v=0, vis_per_wg=0, variant=0) -> B.GrTuning:
+    return B.GrTuning(cu, cv, wg_u, wg_v, vis_per_wg, variant)
+
+
+def grid(dw: DeviceWorkload, grid_out: Optional[torch.Tensor] = None,
+         tune: Optional[B.GrTuning] = None, workspace: Optional[torch.Tensor] = None,
+         stats: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Run the whole path (preprocess + grid) into grid_out (zeros if None)."""
+    wl = dw.wl
+    dev = dw.uvw.device
+    if grid_out is None:
+        grid_out = torch.zeros((wl.n_pol, wl.height, wl.width), dtype=torch.complex64, device=dev)
+    need = B.gr_grid_workspace_bytes(wl.n_vis, wl.n_pol)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    B.gr_grid(dw.uvw, dw.vis, B.GR_F32, None, dw.weights, wl.n_vis, wl.n_pol, dw.kernel,
+              wl.inv_cell_u, wl.inv_cell_v, grid_out, wl.height, wl.width, tune, workspace,
+              workspace.numel(), stats, stream)
+    return grid_out
+
+
+def preprocess(dw: DeviceWorkload, stats: Optional[torch.Tensor] = None, stream=None):
+    """gr_preprocess into fresh buffers: returns (records uint32 [N, 2], wvis complex64 [N, P])."""
+    wl = dw.wl
+    dev = dw.uvw.device
+    rec = torch.empty((max(wl.n_vis, 1), 2), dtype=torch.int32, device=dev)
+    wv = torch.empty((max(wl.n_vis, 1), wl.n_pol), dtype=torch.complex64, device=dev)
+    B.gr_preprocess(dw.uvw, dw.vis, B.GR_F32, None, dw.weights, wl.n_vis, wl.n_pol, dw.kernel,
+                    wl.inv_cell_u, wl.inv_cell_v, wl.height, wl.width, rec, wv, stats, stream)
+    return rec, wv
+
+
+def decode_records(rec: np.ndarray) -> dict:
+    """Unpack records (layout documented in include/gridder.h) for tests."""
+    a = rec.view(np.uint32).reshape(-1, 2)
+    x, y = a[:, 0].astype(np.int64), a[:, 1].astype(np.int64)
+    return dict(x0=x & 0xFFFF, y0=x >> 16, sx=y & 0xFF, sy=(y >> 8) & 0xFF,
+                plane=(y >> 16) & 0x7FFF, valid=(y >> 31) & 1)

@@ -1,0 +1,122 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared
+entry point, and rejects bad arguments on the host before anything is
+enqueued (no device work happens in this file)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for f in os.listdir(os.path.join(ROOT, "include")):
+        if f.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", f)).read()
+            names |= set(re.findall(r"^\s*(?:gr_status|size_t|int32_t|const char\*)\s+(gr_\w+)\(", txt, re.M))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1605_07023_amd import binding
+    path = binding.library_path()
+    if not os.path.exists(path):
+        import __graft_entry__
+        __graft_entry__.build()
+    return binding.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 8
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_version_and_workspace(lib):
+    from paper_1605_07023_amd import binding as B
+    assert B.gr_version() >= 1
+    n = B.gr_grid_workspace_bytes(1000, 4)
+    assert n >= 1000 * 8 + 1000 * 4 * 8
+    assert B.gr_grid_workspace_bytes(-1, 4) == 0
+
+
+def _kernel(**kw):
+    from paper_1605_07023_amd import binding as B
+    base = dict(kind=B.GR_SEPARABLE, tap_dtype=B.GR_F32, taps_complex=1, support=16, oversample=8,
+                n_planes=4, w_min=-1.0, inv_dw=1.5, taps=1 << 20)
+    base.update(kw)
+    return B.GrKernel(**base)
+
+
+@pytest.mark.parametrize("bad,msg", [
+    (dict(support=7), "support"), (dict(support=0), "support"), (dict(support=66), "support"),
+    (dict(oversample=6), "oversample"), (dict(oversample=256), "oversample"),
+    (dict(n_planes=0), "n_planes"), (dict(tap_dtype=9), "tap_dtype"),
+    (dict(taps=None), "taps"), (dict(kind=1), "SEPARABLE"),
+    (dict(w_min=float("nan")), "w_min"),
+])
+def test_grid_records_rejects_bad_kernel(lib, bad, msg):
+    from paper_1605_07023_amd import binding as B
+    k = _kernel(**bad)
+    st = lib.gr_grid_records(1 << 20, 1 << 20, 10, 4, ctypes.byref(k), 1 << 20, 64, 64, None, None)
+    assert st in (B.GR_EINVAL, B.GR_EUNSUPPORTED)
+    assert msg in lib.gr_last_error().decode()
+
+
+@pytest.mark.parametrize("args,msg", [
+    (dict(n_pol=3), "n_pol"), (dict(height=8), "height"), (dict(width=40000), "height"),
+    (dict(n_vis=-1), "n_vis"), (dict(grid=None), "grid"), (dict(records=None), "records"),
+])
+def test_grid_records_rejects_bad_shapes(lib, args, msg):
+    from paper_1605_07023_amd import binding as B
+    a = dict(records=1 << 20, wvis=1 << 20, n_vis=10, n_pol=4, grid=1 << 20, height=64, width=64)
+    a.update(args)
+    k = _kernel()
+    st = lib.gr_grid_records(a["records"], a["wvis"], a["n_vis"], a["n_pol"], ctypes.byref(k),
+                             a["grid"], a["height"], a["width"], None, None)
+    assert st == B.GR_EINVAL
+    assert msg in lib.gr_last_error().decode()
+
+
+def test_tuning_validation(lib):
+    from paper_1605_07023_amd import binding as B
+    k = _kernel()
+    for t, code in [(B.GrTuning(3, 2, 0, 0, 0, 0), B.GR_EINVAL),
+                    (B.GrTuning(8, 8, 0, 0, 0, 0), B.GR_EUNSUPPORTED),
+                    (B.GrTuning(2, 2, 16, 16, 0, 0), B.GR_EINVAL),
+                    (B.GrTuning(0, 0, 0, 0, 0, 7), B.GR_EUNSUPPORTED)]:
+        st = lib.gr_grid_records(1 << 20, 1 << 20, 10, 4, ctypes.byref(k), 1 << 20, 64, 64,
+                                 ctypes.byref(t), None)
+        assert st == code, (t.cu, t.cv, t.wg_u, t.wg_v, t.variant, lib.gr_last_error())
+
+
+def test_grid_rejects_small_workspace(lib):
+    from paper_1605_07023_amd import binding as B
+    k = _kernel()
+    st = lib.gr_grid(1 << 20, 1 << 20, B.GR_F32, None, None, 100, 4, ctypes.byref(k), 1.0, 1.0,
+                     1 << 20, 64, 64, None, 1 << 20, 10, None, None)
+    assert st == B.GR_ENOMEM
+
+
+def test_preprocess_rejects(lib):
+    from paper_1605_07023_amd import binding as B
+    k = _kernel()
+    st = lib.gr_preprocess(1 << 20, 1 << 20, B.GR_F16, None, None, 10, 4, ctypes.byref(k), 1.0, 1.0,
+                           64, 64, 1 << 20, 1 << 20, None, None)
+    assert st == B.GR_EINVAL and "vis_scale" in lib.gr_last_error().decode()
+    st = lib.gr_preprocess(1 << 20, 1 << 20, B.GR_F32, None, None, 10, 4, ctypes.byref(k), 0.0, 1.0,
+                           64, 64, 1 << 20, 1 << 20, None, None)
+    assert st == B.GR_EINVAL and "inv_cell" in lib.gr_last_error().decode()
+
+
+def test_table_generators_reject(lib):
+    from paper_1605_07023_amd import binding as B
+    assert lib.gr_make_kb_table(8.6, 7, 8, B.GR_F32, 1 << 20, None) == B.GR_EINVAL
+    assert lib.gr_make_kb_table(8.6, 8, 8, 7, 1 << 20, None) == B.GR_EINVAL
+    assert lib.gr_make_wkernel_table(16, 8, 0, 0.0, 1.0, 8, 8.6, 0, B.GR_F32, 1 << 20, None) == B.GR_EINVAL
+    assert lib.gr_make_wkernel_table(16, 8, 4, 0.0, 1.0, 20, 8.6, 0, B.GR_F32, 1 << 20, None) == B.GR_EINVAL
+    assert lib.gr_make_wkernel_table(16, 8, 4, 0.0, 1.0, 8, 8.6, 0, B.GR_F32, None, None) == B.GR_EINVAL

@@ -1,0 +1,256 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars: index/record work bit-exact; FP64 table generation within 1e-12;
+FP32 gridding within 1e-5 relative L2 of the FP64 grid; integer-valued inputs
+(every partial sum exact in FP32) bit-exact regardless of atomic order.
+"""
+import copy
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import gridding as G  # noqa: E402
+from synth import full_shape_workload, random_point_workload, tiny_kb_workload  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1605_07023_amd import binding, runner
+    binding.load_library()
+    return runner
+
+
+def _rel_l2(got, ref):
+    return float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+def _oracle_grid(wl, taps):
+    return G.grid_separable(wl.vis, wl.uvw, wl.weights, taps, wl.inv_cell_u, wl.inv_cell_v,
+                            wl.oversample, wl.height, wl.width, wl.n_planes, wl.w_min, wl.inv_dw)
+
+
+def _oracle_taps(wl):
+    if wl.kernel == "kb":
+        return G.kb_table(wl.support, wl.oversample, wl.beta)
+    return G.wkernel_table(wl.support, wl.oversample, wl.plane_w_hat(), wl.support_aa, wl.beta)
+
+
+# ------------------------------------------------------------------ tables
+
+@pytest.mark.parametrize("S,O,beta", [(8, 8, 8.6), (16, 4, 10.0), (6, 16, 0.0)])
+def test_kb_table_fp64_matches_oracle(R, S, O, beta):
+    from paper_1605_07023_amd import binding as B
+    _say(f"kb table S={S} O={O} beta={beta}")
+    out = torch.empty((O, S), dtype=torch.float64, device=DEV)
+    B.gr_make_kb_table(beta, S, O, B.GR_F64, out)
+    ref = G.kb_table(S, O, beta)[0]
+    np.testing.assert_allclose(out.cpu().numpy(), ref, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("S,O,planes", [(16, 8, 5), (32, 8, 3), (8, 4, 2)])
+def test_wkernel_table_fp64_matches_oracle(R, S, O, planes):
+    from paper_1605_07023_amd import binding as B
+    _say(f"wkernel table S={S} O={O} planes={planes}")
+    w0, dw = -float(S - 8), 2.0 * (S - 8) / max(planes - 1, 1)
+    out = torch.empty((planes, O, S, 2), dtype=torch.float64, device=DEV)
+    B.gr_make_wkernel_table(S, O, planes, w0, dw, 8, 8.6, 0, B.GR_F64, out)
+    got = out.cpu().numpy()
+    got = got[..., 0] + 1j * got[..., 1]
+    ref = G.wkernel_table(S, O, w0 + dw * np.arange(planes), 8, 8.6)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+# ------------------------------------------------------------------ preprocess
+
+def test_preprocess_records_exact(R):
+    _say("preprocess records: random points with drops and non-finite values")
+    wl = random_point_workload(5000, 4, 96, 128, 16, 8, seed=3, n_planes=9, margin=12,
+                               weights=True, kernel="wsep")
+    wl.uvw[5, 0] = np.nan
+    wl.uvw[6, 2] = np.inf
+    wl.uvw[7, 2] = 1e6                  # plane out of range
+    wl.vis[8, 2] = np.complex64(complex(np.nan, 0))
+    wl.weights[9, 1] = np.inf
+    dw = R.upload(wl, DEV)
+    stats = torch.zeros(2, dtype=torch.int64, device=DEV)
+    rec, _ = R.preprocess(dw, stats)
+    got = R.decode_records(rec.cpu().numpy())
+    ref = G.pixel_coords(wl.uvw, 1.0, 1.0, 8, 16, 96, 128, 9, wl.w_min, wl.inv_dw)
+    valid = ref["valid"] & G.finite_values(wl.vis, wl.weights)
+    np.testing.assert_array_equal(got["valid"].astype(bool), valid)
+    for k in ("x0", "y0", "sx", "sy", "plane"):
+        np.testing.assert_array_equal(got[k][valid], ref[k][valid], err_msg=k)
+    assert stats.cpu().tolist() == [int(valid.sum()), int((~valid).sum())]
+    assert 0 < (~valid).sum() < wl.n_vis
+
+
+def test_preprocess_tiny_config_exact(R):
+    _say("preprocess records: tiny KB config")
+    wl = tiny_kb_workload()
+    dw = R.upload(wl, DEV)
+    rec, wv = R.preprocess(dw)
+    got = R.decode_records(rec.cpu().numpy())
+    ref = G.pixel_coords(wl.uvw, wl.inv_cell_u, wl.inv_cell_v, 8, 8, 512, 512)
+    assert ref["valid"].all() and got["valid"].all()
+    for k in ("x0", "y0", "sx", "sy"):
+        np.testing.assert_array_equal(got[k], ref[k], err_msg=k)
+    np.testing.assert_array_equal(wv.cpu().numpy(), wl.vis)
+
+
+# ------------------------------------------------------------------ gridding
+
+TUNINGS_P1 = [(1, 1), (2, 2), (4, 4), (8, 2), (2, 8), (8, 8), (4, 1)]
+TUNINGS_P4 = [(1, 1), (2, 2), (4, 2), (2, 4), (4, 4), (8, 2), (8, 1)]
+
+
+@pytest.mark.parametrize("cu,cv", TUNINGS_P1)
+def test_grid_tiny_config(R, cu, cv):
+    _say(f"grid tiny KB config cu={cu} cv={cv}")
+    wl = tiny_kb_workload()
+    dw = R.upload(wl, DEV)
+    g = R.grid(dw, tune=R.tuning(cu, cv)).cpu().numpy()
+    ref, _ = _oracle_grid(wl, _oracle_taps(wl))
+    assert _rel_l2(g, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("cu,cv", TUNINGS_P4)
+@pytest.mark.parametrize("S", [8, 16])
+def test_grid_points_wkernel_p4(R, cu, cv, S):
+    _say(f"grid random points W kernel S={S} P=4 cu={cu} cv={cv}")
+    wl = random_point_workload(3001, 4, 80, 112, S, 8, seed=S + cu, n_planes=7, margin=6,
+                               weights=True, kernel="wsep")
+    dw = R.upload(wl, DEV)
+    stats = torch.zeros(2, dtype=torch.int64, device=DEV)
+    g = R.grid(dw, tune=R.tuning(cu, cv, vis_per_wg=256), stats=stats).cpu().numpy()
+    ref, dropped = _oracle_grid(wl, _oracle_taps(wl))
+    assert _rel_l2(g, ref) <= 1e-5
+    assert stats.cpu().tolist() == [wl.n_vis - dropped, dropped] and dropped > 0
+
+
+@pytest.mark.parametrize("wg_u,wg_v,vpw", [(3, 5, 7), (16, 4, 1), (1, 1, 100000), (5, 1, 33)])
+def test_grid_tile_shapes_and_ragged_chunks(R, wg_u, wg_v, vpw):
+    _say(f"grid tile shape {wg_u}x{wg_v} vis_per_wg={vpw}")
+    wl = random_point_workload(777, 1, 64, 48, 16, 8, seed=5, n_planes=3, margin=2,
+                               weights=False, kernel="wsep")
+    dw = R.upload(wl, DEV)
+    g = R.grid(dw, tune=R.tuning(2, 4, wg_u, wg_v, vpw)).cpu().numpy()
+    ref, _ = _oracle_grid(wl, _oracle_taps(wl))
+    assert _rel_l2(g, ref) <= 1e-5
+
+
+def _custom_taps_run(R, wl, taps_np, tune):
+    from paper_1605_07023_amd import binding as B
+    t = torch.from_numpy(np.ascontiguousarray(taps_np.astype(np.float32))).to(DEV)
+    dw = R.upload(wl, DEV, taps=t)
+    dw.kernel = B.make_kernel(t, wl.support, wl.oversample, wl.n_planes,
+                              taps_complex=(taps_np.ndim == 4), w_min=wl.w_min, inv_dw=wl.inv_dw)
+    return R.grid(dw, tune=tune).cpu().numpy()
+
+
+@pytest.mark.parametrize("cu,cv", [(1, 1), (4, 2), (8, 8)])
+def test_delta_table_and_integer_inputs_bit_exact(R, cu, cv):
+    """Integer visibilities with integer taps: every partial sum is an exact
+    FP32 integer, so the grid must equal the FP64 oracle bit for bit whatever
+    order the atomics land in (a lost or duplicated flush would show)."""
+    _say(f"integer-valued inputs bit-exact cu={cu} cv={cv}")
+    rng = np.random.default_rng(cu * 10 + cv)
+    wl = random_point_workload(4000, 1, 64, 64, 8, 8, seed=11, weights=False)
+    wl.vis = (rng.integers(-3, 4, (wl.n_vis, 1)) + 1j * rng.integers(-3, 4, (wl.n_vis, 1))).astype(np.complex64)
+    # delta table: every visibility lands on its own cell
+    delta = np.zeros((1, 8, 8))
+    delta[:, :, 3] = 1.0
+    g = _custom_taps_run(R, wl, delta, R.tuning(cu, cv, vis_per_wg=64))
+    ref, _ = _oracle_grid(wl, delta)
+    np.testing.assert_array_equal(g.astype(np.complex128), ref)
+    # small-integer taps in {0, 1, 2}
+    ints = rng.integers(0, 3, (1, 8, 8)).astype(np.float64)
+    g = _custom_taps_run(R, wl, ints, R.tuning(cu, cv, vis_per_wg=64))
+    ref, _ = _oracle_grid(wl, ints)
+    assert np.abs(ref).max() < 2 ** 20
+    np.testing.assert_array_equal(g.astype(np.complex128), ref)
+
+
+def test_integer_complex_taps_quad_pol_bit_exact(R):
+    _say("integer complex taps, quad pol, bit-exact")
+    rng = np.random.default_rng(7)
+    wl = random_point_workload(2000, 4, 48, 56, 16, 4, seed=12, n_planes=3, weights=False,
+                               kernel="wsep")
+    wl.vis = (rng.integers(-2, 3, (wl.n_vis, 4)) + 1j * rng.integers(-2, 3, (wl.n_vis, 4))).astype(np.complex64)
+    taps = (rng.integers(-1, 2, (3, 4, 16)) + 1j * rng.integers(-1, 2, (3, 4, 16)))
+    taps_np = np.stack([taps.real, taps.imag], axis=-1)
+    g = _custom_taps_run(R, wl, taps_np, R.tuning(4, 2, vis_per_wg=128))
+    ref, _ = _oracle_grid(wl, taps)
+    np.testing.assert_array_equal(g.astype(np.complex128), ref)
+
+
+def test_accumulates_and_edge_cases(R):
+    _say("accumulate into existing grid; empty input; all dropped")
+    wl = random_point_workload(500, 4, 40, 40, 8, 8, seed=2, n_planes=1, kernel="kb")
+    dw = R.upload(wl, DEV)
+    base = (torch.randn(4, 40, 40, dtype=torch.complex64, device=DEV))
+    g0 = base.clone()
+    R.grid(dw, grid_out=g0)
+    ref, _ = _oracle_grid(wl, _oracle_taps(wl))
+    got = g0.cpu().numpy().astype(np.complex128) - base.cpu().numpy()
+    assert _rel_l2(got, ref) <= 1e-5
+    # empty input leaves the grid untouched
+    e = copy.copy(wl)
+    e.uvw, e.vis = wl.uvw[:0], wl.vis[:0]
+    de = R.upload(e, DEV)
+    g1 = base.clone()
+    R.grid(de, grid_out=g1)
+    assert torch.equal(g1, base)
+    # every visibility off the grid: dropped and counted, grid untouched
+    off = copy.copy(wl)
+    off.uvw = wl.uvw.copy()
+    off.uvw[:, 0] += 1000.0
+    do = R.upload(off, DEV)
+    stats = torch.zeros(2, dtype=torch.int64, device=DEV)
+    g2 = base.clone()
+    R.grid(do, grid_out=g2, stats=stats)
+    assert torch.equal(g2, base)
+    assert stats.cpu().tolist() == [0, wl.n_vis]
+
+
+# ------------------------------------------------------------------ full shape
+
+@pytest.fixture(scope="module")
+def full_S16():
+    return full_shape_workload(16)
+
+
+@pytest.mark.parametrize("S", [16, 32])
+def test_full_shape_sampled_rows(R, c_oracle, S, full_S16):
+    """The 64-antenna, 16-channel, 1024-dump, quad-pol 4096^2 workload at full
+    size, in the default launch configuration, checked on sampled grid rows
+    against the FP64 C oracle (which computes those rows from every visibility)."""
+    wl = full_S16 if S == 16 else full_shape_workload(32)
+    _say(f"full shape S={S}: N={wl.n_vis}")
+    dw = R.upload(wl, DEV)
+    stats = torch.zeros(2, dtype=torch.int64, device=DEV)
+    g = R.grid(dw, stats=stats)
+    torch.cuda.synchronize()
+    assert stats.cpu().tolist() == [wl.n_vis, 0]
+    rows = [64, 1100, 2047, 2048, 2049, 2900, 3990]
+    got = g[:, rows].cpu().numpy()
+    del g, dw
+    torch.cuda.empty_cache()
+    ref, dropped = c_oracle.grid_separable(wl.vis, wl.uvw, None, _oracle_taps(wl), wl.inv_cell_u,
+                                           wl.inv_cell_v, 8, wl.height, wl.width, wl.n_planes,
+                                           wl.w_min, wl.inv_dw, rows=rows)
+    assert dropped == 0
+    err = _rel_l2(got, ref)
+    _say(f"full shape S={S}: sampled-row rel L2 = {err:.3e}")
+    assert err <= 1e-5
