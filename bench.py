@@ -1,0 +1,225 @@
+#!/usr/bin/env python3
+"""Benchmark: convolutional gridding throughput on one MI355X.
+
+Workload: 64 antennas (2016 baselines) x 1024 dumps over 8 h x 16 channels
+(33,030,144 visibilities, ordered baseline / time / channel), four
+polarisations, 4096^2 complex64 grid per polarisation, separable complex W
+kernels with 32 planes and oversampling 8, supports 16 and 32.
+
+One step = the whole hot path over that batch for both supports: preprocess
+(FP64 index conversion, weighting) and gridding, S = 16 then S = 32, each into
+its own grid.  Inputs and kernel tables are resident in HBM before timing.
+
+value = useful vis-tap updates per second over the step (a vis-tap update is
+one polarisation of one visibility times one in-footprint tap: 8 flops with
+complex taps; padding taps are not counted).
+
+Prints one JSON line.  Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP32_VALU_PEAK = 157.3e12   # MI355X FP32 vector peak (packed), flop/s
+FP32_MFMA_PEAK = 157.3e12   # MI355X dense FP32 matrix peak, flop/s
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = {1: [os.path.join(ROOT, "paper_1605_07023_amd", "csrc", "grid_romein.hip")],
+                  2: [os.path.join(ROOT, "paper_1605_07023_amd", "csrc", "grid_mfma.hip")]}
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_hash(variant: int) -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[variant]:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(wl_fn, support: int, budget_s: float, threads: int) -> dict:
+    """The FP64 C oracle, as it stands, on a bounded sample of the workload:
+    the first k baselines (all dumps and channels), k sized for ~budget_s."""
+    import numpy as np
+    from oracle import cgrid
+    from oracle import gridding as G
+    cgrid.build()
+    cgrid.set_threads(threads)
+    per_bl = 1024 * 16
+
+    def run(k):
+        wl = wl_fn(support, n_baselines=k)
+        taps = G.wkernel_table(support, 8, wl.plane_w_hat(), wl.support_aa, wl.beta)
+        t0 = time.perf_counter()
+        _, dropped = cgrid.grid_separable(wl.vis, wl.uvw, None, taps, wl.inv_cell_u, wl.inv_cell_v,
+                                          8, wl.height, wl.width, wl.n_planes, wl.w_min, wl.inv_dw)
+        dt = time.perf_counter() - t0
+        return (wl.n_vis - dropped) * wl.n_pol * support * support, dt
+
+    upd, dt = run(32)
+    k = int(max(32, min(2016, 32 * budget_s / max(dt, 1e-3))))
+    log(f"cpu baseline: calibration 32 baselines {dt:.2f}s -> sample {k} baselines")
+    upd, dt = run(k)
+    return {"value": upd / dt, "unit": "updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {k} of 2016 baselines x 1024 dumps x 16 channels "
+                      f"({k * per_bl} vis, S={support}, quad pol, 4096^2), C FP64 oracle, {dt:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--supports", default="16,32")
+    ap.add_argument("--cu", type=int, default=0)
+    ap.add_argument("--cv", type=int, default=0)
+    ap.add_argument("--variant", type=int, default=2, help="1: VALU work-item kernel, 2: MFMA")
+    ap.add_argument("--seg-len", type=int, default=0)
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not "
+                                   "part of this build (see DESIGN.md for how gridding would shard)",
+                          "n_gpus": args.gpus}), flush=True)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1605_07023_amd import binding as B
+    from paper_1605_07023_amd import runner
+    from synth import full_shape_workload
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    supports = [int(s) for s in args.supports.split(",")]
+    log("generating inputs")
+    wls = {S: full_shape_workload(S) for S in supports}
+    wl0 = wls[supports[0]]
+    N, P = wl0.n_vis, wl0.n_pol
+    log(f"uploading N={N} P={P}")
+    uvw = torch.from_numpy(np.ascontiguousarray(wl0.uvw)).to(dev)
+    vis = torch.from_numpy(np.ascontiguousarray(wl0.vis)).to(dev)
+    taps, kern, grids = {}, {}, {}
+    for S, wl in wls.items():
+        taps[S] = runner.make_taps(wl, dev, B.GR_F32)
+        kern[S] = B.make_kernel(taps[S], S, wl.oversample, wl.n_planes, taps_complex=True,
+                                tap_dtype=B.GR_F32, w_min=wl.w_min, inv_dw=wl.inv_dw)
+        grids[S] = torch.zeros((P, wl.height, wl.width), dtype=torch.complex64, device=dev)
+    rec = torch.empty((N, 2), dtype=torch.int32, device=dev)
+    wvis = torch.empty((N, P), dtype=torch.complex64, device=dev)
+    stats = torch.zeros(2, dtype=torch.int64, device=dev)
+    variant = args.variant if args.variant in (1, 2) else 2
+    tune = runner.tuning(args.cu, args.cv, vis_per_wg=args.seg_len, variant=variant)
+    seg_len = args.seg_len
+    bins_bytes = max(B.gr_bin_bytes(N, P, S, wls[S].height, wls[S].width, seg_len) for S in supports)
+    bins = torch.empty(bins_bytes, dtype=torch.uint8, device=dev) if variant == 2 else None
+    stream = torch.cuda.current_stream(dev)
+    ev = {S: [] for S in supports}
+
+    def step(record: bool):
+        for S in supports:
+            wl = wls[S]
+            B.gr_preprocess(uvw, vis, B.GR_F32, None, None, N, P, kern[S], wl.inv_cell_u,
+                            wl.inv_cell_v, wl.height, wl.width, rec, wvis, stats, stream)
+            if variant == 2:
+                B.gr_bin(rec, wvis, N, P, S, wl.height, wl.width, seg_len, bins, bins_bytes, stream)
+            if record:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+            if variant == 2:
+                B.gr_grid_binned(bins, N, P, kern[S], seg_len, grids[S], wl.height, wl.width, stream)
+            else:
+                B.gr_grid_records(rec, wvis, N, P, kern[S], grids[S], wl.height, wl.width, tune, stream)
+            if record:
+                e1.record(stream)
+                ev[S].append((e0, e1))
+
+    log(f"warmup {args.warmup} steps")
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    stats.zero_()
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps")
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gridded, dropped = [int(x) for x in stats.cpu().tolist()]
+    n_valid = gridded // (args.steps * len(supports))
+    log(f"timed region {t1 - t0:.3f}s, gridded per pass {n_valid}, dropped {dropped}")
+
+    per_support = {}
+    total_updates = 0
+    for S in supports:
+        upd = n_valid * P * S * S
+        total_updates += upd
+        kms = [a.elapsed_time(b) for a, b in ev[S]]
+        avg = sum(kms) / len(kms) * 1e-3
+        per_support[str(S)] = {"updates_per_step": upd, "grid_kernel_ms": avg * 1e3,
+                               "grid_kernel_updates_per_s": upd / avg,
+                               "grid_kernel_pct_fp32_valu_peak": 100.0 * 8 * upd / avg / FP32_VALU_PEAK}
+    ms_per_step = (t1 - t0) / args.steps * 1e3
+    value = total_updates * args.steps / (t1 - t0)
+
+    dom = str(max(supports))
+    d = per_support[dom]
+    achieved = 8.0 * d["updates_per_step"] / (d["grid_kernel_ms"] * 1e-3)
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        try:
+            tr = json.load(open(TRAFFIC_FILE))
+            if tr.get("source_hash") == source_hash(variant) and tr.get("support") == int(dom):
+                traffic = tr.get("bytes_per_launch")
+        except (ValueError, OSError):
+            traffic = None
+    if variant == 2:
+        roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": FP32_MFMA_PEAK / 1e12,
+                    "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK, "traffic": traffic,
+                    "kernel": f"grid_mfma_kernel<4, complex> (S={dom}), FP32 MFMA 16x16x4"}
+    else:
+        roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": FP32_VALU_PEAK / 1e12,
+                    "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK, "traffic": traffic,
+                    "kernel": f"romein_valu_kernel (S={dom})"}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = min(16, os.cpu_count() or 1)
+        log(f"cpu baseline on {threads} threads")
+        cpu = cpu_baseline(full_shape_workload, int(dom), args.cpu_budget, threads)
+
+    out = {
+        "metric": "vis-tap updates/s", "value": value, "unit": "updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "earth-rotation uv tracks, 64 antennas (2016 baselines) x 1024 dumps "
+                               "over 8 h x 16 channels, quad pol, 4096^2 grid, separable W kernels "
+                               "S=16 and S=32, 32 planes, oversampling 8",
+                   "n_vis": N, "n_pol": P, "grid": [wl0.height, wl0.width], "supports": supports,
+                   "order": "baseline, time, channel"},
+        "pct_fp32_valu_peak": 100.0 * 8 * value / FP32_VALU_PEAK,
+        "per_support": per_support,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

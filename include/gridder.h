@@ -70,8 +70,10 @@ typedef struct {
  *   cu, cv      thread-coarsening factors: each work-item owns a cu x cv block
  *               of cells (Section 3); 1, 2, 4 or 8
  *   wg_u, wg_v  tile shape in blocks handled by one wave (Section 2.2 tiles)
- *   vis_per_wg  visibilities per work-group (Section 4 uses 1024)
- *   variant     0 = library choice, 1 = VALU work-item kernel, 2 = MFMA kernel */
+ *   vis_per_wg  visibilities per work-group (Section 4 uses 1024) for the VALU
+ *               kernel; maximum segment length for the binned MFMA kernel
+ *   variant     0 = library choice, 1 = VALU work-item kernel on the input
+ *               order (gr_grid_records), 2 = MFMA kernel on the binned stream */
 typedef struct {
   int32_t cu, cv, wg_u, wg_v, vis_per_wg, variant;
 } gr_tuning;
@@ -113,11 +115,41 @@ gr_status gr_grid_records(const void* records, const void* wvis, int64_t n_vis, 
                           const gr_kernel* kernel, void* grid, int32_t height, int32_t width,
                           const gr_tuning* tuning, void* stream);
 
-/* Bytes of workspace gr_grid needs for n_vis visibilities of n_pol polarisations. */
-size_t gr_grid_workspace_bytes(int64_t n_vis, int32_t n_pol);
+/* Size in bytes of the `bins` buffer of gr_bin / gr_grid_binned (0 if the
+ * arguments are invalid).  seg_len <= 0 selects the default (4096). */
+size_t gr_bin_bytes(int64_t n_vis, int32_t n_pol, int32_t support, int32_t height, int32_t width,
+                    int32_t seg_len);
 
-/* The whole hot path: gr_preprocess into `workspace`, then gr_grid_records.
- * Same arguments and semantics as those two calls. */
+/* Bin preprocessed visibilities by footprint position.  The grid is cut into
+ * square tiles of T = 64 - S cells; each valid visibility goes to the tile that
+ * holds its footprint origin (x0, y0), so every footprint of a tile lies in a
+ * 64 x 64-cell window.  The input order (the baseline-ordered stream of
+ * Section 4) is kept within each run of 64 consecutive visibilities of a
+ * tile; each tile's list is cut into segments of at most seg_len entries.
+ * bins (device, gr_bin_bytes) receives the reordered records, the reordered
+ * weighted visibilities and the segment table.  support <= 56; n_vis < 2^31. */
+gr_status gr_bin(const void* records, const void* wvis, int64_t n_vis, int32_t n_pol,
+                 int32_t support, int32_t height, int32_t width, int32_t seg_len, void* bins,
+                 size_t bins_bytes, void* stream);
+
+/* Grid a binned stream (gr_bin output; the same n_vis, n_pol, support,
+ * height, width and seg_len) onto grid (+=).  Per segment, the 64 x 64-cell
+ * window is accumulated in matrix-core registers: the separable tile update
+ * of Section 4, in the factored form G^u_i (G^v_j V_p) of Section 6, is a
+ * rank-2 product per pair of visibilities (v_mfma_f32_16x16x4_f32), and the
+ * window is added to the grid once with FP32 atomic adds (Section 2.2).
+ * support <= 56; the FP32 tap table [planes][O][S] must fit in 160 KiB. */
+gr_status gr_grid_binned(const void* bins, int64_t n_vis, int32_t n_pol, const gr_kernel* kernel,
+                         int32_t seg_len, void* grid, int32_t height, int32_t width, void* stream);
+
+/* Bytes of workspace gr_grid needs (depends on the variant gr_grid selects
+ * for these arguments; 0 if they are invalid). */
+size_t gr_grid_workspace_bytes(int64_t n_vis, int32_t n_pol, const gr_kernel* kernel,
+                               int32_t height, int32_t width, const gr_tuning* tuning);
+
+/* The whole hot path: gr_preprocess into `workspace`, then either
+ * gr_grid_records (variant 1) or gr_bin + gr_grid_binned (variant 2; chosen
+ * by default when the kernel allows it).  Same semantics as those calls. */
 gr_status gr_grid(const double* uvw, const void* vis, int32_t vis_dtype, const float* vis_scale,
                   const float* weights, int64_t n_vis, int32_t n_pol, const gr_kernel* kernel,
                   double inv_cell_u, double inv_cell_v, void* grid, int32_t height,

@@ -63,13 +63,17 @@ def load_library():
         "gr_grid": [P, P, I32, P, P, I64, I32, KP, D, D, P, I32, I32, TP, P, SZ, P, P],
         "gr_make_kb_table": [D, I32, I32, I32, P, P],
         "gr_make_wkernel_table": [I32, I32, I32, D, D, I32, D, I32, I32, P, P],
+        "gr_bin": [P, P, I64, I32, I32, I32, I32, I32, P, SZ, P],
+        "gr_grid_binned": [P, I64, I32, KP, I32, P, I32, I32, P],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = ctypes.c_int
-    lib.gr_grid_workspace_bytes.argtypes = [I64, I32]
+    lib.gr_grid_workspace_bytes.argtypes = [I64, I32, KP, I32, I32, TP]
     lib.gr_grid_workspace_bytes.restype = SZ
+    lib.gr_bin_bytes.argtypes = [I64, I32, I32, I32, I32, I32]
+    lib.gr_bin_bytes.restype = SZ
     lib.gr_last_error.argtypes = []
     lib.gr_last_error.restype = ctypes.c_char_p
     lib.gr_version.argtypes = []
@@ -107,8 +111,25 @@ def gr_last_error() -> str:
     return load_library().gr_last_error().decode()
 
 
-def gr_grid_workspace_bytes(n_vis: int, n_pol: int) -> int:
-    return int(load_library().gr_grid_workspace_bytes(n_vis, n_pol))
+def gr_grid_workspace_bytes(n_vis: int, n_pol: int, kernel: GrKernel, height: int, width: int,
+                            tuning: Optional[GrTuning] = None) -> int:
+    return int(load_library().gr_grid_workspace_bytes(
+        n_vis, n_pol, ctypes.byref(kernel), height, width,
+        ctypes.byref(tuning) if tuning is not None else None))
+
+
+def gr_bin_bytes(n_vis: int, n_pol: int, support: int, height: int, width: int, seg_len: int = 0) -> int:
+    return int(load_library().gr_bin_bytes(n_vis, n_pol, support, height, width, seg_len))
+
+
+def gr_bin(records, wvis, n_vis, n_pol, support, height, width, seg_len, bins, bins_bytes, stream=None):
+    _check(load_library().gr_bin(_ptr(records), _ptr(wvis), n_vis, n_pol, support, height, width,
+                                 seg_len, _ptr(bins), bins_bytes, _stream(stream, bins)))
+
+
+def gr_grid_binned(bins, n_vis, n_pol, kernel: GrKernel, seg_len, grid, height, width, stream=None):
+    _check(load_library().gr_grid_binned(_ptr(bins), n_vis, n_pol, ctypes.byref(kernel), seg_len,
+                                         _ptr(grid), height, width, _stream(stream, grid)))
 
 
 def make_kernel(taps, support: int, oversample: int, n_planes: int = 1, taps_complex: bool = True,

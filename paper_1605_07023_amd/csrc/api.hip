@@ -9,8 +9,9 @@ namespace gr {
 namespace {
 thread_local std::string g_last_error;
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
-size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 }  // namespace
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
@@ -61,9 +62,41 @@ extern "C" const char* gr_last_error(void) { return g_last_error.c_str(); }
 
 extern "C" int32_t gr_version(void) { return 1; }
 
-extern "C" size_t gr_grid_workspace_bytes(int64_t n_vis, int32_t n_pol) {
-  if (n_vis < 0 || n_pol < 1) return 0;
+namespace {
+
+int seg_len_of(const gr_tuning* t) { return t && t->vis_per_wg > 0 ? t->vis_per_wg : kDefaultSegLen; }
+
+// variant actually used by gr_grid: 1 = VALU work-item kernel on the input order,
+// 2 = MFMA kernel on the binned stream
+int pick_variant(const gr_kernel& k, int n_pol, const gr_tuning* t) {
+  const int want = t ? t->variant : 0;
+  if (want == 1 || want == 2) return want;
+  size_t lds;
+  const std::string saved = g_last_error;
+  const bool mfma_ok = plan_mfma(k, n_pol, &lds) == GR_OK;
+  g_last_error = saved;
+  return mfma_ok ? 2 : 1;
+}
+
+size_t pre_bytes(int64_t n_vis, int n_pol) {
   return align256(sizeof(Record) * (size_t)n_vis) + align256(sizeof(float2) * (size_t)n_vis * n_pol);
+}
+
+}  // namespace
+
+extern "C" size_t gr_bin_bytes(int64_t n_vis, int32_t n_pol, int32_t support, int32_t height,
+                               int32_t width, int32_t seg_len) {
+  if (n_vis < 0 || n_pol < 1 || support < 2 || support > 56 || height < 1 || width < 1) return 0;
+  return bin_layout(n_vis, n_pol, support, height, width, seg_len > 0 ? seg_len : kDefaultSegLen).bytes;
+}
+
+extern "C" size_t gr_grid_workspace_bytes(int64_t n_vis, int32_t n_pol, const gr_kernel* kernel,
+                                          int32_t height, int32_t width, const gr_tuning* tuning) {
+  if (n_vis < 0 || n_pol < 1 || kernel == nullptr || height < 1 || width < 1) return 0;
+  size_t b = pre_bytes(n_vis, n_pol);
+  if (pick_variant(*kernel, n_pol, tuning) == 2)
+    b += bin_layout(n_vis, n_pol, kernel->support, height, width, seg_len_of(tuning)).bytes;
+  return b;
 }
 
 extern "C" gr_status gr_preprocess(const double* uvw, const void* vis, int32_t vis_dtype,
@@ -100,12 +133,43 @@ extern "C" gr_status gr_grid_records(const void* records, const void* wvis, int6
   if (n_vis > 0 && (records == nullptr || wvis == nullptr))
     return fail(GR_EINVAL, "records and wvis must be non-NULL");
   if (tuning && tuning->variant != 0 && tuning->variant != 1)
-    return fail(GR_EUNSUPPORTED, "tuning.variant not available in this build");
+    return fail(GR_EUNSUPPORTED, "gr_grid_records runs the VALU work-item kernel (variant 0 or 1)");
   RomeinPlan plan;
   if ((st = plan_romein(*kernel, n_pol, tuning, &plan)) != GR_OK) return st;
   return launch_romein(reinterpret_cast<const Record*>(records), reinterpret_cast<const float2*>(wvis),
                        n_vis, n_pol, *kernel, reinterpret_cast<float2*>(grid), height, width, plan,
                        (hipStream_t)stream);
+}
+
+extern "C" gr_status gr_bin(const void* records, const void* wvis, int64_t n_vis, int32_t n_pol,
+                            int32_t support, int32_t height, int32_t width, int32_t seg_len,
+                            void* bins, size_t bins_bytes, void* stream) {
+  if (n_pol != 1 && n_pol != 4) return fail(GR_EINVAL, "n_pol must be 1 or 4");
+  if (support < 2 || support > 56 || (support & 1)) return fail(GR_EINVAL, "gr_bin: support must be even, 2..56");
+  if (height < support || width < support || height > kMaxGrid || width > kMaxGrid)
+    return fail(GR_EINVAL, "grid height/width must be in [support, 32768]");
+  if (n_vis < 0 || n_vis > 0x7fffffffLL) return fail(GR_EINVAL, "gr_bin: n_vis must be in [0, 2^31)");
+  if (n_vis > 0 && (records == nullptr || wvis == nullptr)) return fail(GR_EINVAL, "records and wvis must be non-NULL");
+  if (bins == nullptr) return fail(GR_EINVAL, "bins is NULL");
+  const BinLayout L = bin_layout(n_vis, n_pol, support, height, width, seg_len > 0 ? seg_len : kDefaultSegLen);
+  if (bins_bytes < L.bytes) return fail(GR_ENOMEM, "bins buffer too small (see gr_bin_bytes)");
+  return launch_bin(reinterpret_cast<const Record*>(records), reinterpret_cast<const float2*>(wvis), n_vis,
+                    n_pol, L, bins, (hipStream_t)stream);
+}
+
+extern "C" gr_status gr_grid_binned(const void* bins, int64_t n_vis, int32_t n_pol, const gr_kernel* kernel,
+                                    int32_t seg_len, void* grid, int32_t height, int32_t width, void* stream) {
+  gr_status st = validate_kernel(kernel, true);
+  if (st != GR_OK) return st;
+  if ((st = validate_grid(n_pol, height, width, kernel->support)) != GR_OK) return st;
+  if (n_vis < 0 || n_vis > 0x7fffffffLL) return fail(GR_EINVAL, "n_vis must be in [0, 2^31)");
+  if (grid == nullptr || bins == nullptr) return fail(GR_EINVAL, "grid and bins must be non-NULL");
+  size_t lds;
+  if ((st = plan_mfma(*kernel, n_pol, &lds)) != GR_OK) return st;
+  const BinLayout L = bin_layout(n_vis, n_pol, kernel->support, height, width,
+                                 seg_len > 0 ? seg_len : kDefaultSegLen);
+  return launch_mfma(bins, L, n_pol, *kernel, reinterpret_cast<float2*>(grid), height, width,
+                     (hipStream_t)stream);
 }
 
 extern "C" gr_status gr_grid(const double* uvw, const void* vis, int32_t vis_dtype,
@@ -119,19 +183,31 @@ extern "C" gr_status gr_grid(const double* uvw, const void* vis, int32_t vis_dty
   if ((st = validate_grid(n_pol, height, width, kernel->support)) != GR_OK) return st;
   if (n_vis < 0) return fail(GR_EINVAL, "n_vis must be >= 0");
   if (grid == nullptr) return fail(GR_EINVAL, "grid is NULL");
-  const size_t need = gr_grid_workspace_bytes(n_vis, n_pol);
+  if (tuning && (tuning->variant < 0 || tuning->variant > 2))
+    return fail(GR_EUNSUPPORTED, "tuning.variant not available in this build");
+  const int variant = pick_variant(*kernel, n_pol, tuning);
+  const size_t need = gr_grid_workspace_bytes(n_vis, n_pol, kernel, height, width, tuning);
   if (n_vis > 0 && workspace == nullptr) return fail(GR_EINVAL, "workspace is NULL");
   if (workspace_bytes < need) return fail(GR_ENOMEM, "workspace too small (see gr_grid_workspace_bytes)");
   RomeinPlan plan;
-  if ((st = plan_romein(*kernel, n_pol, tuning, &plan)) != GR_OK) return st;
-  if (tuning && tuning->variant != 0 && tuning->variant != 1)
-    return fail(GR_EUNSUPPORTED, "tuning.variant not available in this build");
+  size_t lds;
+  if (variant == 1 && (st = plan_romein(*kernel, n_pol, tuning, &plan)) != GR_OK) return st;
+  if (variant == 2) {
+    if ((st = plan_mfma(*kernel, n_pol, &lds)) != GR_OK) return st;
+    if (n_vis > 0x7fffffffLL) return fail(GR_EINVAL, "n_vis must be < 2^31 for the MFMA gridder");
+  }
   auto* rec = reinterpret_cast<Record*>(workspace);
   auto* wv = reinterpret_cast<float2*>(reinterpret_cast<char*>(workspace) +
                                        align256(sizeof(Record) * (size_t)n_vis));
   st = gr_preprocess(uvw, vis, vis_dtype, vis_scale, weights, n_vis, n_pol, kernel, inv_cell_u,
                      inv_cell_v, height, width, rec, wv, dev_stats, stream);
   if (st != GR_OK) return st;
-  return launch_romein(rec, wv, n_vis, n_pol, *kernel, reinterpret_cast<float2*>(grid), height, width,
-                       plan, (hipStream_t)stream);
+  if (variant == 1)
+    return launch_romein(rec, wv, n_vis, n_pol, *kernel, reinterpret_cast<float2*>(grid), height, width,
+                         plan, (hipStream_t)stream);
+  void* bins = reinterpret_cast<char*>(workspace) + pre_bytes(n_vis, n_pol);
+  const BinLayout L = bin_layout(n_vis, n_pol, kernel->support, height, width, seg_len_of(tuning));
+  if ((st = launch_bin(rec, wv, n_vis, n_pol, L, bins, (hipStream_t)stream)) != GR_OK) return st;
+  return launch_mfma(bins, L, n_pol, *kernel, reinterpret_cast<float2*>(grid), height, width,
+                     (hipStream_t)stream);
 }

@@ -1,0 +1,168 @@
+// Binning of the preprocessed visibility stream by footprint position.
+//
+// The grid is cut into square tiles of T cells; each valid visibility goes to
+// the tile that holds its footprint origin (x0, y0), so its whole footprint
+// lies inside the tile's (T + S - 1)-cell window.  Within a tile the input
+// order is kept for every run of 64 consecutive visibilities (in practice runs
+// of one baseline's track), so that neighbouring entries of a tile's list are
+// neighbours on the sky as they are in the paper's baseline-ordered stream
+// (Section 4).  Each tile's list is cut into segments of at most L entries;
+// one segment is the unit of work of the MFMA gridder.
+//
+// Kernels: count (wave-aggregated atomics per tile), scan (one block:
+// offsets, segment table), scatter (wave-aggregated reservation, stable
+// within each wave's 64 entries).
+#include "internal.h"
+
+namespace gr {
+
+namespace {
+
+__device__ inline int tile_of(Record r, int tile, int n_tx) {
+  return (rec_y0(r) / tile) * n_tx + rec_x0(r) / tile;
+}
+
+__global__ void __launch_bounds__(256) fill_i32(int32_t* p, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// One visibility per lane; lanes of a wave with the same tile add once.
+__global__ void __launch_bounds__(256)
+bin_count_kernel(const Record* __restrict__ rec, int64_t n, int tile, int n_tx,
+                 int32_t* __restrict__ count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  int key = -1;
+  if (i < n) {
+    const Record r = rec[i];
+    if (rec_valid(r)) key = tile_of(r, tile, n_tx);
+  }
+  uint64_t todo = __ballot(key >= 0);
+  while (todo) {
+    const int leader = __ffsll((unsigned long long)todo) - 1;
+    const int k = __shfl(key, leader);
+    const uint64_t same = __ballot(key == k);
+    if (lane == leader) atomicAdd(&count[k], (int32_t)__popcll(same));
+    todo &= ~same;
+  }
+}
+
+// Single block of 1024 threads: exclusive scan of counts -> cursor (list
+// offsets), and the segment table {begin, length, tile, 0}.
+__global__ void __launch_bounds__(1024)
+bin_scan_kernel(const int32_t* __restrict__ count, int n_tiles, int seg_len,
+                int32_t* __restrict__ cursor, int4* __restrict__ segs,
+                int32_t* __restrict__ n_segs_out) {
+  __shared__ int64_t s_vis[1024];
+  __shared__ int64_t s_seg[1024];
+  const int t = threadIdx.x, T = blockDim.x;
+  const int per = (n_tiles + T - 1) / T;
+  const int a = min(n_tiles, t * per), b = min(n_tiles, a + per);
+  int64_t v = 0, g = 0;
+  for (int i = a; i < b; ++i) {
+    v += count[i];
+    g += (count[i] + seg_len - 1) / seg_len;
+  }
+  s_vis[t] = v;
+  s_seg[t] = g;
+  __syncthreads();
+  for (int off = 1; off < T; off <<= 1) {          // Hillis-Steele inclusive scan
+    int64_t xv = 0, xg = 0;
+    if (t >= off) {
+      xv = s_vis[t - off];
+      xg = s_seg[t - off];
+    }
+    __syncthreads();
+    s_vis[t] += xv;
+    s_seg[t] += xg;
+    __syncthreads();
+  }
+  int64_t base = s_vis[t] - v, sbase = s_seg[t] - g;
+  for (int i = a; i < b; ++i) {
+    const int c = count[i];
+    cursor[i] = (int32_t)base;
+    for (int s0 = 0; s0 < c; s0 += seg_len) {
+      segs[sbase++] = make_int4((int)(base + s0), min(seg_len, c - s0), i, 0);
+    }
+    base += c;
+  }
+  if (t == T - 1) *n_segs_out = (int32_t)s_seg[T - 1];
+}
+
+__global__ void __launch_bounds__(256)
+bin_scatter_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvis, int64_t n,
+                   int n_pol, int tile, int n_tx, int32_t* __restrict__ cursor,
+                   Record* __restrict__ out_rec, float2* __restrict__ out_wvis) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  int key = -1;
+  Record r{0, 0};
+  if (i < n) {
+    r = rec[i];
+    if (rec_valid(r)) key = tile_of(r, tile, n_tx);
+  }
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  int pos = -1;
+  uint64_t todo = __ballot(key >= 0);
+  while (todo) {
+    const int leader = __ffsll((unsigned long long)todo) - 1;
+    const int k = __shfl(key, leader);
+    const uint64_t same = __ballot(key == k);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&cursor[k], (int32_t)__popcll(same));
+    base = __shfl(base, leader);
+    if (key == k) pos = base + (int)__popcll(same & below);
+    todo &= ~same;
+  }
+  if (pos >= 0) {
+    out_rec[pos] = r;
+    for (int p = 0; p < n_pol; ++p) out_wvis[(int64_t)pos * n_pol + p] = wvis[i * n_pol + p];
+  }
+}
+
+}  // namespace
+
+BinLayout bin_layout(int64_t n_vis, int n_pol, int support, int height, int width, int seg_len) {
+  BinLayout L{};
+  L.tile = binned_tile(support);
+  L.n_tx = (width + L.tile - 1) / L.tile;
+  L.n_ty = (height + L.tile - 1) / L.tile;
+  L.n_tiles = (int64_t)L.n_tx * L.n_ty;
+  L.seg_len = seg_len;
+  L.max_segs = L.n_tiles + (n_vis + seg_len - 1) / seg_len;
+  size_t off = 0;
+  L.off_rec = off;     off += align256(sizeof(Record) * (size_t)n_vis);
+  L.off_wvis = off;    off += align256(sizeof(float2) * (size_t)n_vis * n_pol);
+  L.off_count = off;   off += align256(sizeof(int32_t) * (size_t)L.n_tiles);
+  L.off_cursor = off;  off += align256(sizeof(int32_t) * (size_t)L.n_tiles);
+  L.off_segs = off;    off += align256(sizeof(int4) * (size_t)L.max_segs);
+  L.off_nsegs = off;   off += 256;
+  L.bytes = off;
+  return L;
+}
+
+gr_status launch_bin(const Record* rec, const float2* wvis, int64_t n_vis, int n_pol,
+                     const BinLayout& L, void* bins, hipStream_t stream) {
+  char* base = reinterpret_cast<char*>(bins);
+  auto* count = reinterpret_cast<int32_t*>(base + L.off_count);
+  auto* cursor = reinterpret_cast<int32_t*>(base + L.off_cursor);
+  auto* segs = reinterpret_cast<int4*>(base + L.off_segs);
+  auto* nsegs = reinterpret_cast<int32_t*>(base + L.off_nsegs);
+  auto* orec = reinterpret_cast<Record*>(base + L.off_rec);
+  auto* owv = reinterpret_cast<float2*>(base + L.off_wvis);
+  if (L.n_tiles > 0x7fffffff) return fail(GR_EINVAL, "gr_bin: too many tiles");
+  fill_i32<<<(unsigned)((L.n_tiles + 255) / 256), 256, 0, stream>>>(count, L.n_tiles, 0);
+  fill_i32<<<1, 256, 0, stream>>>(nsegs, 1, 0);
+  const int64_t blocks = (n_vis + 255) / 256;
+  if (blocks > 0x7fffffff) return fail(GR_EINVAL, "gr_bin: n_vis too large");
+  if (n_vis > 0)
+    bin_count_kernel<<<(unsigned)blocks, 256, 0, stream>>>(rec, n_vis, L.tile, L.n_tx, count);
+  bin_scan_kernel<<<1, 1024, 0, stream>>>(count, (int)L.n_tiles, L.seg_len, cursor, segs, nsegs);
+  if (n_vis > 0)
+    bin_scatter_kernel<<<(unsigned)blocks, 256, 0, stream>>>(rec, wvis, n_vis, n_pol, L.tile, L.n_tx,
+                                                            cursor, orec, owv);
+  return check_launch("gr_bin");
+}
+
+}  // namespace gr

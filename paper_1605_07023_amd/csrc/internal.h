@@ -60,4 +60,23 @@ gr_status launch_romein(const Record* rec, const float2* wvis, int64_t n_vis, in
                         const gr_kernel& k, float2* grid, int height, int width,
                         const RomeinPlan& plan, hipStream_t stream);
 
+// Binning of the preprocessed stream by footprint tile (bin.hip).
+struct BinLayout {
+  int tile, n_tx, n_ty, seg_len;
+  int64_t n_tiles, max_segs;
+  size_t off_rec, off_wvis, off_count, off_cursor, off_segs, off_nsegs, bytes;
+};
+int binned_tile(int support);   // tile edge T (cells): every footprint of the tile fits 64 cells
+BinLayout bin_layout(int64_t n_vis, int n_pol, int support, int height, int width, int seg_len);
+gr_status launch_bin(const Record* rec, const float2* wvis, int64_t n_vis, int n_pol,
+                     const BinLayout& L, void* bins, hipStream_t stream);
+
+// MFMA gridder over the binned stream (grid_mfma.hip).
+gr_status plan_mfma(const gr_kernel& k, int n_pol, size_t* lds_bytes);
+gr_status launch_mfma(const void* bins, const BinLayout& L, int n_pol, const gr_kernel& k,
+                      float2* grid, int height, int width, hipStream_t stream);
+
+constexpr int kDefaultSegLen = 4096;
+size_t align256(size_t v);
+
 }  // namespace gr

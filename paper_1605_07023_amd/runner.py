@@ -80,7 +80,7 @@ def grid(dw: DeviceWorkload, grid_out: Optional[torch.Tensor] = None,
     dev = dw.uvw.device
     if grid_out is None:
         grid_out = torch.zeros((wl.n_pol, wl.height, wl.width), dtype=torch.complex64, device=dev)
-    need = B.gr_grid_workspace_bytes(wl.n_vis, wl.n_pol)
+    need = B.gr_grid_workspace_bytes(wl.n_vis, wl.n_pol, dw.kernel, wl.height, wl.width, tune)
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
     B.gr_grid(dw.uvw, dw.vis, B.GR_F32, None, dw.weights, wl.n_vis, wl.n_pol, dw.kernel,

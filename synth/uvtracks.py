@@ -20,6 +20,7 @@ then time.
 from __future__ import annotations
 
 import dataclasses
+import functools
 import math
 from typing import Optional
 
@@ -126,9 +127,30 @@ def _w_planes(uvw: np.ndarray, n_planes: int, w_hat_max: float):
 
 
 def _draw_vis(rng: np.random.Generator, n: int, n_pol: int) -> np.ndarray:
-    re = rng.standard_normal((n, n_pol), dtype=np.float32)
-    im = rng.standard_normal((n, n_pol), dtype=np.float32)
-    return (re + 1j * im).astype(np.complex64)
+    """Real and imaginary parts i.i.d. N(0, 1), drawn interleaved (re, im) per value."""
+    out = np.empty((n, n_pol), dtype=np.complex64)
+    rng.standard_normal(out=out.view(np.float32), dtype=np.float32)
+    return out
+
+
+@functools.lru_cache(maxsize=2)
+def _full_shape_arrays(seed: int, n_times: int, n_chan: int, n_pol: int, n_ant: int):
+    """uvw [N, 3] (baseline, time, channel order), vis [N, P], and
+    (max(|u|, |v|), max |w|) of the full array; shared by every support size."""
+    rng = np.random.default_rng(seed)
+    enu = antenna_enu(rng, n_ant, 1000.0)
+    pairs = baseline_pairs(n_ant)
+    b = enu[pairs[:, 1]] - enu[pairs[:, 0]]
+    freqs = np.linspace(1.4e9 * 0.95, 1.4e9 * 1.05, n_chan)
+    uvw = enu_baselines_to_uvw(b, math.radians(-30.7), math.radians(-30.0),
+                               _hour_angles(8.0, n_times), freqs).reshape(-1, 3)
+    uvw = np.ascontiguousarray(uvw)
+    uv_max = float(max(np.max(np.abs(uvw[:, 0])), np.max(np.abs(uvw[:, 1]))))
+    w_max = float(np.max(np.abs(uvw[:, 2])))
+    vis = _draw_vis(rng, uvw.shape[0], n_pol)
+    uvw.setflags(write=False)
+    vis.setflags(write=False)
+    return uvw, vis, (uv_max, w_max)
 
 
 def tiny_kb_workload(seed: int = 0) -> Workload:
@@ -159,20 +181,16 @@ def full_shape_workload(support: int, seed: int = 0, n_baselines: Optional[int] 
     tests that need the real geometry at a smaller size; the scale factors are
     always those of the full array so positions do not change.
     """
-    rng = np.random.default_rng(seed)
-    enu = antenna_enu(rng, n_ant, 1000.0)
-    pairs = baseline_pairs(n_ant)
-    b = enu[pairs[:, 1]] - enu[pairs[:, 0]]
-    freqs = np.linspace(1.4e9 * 0.95, 1.4e9 * 1.05, n_chan)
-    uvw_full = enu_baselines_to_uvw(b, math.radians(-30.7), math.radians(-30.0),
-                                    _hour_angles(8.0, n_times), freqs)
-    flat = uvw_full.reshape(-1, 3)
-    s = _fit_scale(flat, grid, grid, support)
-    w_min, inv_dw, w_hat_scale = _w_planes(flat, n_planes, float(support - 8))
+    uvw_full, vis_full, umax = _full_shape_arrays(seed, n_times, n_chan, n_pol, n_ant)
+    half = grid // 2 - support // 2 - 2
+    s = half / umax[0]
+    wmax = umax[1]
+    w_min, inv_dw, w_hat_scale = -wmax, (n_planes - 1) / (2.0 * wmax), float(support - 8) / wmax
     if n_baselines is not None:
-        flat = uvw_full[:n_baselines].reshape(-1, 3)
-    flat = np.ascontiguousarray(flat)
-    vis = _draw_vis(rng, flat.shape[0], n_pol)
+        n_rows = n_baselines * n_times * n_chan
+        flat, vis = uvw_full[:n_rows], vis_full[:n_rows]
+    else:
+        flat, vis = uvw_full, vis_full
     return Workload(f"full-shape-S{support}", flat, vis, None, grid, grid, support, 8, s, s,
                     n_planes=n_planes, w_min=w_min, inv_dw=inv_dw, w_hat_scale=w_hat_scale,
                     kernel="wsep", beta=8.6, support_aa=8)
@@ -220,6 +238,8 @@ def random_point_workload(n_vis: int, n_pol: int, height: int, width: int, suppo
     parity and edge-case tests.  ``margin`` pixels beyond the grid edge are
     allowed so that some footprints fall off the grid and get dropped."""
     rng = np.random.default_rng(seed)
+    if kernel == "kb":
+        n_planes = 1                    # the Kaiser-Bessel table has a single plane
     inv_cell = 1.0
     half_u = width / 2 - support / 2 - 1 + margin
     half_v = height / 2 - support / 2 - 1 + margin

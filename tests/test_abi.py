@@ -39,9 +39,13 @@ def test_every_declared_symbol_is_exported(lib):
 def test_version_and_workspace(lib):
     from paper_1605_07023_amd import binding as B
     assert B.gr_version() >= 1
-    n = B.gr_grid_workspace_bytes(1000, 4)
-    assert n >= 1000 * 8 + 1000 * 4 * 8
-    assert B.gr_grid_workspace_bytes(-1, 4) == 0
+    k = _kernel()
+    n1 = B.gr_grid_workspace_bytes(1000, 4, k, 64, 64, B.GrTuning(0, 0, 0, 0, 0, 1))
+    assert n1 >= 1000 * 8 + 1000 * 4 * 8
+    n2 = B.gr_grid_workspace_bytes(1000, 4, k, 64, 64)
+    assert n2 >= 2 * n1 and n2 >= n1 + B.gr_bin_bytes(1000, 4, 16, 64, 64)
+    assert B.gr_grid_workspace_bytes(-1, 4, k, 64, 64) == 0
+    assert B.gr_bin_bytes(10, 4, 58, 64, 64) == 0
 
 
 def _kernel(**kw):

@@ -117,12 +117,81 @@ TUNINGS_P4 = [(1, 1), (2, 2), (4, 2), (2, 4), (4, 4), (8, 2), (8, 1)]
 
 @pytest.mark.parametrize("cu,cv", TUNINGS_P1)
 def test_grid_tiny_config(R, cu, cv):
-    _say(f"grid tiny KB config cu={cu} cv={cv}")
+    _say(f"grid tiny KB config VALU cu={cu} cv={cv}")
     wl = tiny_kb_workload()
     dw = R.upload(wl, DEV)
-    g = R.grid(dw, tune=R.tuning(cu, cv)).cpu().numpy()
+    g = R.grid(dw, tune=R.tuning(cu, cv, variant=1)).cpu().numpy()
     ref, _ = _oracle_grid(wl, _oracle_taps(wl))
     assert _rel_l2(g, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("seg", [0, 1, 7, 64])
+def test_grid_tiny_config_mfma(R, seg):
+    _say(f"grid tiny KB config MFMA seg_len={seg}")
+    wl = tiny_kb_workload()
+    dw = R.upload(wl, DEV)
+    g = R.grid(dw, tune=R.tuning(vis_per_wg=seg, variant=2)).cpu().numpy()
+    ref, _ = _oracle_grid(wl, _oracle_taps(wl))
+    assert _rel_l2(g, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("S,P,seg", [(8, 4, 0), (16, 4, 33), (32, 4, 4096), (16, 1, 5), (32, 1, 0),
+                                     (56, 4, 100), (2, 1, 3)])
+def test_grid_points_mfma(R, S, P, seg):
+    _say(f"grid random points MFMA S={S} P={P} seg_len={seg}")
+    wl = random_point_workload(4001, P, 200, 136, S, 8, seed=S + P, n_planes=5, margin=6,
+                               weights=True, kernel="wsep" if S >= 8 else "kb")
+    if S < 8:
+        wl.beta = 2.0
+    dw = R.upload(wl, DEV)
+    stats = torch.zeros(2, dtype=torch.int64, device=DEV)
+    g = R.grid(dw, tune=R.tuning(vis_per_wg=seg, variant=2), stats=stats).cpu().numpy()
+    ref, dropped = _oracle_grid(wl, _oracle_taps(wl))
+    assert _rel_l2(g, ref) <= 1e-5
+    assert stats.cpu().tolist() == [wl.n_vis - dropped, dropped] and dropped > 0
+
+
+def test_bin_is_a_grouping_of_the_valid_stream(R):
+    """gr_bin output: every valid record exactly once, each segment inside its
+    tile, segment lengths <= seg_len, input order kept within runs."""
+    from paper_1605_07023_amd import binding as B
+    _say("gr_bin grouping")
+    S, seg = 16, 50
+    wl = random_point_workload(3000, 4, 256, 192, S, 8, seed=1, n_planes=3, margin=4,
+                               weights=False, kernel="wsep")
+    dw = R.upload(wl, DEV)
+    rec, wv = R.preprocess(dw)
+    nb = B.gr_bin_bytes(wl.n_vis, 4, S, 256, 192, seg)
+    bins = torch.zeros(nb, dtype=torch.uint8, device=DEV)
+    B.gr_bin(rec, wv, wl.n_vis, 4, S, 256, 192, seg, bins, nb)
+    torch.cuda.synchronize()
+    raw = bins.cpu().numpy()
+    r_in = rec.cpu().numpy().view(np.uint64).ravel()
+    valid = (r_in >> np.uint64(63)) == 1
+    nv = int(valid.sum())
+    r_out = raw[:8 * nv].view(np.uint64)
+    np.testing.assert_array_equal(np.sort(r_out), np.sort(r_in[valid]))
+    # weighted visibilities travel with their records
+    off_w = (8 * wl.n_vis + 255) // 256 * 256
+    w_out = raw[off_w:off_w + 32 * nv].view(np.complex64).reshape(nv, 4)
+    w_in = wv.cpu().numpy()[valid]
+    order = {int(k): i for i, k in enumerate(r_in[valid])}
+    # records can repeat in principle; this draw has unique records
+    assert len(order) == nv
+    np.testing.assert_array_equal(w_out, w_in[[order[int(k)] for k in r_out]])
+    T = 64 - S
+    n_tx, n_ty = -(-192 // T), -(-256 // T)
+    off = off_w + (32 * wl.n_vis + 255) // 256 * 256
+    off += 2 * ((4 * n_tx * n_ty + 255) // 256 * 256)
+    max_segs = n_tx * n_ty + -(-wl.n_vis // seg)
+    segs = raw[off:off + 16 * max_segs].view(np.int32).reshape(-1, 4)
+    n_segs = int(raw[off + (16 * max_segs + 255) // 256 * 256:][:4].view(np.int32)[0])
+    segs = segs[:n_segs]
+    assert segs[:, 1].sum() == nv and segs[:, 1].max() <= seg and segs[:, 1].min() >= 1
+    x0 = (r_out & np.uint64(0xFFFF)).astype(np.int64)
+    y0 = ((r_out >> np.uint64(16)) & np.uint64(0xFFFF)).astype(np.int64)
+    for b, ln, t, _ in segs:
+        assert np.all(x0[b:b + ln] // T == t % n_tx) and np.all(y0[b:b + ln] // T == t // n_tx)
 
 
 @pytest.mark.parametrize("cu,cv", TUNINGS_P4)
@@ -159,49 +228,53 @@ def _custom_taps_run(R, wl, taps_np, tune):
     return R.grid(dw, tune=tune).cpu().numpy()
 
 
-@pytest.mark.parametrize("cu,cv", [(1, 1), (4, 2), (8, 8)])
-def test_delta_table_and_integer_inputs_bit_exact(R, cu, cv):
+@pytest.mark.parametrize("cu,cv,variant", [(1, 1, 1), (4, 2, 1), (8, 8, 1), (0, 0, 2)])
+def test_delta_table_and_integer_inputs_bit_exact(R, cu, cv, variant):
     """Integer visibilities with integer taps: every partial sum is an exact
     FP32 integer, so the grid must equal the FP64 oracle bit for bit whatever
     order the atomics land in (a lost or duplicated flush would show)."""
-    _say(f"integer-valued inputs bit-exact cu={cu} cv={cv}")
+    _say(f"integer-valued inputs bit-exact cu={cu} cv={cv} variant={variant}")
     rng = np.random.default_rng(cu * 10 + cv)
     wl = random_point_workload(4000, 1, 64, 64, 8, 8, seed=11, weights=False)
     wl.vis = (rng.integers(-3, 4, (wl.n_vis, 1)) + 1j * rng.integers(-3, 4, (wl.n_vis, 1))).astype(np.complex64)
     # delta table: every visibility lands on its own cell
     delta = np.zeros((1, 8, 8))
     delta[:, :, 3] = 1.0
-    g = _custom_taps_run(R, wl, delta, R.tuning(cu, cv, vis_per_wg=64))
+    g = _custom_taps_run(R, wl, delta, R.tuning(cu, cv, vis_per_wg=64, variant=variant))
     ref, _ = _oracle_grid(wl, delta)
     np.testing.assert_array_equal(g.astype(np.complex128), ref)
     # small-integer taps in {0, 1, 2}
     ints = rng.integers(0, 3, (1, 8, 8)).astype(np.float64)
-    g = _custom_taps_run(R, wl, ints, R.tuning(cu, cv, vis_per_wg=64))
+    g = _custom_taps_run(R, wl, ints, R.tuning(cu, cv, vis_per_wg=64, variant=variant))
     ref, _ = _oracle_grid(wl, ints)
     assert np.abs(ref).max() < 2 ** 20
     np.testing.assert_array_equal(g.astype(np.complex128), ref)
 
 
-def test_integer_complex_taps_quad_pol_bit_exact(R):
-    _say("integer complex taps, quad pol, bit-exact")
+@pytest.mark.parametrize("variant", [1, 2])
+def test_integer_complex_taps_quad_pol_bit_exact(R, variant):
+    _say(f"integer complex taps, quad pol, bit-exact, variant={variant}")
     rng = np.random.default_rng(7)
     wl = random_point_workload(2000, 4, 48, 56, 16, 4, seed=12, n_planes=3, weights=False,
                                kernel="wsep")
     wl.vis = (rng.integers(-2, 3, (wl.n_vis, 4)) + 1j * rng.integers(-2, 3, (wl.n_vis, 4))).astype(np.complex64)
     taps = (rng.integers(-1, 2, (3, 4, 16)) + 1j * rng.integers(-1, 2, (3, 4, 16)))
     taps_np = np.stack([taps.real, taps.imag], axis=-1)
-    g = _custom_taps_run(R, wl, taps_np, R.tuning(4, 2, vis_per_wg=128))
+    g = _custom_taps_run(R, wl, taps_np, R.tuning(4 if variant == 1 else 0, 2 if variant == 1 else 0,
+                                                   vis_per_wg=128, variant=variant))
     ref, _ = _oracle_grid(wl, taps)
     np.testing.assert_array_equal(g.astype(np.complex128), ref)
 
 
-def test_accumulates_and_edge_cases(R):
-    _say("accumulate into existing grid; empty input; all dropped")
+@pytest.mark.parametrize("variant", [1, 2])
+def test_accumulates_and_edge_cases(R, variant):
+    _say(f"accumulate into existing grid; empty input; all dropped; variant={variant}")
+    tune = R.tuning(variant=variant)
     wl = random_point_workload(500, 4, 40, 40, 8, 8, seed=2, n_planes=1, kernel="kb")
     dw = R.upload(wl, DEV)
     base = (torch.randn(4, 40, 40, dtype=torch.complex64, device=DEV))
     g0 = base.clone()
-    R.grid(dw, grid_out=g0)
+    R.grid(dw, grid_out=g0, tune=tune)
     ref, _ = _oracle_grid(wl, _oracle_taps(wl))
     got = g0.cpu().numpy().astype(np.complex128) - base.cpu().numpy()
     assert _rel_l2(got, ref) <= 1e-5
@@ -210,7 +283,7 @@ def test_accumulates_and_edge_cases(R):
     e.uvw, e.vis = wl.uvw[:0], wl.vis[:0]
     de = R.upload(e, DEV)
     g1 = base.clone()
-    R.grid(de, grid_out=g1)
+    R.grid(de, grid_out=g1, tune=tune)
     assert torch.equal(g1, base)
     # every visibility off the grid: dropped and counted, grid untouched
     off = copy.copy(wl)
@@ -219,7 +292,7 @@ def test_accumulates_and_edge_cases(R):
     do = R.upload(off, DEV)
     stats = torch.zeros(2, dtype=torch.int64, device=DEV)
     g2 = base.clone()
-    R.grid(do, grid_out=g2, stats=stats)
+    R.grid(do, grid_out=g2, stats=stats, tune=tune)
     assert torch.equal(g2, base)
     assert stats.cpu().tolist() == [0, wl.n_vis]
 
@@ -231,16 +304,16 @@ def full_S16():
     return full_shape_workload(16)
 
 
-@pytest.mark.parametrize("S", [16, 32])
-def test_full_shape_sampled_rows(R, c_oracle, S, full_S16):
+@pytest.mark.parametrize("S,variant", [(16, 2), (32, 2), (32, 1)])
+def test_full_shape_sampled_rows(R, c_oracle, S, variant, full_S16):
     """The 64-antenna, 16-channel, 1024-dump, quad-pol 4096^2 workload at full
     size, in the default launch configuration, checked on sampled grid rows
     against the FP64 C oracle (which computes those rows from every visibility)."""
     wl = full_S16 if S == 16 else full_shape_workload(32)
-    _say(f"full shape S={S}: N={wl.n_vis}")
+    _say(f"full shape S={S} variant={variant}: N={wl.n_vis}")
     dw = R.upload(wl, DEV)
     stats = torch.zeros(2, dtype=torch.int64, device=DEV)
-    g = R.grid(dw, stats=stats)
+    g = R.grid(dw, stats=stats, tune=R.tuning(variant=variant))
     torch.cuda.synchronize()
     assert stats.cpu().tolist() == [wl.n_vis, 0]
     rows = [64, 1100, 2047, 2048, 2049, 2900, 3990]
