@@ -88,6 +88,9 @@ def main() -> int:
     ap.add_argument("--seg-len", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one device-to-device copy of this size before timing "
+                         "(reference dispatch for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not "
@@ -147,6 +150,15 @@ def main() -> int:
                 e1.record(stream)
                 ev[S].append((e0, e1))
 
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib << 18                     # float32 elements
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.calib_copy_mib} MiB done")
+        del src, dst
     log(f"warmup {args.warmup} steps")
     for _ in range(args.warmup):
         step(False)
