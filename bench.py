@@ -88,6 +88,9 @@ def main() -> int:
     ap.add_argument("--seg-len", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=["f32", "f16", "bf16"], default="f32",
+                    help="storage of taps and visibilities (f16/bf16: taps in that type, "
+                         "visibilities as float16 pairs with one float32 scale per 256)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this size before timing "
                          "(reference dispatch for HBM byte counters)")
@@ -114,12 +117,22 @@ def main() -> int:
     N, P = wl0.n_vis, wl0.n_pol
     log(f"uploading N={N} P={P}")
     uvw = torch.from_numpy(np.ascontiguousarray(wl0.uvw)).to(dev)
-    vis = torch.from_numpy(np.ascontiguousarray(wl0.vis)).to(dev)
+    tap_dt = {"f32": B.GR_F32, "f16": B.GR_F16, "bf16": B.GR_BF16}[args.precision]
+    vis_scale = None
+    vis_dt = B.GR_F32
+    if args.precision == "f32":
+        vis = torch.from_numpy(np.ascontiguousarray(wl0.vis)).to(dev)
+    else:
+        from synth import quantize_vis_f16
+        halves, scales = quantize_vis_f16(wl0.vis)
+        vis = torch.from_numpy(halves).to(dev)
+        vis_scale = torch.from_numpy(scales).to(dev)
+        vis_dt = B.GR_F16
     taps, kern, grids = {}, {}, {}
     for S, wl in wls.items():
-        taps[S] = runner.make_taps(wl, dev, B.GR_F32)
+        taps[S] = runner.make_taps(wl, dev, tap_dt)
         kern[S] = B.make_kernel(taps[S], S, wl.oversample, wl.n_planes, taps_complex=True,
-                                tap_dtype=B.GR_F32, w_min=wl.w_min, inv_dw=wl.inv_dw)
+                                tap_dtype=tap_dt, w_min=wl.w_min, inv_dw=wl.inv_dw)
         grids[S] = torch.zeros((P, wl.height, wl.width), dtype=torch.complex64, device=dev)
     rec = torch.empty((N, 2), dtype=torch.int32, device=dev)
     wvis = torch.empty((N, P), dtype=torch.complex64, device=dev)
@@ -135,7 +148,7 @@ def main() -> int:
     def step(record: bool):
         for S in supports:
             wl = wls[S]
-            B.gr_preprocess(uvw, vis, B.GR_F32, None, None, N, P, kern[S], wl.inv_cell_u,
+            B.gr_preprocess(uvw, vis, vis_dt, vis_scale, None, N, P, kern[S], wl.inv_cell_u,
                             wl.inv_cell_v, wl.height, wl.width, rec, wvis, stats, stream)
             if variant == 2:
                 B.gr_bin(rec, wvis, N, P, S, wl.height, wl.width, seg_len, bins, bins_bytes, stream)
@@ -218,6 +231,7 @@ def main() -> int:
         "metric": "vis-tap updates/s", "value": value, "unit": "updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "storage": args.precision,
         "data": "synthetic",
         "config": {"workload": "earth-rotation uv tracks, 64 antennas (2016 baselines) x 1024 dumps "
                                "over 8 h x 16 channels, quad pol, 4096^2 grid, separable W kernels "

@@ -45,6 +45,8 @@ class DeviceWorkload:
     taps: torch.Tensor
     kernel: B.GrKernel
     tap_dtype: int
+    vis_dtype: int = B.GR_F32
+    vis_scale: Optional[torch.Tensor] = None
 
     @property
     def n_vis(self):
@@ -56,16 +58,24 @@ class DeviceWorkload:
 
 
 def upload(wl, device="cuda:0", tap_dtype: int = B.GR_F32, taps: Optional[torch.Tensor] = None,
-           stream=None) -> DeviceWorkload:
+           stream=None, vis_f16=None) -> DeviceWorkload:
+    """vis_f16: optional (halves [N][P][2] float16, scales [ceil(N/256)] float32) encoding of the
+    visibilities to pass instead of complex64."""
     uvw = torch.from_numpy(np.ascontiguousarray(wl.uvw)).to(device)
-    vis = torch.from_numpy(np.ascontiguousarray(wl.vis)).to(device)
+    scale = None
+    if vis_f16 is None:
+        vis = torch.from_numpy(np.ascontiguousarray(wl.vis)).to(device)
+    else:
+        vis = torch.from_numpy(np.ascontiguousarray(vis_f16[0])).to(device)
+        scale = torch.from_numpy(np.ascontiguousarray(vis_f16[1], dtype=np.float32)).to(device)
     w = None if wl.weights is None else torch.from_numpy(np.ascontiguousarray(wl.weights)).to(device)
     if taps is None:
         taps = make_taps(wl, device, tap_dtype, stream)
     k = B.make_kernel(taps, wl.support, wl.oversample, wl.n_planes,
                       taps_complex=(wl.kernel != "kb"), tap_dtype=tap_dtype,
                       w_min=wl.w_min, inv_dw=wl.inv_dw)
-    return DeviceWorkload(wl, uvw, vis, w, taps, k, tap_dtype)
+    return DeviceWorkload(wl, uvw, vis, w, taps, k, tap_dtype,
+                          B.GR_F32 if vis_f16 is None else B.GR_F16, scale)
 
 
 def tuning(cu=0, cv=0, wg_u=0, wg_v=0, vis_per_wg=0, variant=0) -> B.GrTuning:
@@ -83,7 +93,7 @@ def grid(dw: DeviceWorkload, grid_out: Optional[torch.Tensor] = None,
     need = B.gr_grid_workspace_bytes(wl.n_vis, wl.n_pol, dw.kernel, wl.height, wl.width, tune)
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
-    B.gr_grid(dw.uvw, dw.vis, B.GR_F32, None, dw.weights, wl.n_vis, wl.n_pol, dw.kernel,
+    B.gr_grid(dw.uvw, dw.vis, dw.vis_dtype, dw.vis_scale, dw.weights, wl.n_vis, wl.n_pol, dw.kernel,
               wl.inv_cell_u, wl.inv_cell_v, grid_out, wl.height, wl.width, tune, workspace,
               workspace.numel(), stats, stream)
     return grid_out
@@ -95,7 +105,7 @@ def preprocess(dw: DeviceWorkload, stats: Optional[torch.Tensor] = None, stream=
     dev = dw.uvw.device
     rec = torch.empty((max(wl.n_vis, 1), 2), dtype=torch.int32, device=dev)
     wv = torch.empty((max(wl.n_vis, 1), wl.n_pol), dtype=torch.complex64, device=dev)
-    B.gr_preprocess(dw.uvw, dw.vis, B.GR_F32, None, dw.weights, wl.n_vis, wl.n_pol, dw.kernel,
+    B.gr_preprocess(dw.uvw, dw.vis, dw.vis_dtype, dw.vis_scale, dw.weights, wl.n_vis, wl.n_pol, dw.kernel,
                     wl.inv_cell_u, wl.inv_cell_v, wl.height, wl.width, rec, wv, stats, stream)
     return rec, wv
 

@@ -153,6 +153,35 @@ def _full_shape_arrays(seed: int, n_times: int, n_chan: int, n_pol: int, n_ant: 
     return uvw, vis, (uv_max, w_max)
 
 
+def quantize_vis_f16(vis: np.ndarray, block: int = 256):
+    """Input encoding for reduced-precision runs: visibilities as (re, im)
+    float16 pairs with one float32 scale per block of ``block`` consecutive
+    visibilities (all polarisations).  The scale is the block's largest
+    |component| / 2^14, so every scaled value is at most 2^14 in magnitude.
+    Returns (halves [N][P][2] float16, scales [ceil(N / block)] float32)."""
+    v = np.asarray(vis)
+    n = v.shape[0]
+    comp = v.view(np.float32).reshape(n, -1)
+    nb = -(-n // block)
+    pad = nb * block - n
+    mag = np.abs(comp).max(axis=1)
+    if pad:
+        mag = np.concatenate([mag, np.zeros(pad, np.float32)])
+    blk = mag.reshape(nb, block).max(axis=1).astype(np.float32)
+    scale = np.where(blk > 0, blk / np.float32(2 ** 14), np.float32(1.0)).astype(np.float32)
+    per_vis = np.repeat(scale, block)[:n]
+    halves = (comp / per_vis[:, None]).astype(np.float16).reshape(n, v.shape[1], 2)
+    return halves, scale
+
+
+def dequantize_vis_f16(halves: np.ndarray, scale: np.ndarray, block: int = 256) -> np.ndarray:
+    """complex128 values the scaled float16 encoding represents (exact in FP64)."""
+    n = halves.shape[0]
+    per_vis = np.repeat(scale.astype(np.float64), block)[:n]
+    h = halves.astype(np.float64) * per_vis[:, None, None]
+    return h[..., 0] + 1j * h[..., 1]
+
+
 def tiny_kb_workload(seed: int = 0) -> Workload:
     """8 antennas (28 baselines), 1 channel at 1.4 GHz, 256 dumps over 1 h,
     512x512 grid, one polarisation, real Kaiser-Bessel kernel S=8, O=8."""
