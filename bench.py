@@ -91,6 +91,8 @@ def main() -> int:
     ap.add_argument("--precision", choices=["f32", "f16", "bf16"], default="f32",
                     help="storage of taps and visibilities (f16/bf16: taps in that type, "
                          "visibilities as float16 pairs with one float32 scale per 256)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the segment-length sweep on a small subset (library default instead)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this size before timing "
                          "(reference dispatch for HBM byte counters)")
@@ -134,13 +136,29 @@ def main() -> int:
         kern[S] = B.make_kernel(taps[S], S, wl.oversample, wl.n_planes, taps_complex=True,
                                 tap_dtype=tap_dt, w_min=wl.w_min, inv_dw=wl.inv_dw)
         grids[S] = torch.zeros((P, wl.height, wl.width), dtype=torch.complex64, device=dev)
+    variant = args.variant if args.variant in (1, 2) else 2
+    tune = runner.tuning(args.cu, args.cv, vis_per_wg=args.seg_len, variant=variant)
+    seg_len = {S: args.seg_len for S in supports}
+    tuned = {}
+    if variant == 2 and not args.no_autotune and args.seg_len <= 0:
+        # Section 4: tune on a small synthetic data set (the first 128 baselines of
+        # the same geometry), then run the full batch with the winner
+        from paper_1605_07023_amd import autotune
+        for S in supports:
+            small = full_shape_workload(S, n_baselines=128)
+            sdw = runner.upload(small, dev, tap_dtype=tap_dt, taps=taps[S])
+            best, times = autotune.tune(sdw, autotune.candidates(P, S, variants=(2,)), reps=3)
+            seg_len[S] = best.vis_per_wg
+            tuned[str(S)] = {"seg_len": best.vis_per_wg,
+                             "sweep_ms": {str(c.vis_per_wg): round(t, 4) for c, t in
+                                          zip(autotune.candidates(P, S, variants=(2,)), times)}}
+            log(f"autotune S={S}: seg_len {best.vis_per_wg}")
+            del sdw
+        torch.cuda.synchronize()
     rec = torch.empty((N, 2), dtype=torch.int32, device=dev)
     wvis = torch.empty((N, P), dtype=torch.complex64, device=dev)
     stats = torch.zeros(2, dtype=torch.int64, device=dev)
-    variant = args.variant if args.variant in (1, 2) else 2
-    tune = runner.tuning(args.cu, args.cv, vis_per_wg=args.seg_len, variant=variant)
-    seg_len = args.seg_len
-    bins_bytes = max(B.gr_bin_bytes(N, P, S, wls[S].height, wls[S].width, seg_len) for S in supports)
+    bins_bytes = max(B.gr_bin_bytes(N, P, S, wls[S].height, wls[S].width, seg_len[S]) for S in supports)
     bins = torch.empty(bins_bytes, dtype=torch.uint8, device=dev) if variant == 2 else None
     stream = torch.cuda.current_stream(dev)
     ev = {S: [] for S in supports}
@@ -151,12 +169,12 @@ def main() -> int:
             B.gr_preprocess(uvw, vis, vis_dt, vis_scale, None, N, P, kern[S], wl.inv_cell_u,
                             wl.inv_cell_v, wl.height, wl.width, rec, wvis, stats, stream)
             if variant == 2:
-                B.gr_bin(rec, wvis, N, P, S, wl.height, wl.width, seg_len, bins, bins_bytes, stream)
+                B.gr_bin(rec, wvis, N, P, S, wl.height, wl.width, seg_len[S], bins, bins_bytes, stream)
             if record:
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
             if variant == 2:
-                B.gr_grid_binned(bins, N, P, kern[S], seg_len, grids[S], wl.height, wl.width, stream)
+                B.gr_grid_binned(bins, N, P, kern[S], seg_len[S], grids[S], wl.height, wl.width, stream)
             else:
                 B.gr_grid_records(rec, wvis, N, P, kern[S], grids[S], wl.height, wl.width, tune, stream)
             if record:
@@ -240,6 +258,7 @@ def main() -> int:
                    "order": "baseline, time, channel"},
         "pct_fp32_valu_peak": 100.0 * 8 * value / FP32_VALU_PEAK,
         "per_support": per_support,
+        "tuning": tuned or None,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -38,7 +38,7 @@ typedef enum {
 
 typedef enum { GR_F32 = 0, GR_F16 = 1, GR_BF16 = 2, GR_F64 = 3 } gr_dtype;
 
-typedef enum { GR_SEPARABLE = 0, GR_TABLE2D = 1 } gr_kernel_kind;
+typedef enum { GR_SEPARABLE = 0, GR_TABLE2D = 1, GR_MLP = 2 } gr_kernel_kind;
 
 /* Gridding convolution function (GCF) description (Section 2.2: precomputed
  * tables sampled at `oversample` times the grid resolution; Section 4: a
@@ -51,6 +51,12 @@ typedef enum { GR_SEPARABLE = 0, GR_TABLE2D = 1 } gr_kernel_kind;
  * taps (device):
  *   GR_SEPARABLE: [n_planes][O][S] elements, used along u and along v;
  *   GR_TABLE2D:   [n_planes][O][O][S][S] indexed [plane][s_v][s_u][k_v][k_u].
+ *   GR_MLP:       the FP32 weight blob of a learned tap network (see
+ *                 gr_mlp_eval); tap_dtype must be GR_F32 and taps_complex 1.
+ *                 The plane index p of a visibility enters the network as
+ *                 x0 = blob[0] + p * blob[1], so n_planes may be a fine grid
+ *                 in w (up to 32767 planes), and oversample up to 128, at no
+ *                 memory cost.
  * Element type `tap_dtype` (GR_F32, GR_F16 or GR_BF16); complex taps are
  * (re, im) pairs of that type. */
 typedef struct {
@@ -138,7 +144,13 @@ gr_status gr_bin(const void* records, const void* wvis, int64_t n_vis, int32_t n
  * of Section 4, in the factored form G^u_i (G^v_j V_p) of Section 6, is a
  * rank-2 product per pair of visibilities (v_mfma_f32_16x16x4_f32), and the
  * window is added to the grid once with FP32 atomic adds (Section 2.2).
- * support <= 56; the FP32 tap table [planes][O][S] must fit in 160 KiB. */
+ * support <= 56; the FP32 tap table [planes][O][S] must fit in 160 KiB.
+ * With a GR_TABLE2D kernel the non-separable taps are read per visibility
+ * from the [planes][O][O][S][S] table instead: each work-item keeps a 4 x 4
+ * block of the window per polarisation in registers.  With a GR_MLP kernel
+ * the block evaluates each visibility's S x S taps with the network into LDS
+ * first (FP16 matrix-core layers, FP32 accumulation), then updates the window
+ * the same way. */
 gr_status gr_grid_binned(const void* bins, int64_t n_vis, int32_t n_pol, const gr_kernel* kernel,
                          int32_t seg_len, void* grid, int32_t height, int32_t width, void* stream);
 
@@ -155,6 +167,22 @@ gr_status gr_grid(const double* uvw, const void* vis, int32_t vis_dtype, const f
                   double inv_cell_u, double inv_cell_v, void* grid, int32_t height,
                   int32_t width, const gr_tuning* tuning, void* workspace,
                   size_t workspace_bytes, int64_t* dev_stats, void* stream);
+
+/* Autotuning (Section 4: a small data set is benchmarked with a range of
+ * coarsening factors and work-group sizes and the best is remembered).
+ * Times each of n_candidates tunings on preprocessed records/wvis: variant 1
+ * candidates with gr_grid_records, others with gr_bin (into `bins`, sized for
+ * the largest seg_len = vis_per_wg among them) + gr_grid_binned, `reps` times
+ * after one warm-up, accumulating into `grid` (scratch: its contents become
+ * meaningless).  times_ms[c] receives the mean time (+inf when the candidate
+ * is unsupported); *best the fastest index.  Unlike every other entry point
+ * this one SYNCHRONISES `stream` (once per candidate).  The memo of chosen
+ * tunings is kept by the caller. */
+gr_status gr_autotune(const void* records, const void* wvis, int64_t n_vis, int32_t n_pol,
+                      const gr_kernel* kernel, void* grid, int32_t height, int32_t width,
+                      void* bins, size_t bins_bytes, const gr_tuning* candidates,
+                      int32_t n_candidates, int32_t reps, float* times_ms, int32_t* best,
+                      void* stream);
 
 /* Kaiser-Bessel taps (real, one plane), evaluated in FP64 on the device and
  * stored as out_dtype (GR_F64, GR_F32, GR_F16 or GR_BF16), layout [O][S]:
@@ -176,6 +204,72 @@ gr_status gr_make_wkernel_table(int32_t support, int32_t oversample, int32_t n_p
                                 double w_hat_first, double w_hat_step, int32_t support_aa,
                                 double beta, int32_t n_samples, int32_t out_dtype, void* out,
                                 void* stream);
+
+/* Exact (non-paraxial) 2-D W-projection taps (the w term of Section 2.2
+ * without the separable approximation of Section 4), complex, FP64 on the
+ * device, layout [n_planes][O][O][S][S] of (re, im) out_dtype pairs, indexed
+ * [plane][s_v][s_u][k_v][k_u]:
+ *   C(du, dv) = c^2 sum_a sum_b t(nu_a) t(nu_b)
+ *               exp(2 pi i (w_hat / fov^2) (sqrt(1 - fov^2 (nu_a^2 + nu_b^2)) - 1))
+ *               exp(-2 pi i (du nu_a + dv nu_b))
+ * with the taper t, midpoints nu, M = n_samples (<= 0: 4 S) and normaliser c of
+ * gr_make_wkernel_table, fov the field of view in direction cosines
+ * (0 < fov < sqrt 2), and zero where |du| or |dv| >= S/2. */
+gr_status gr_make_wkernel2d_table(int32_t support, int32_t oversample, int32_t n_planes,
+                                  double w_hat_first, double w_hat_step, double fov,
+                                  int32_t support_aa, double beta, int32_t n_samples,
+                                  int32_t out_dtype, void* out, void* stream);
+
+/* ---- Learned tap network (GR_MLP) ------------------------------------------
+ * Replaces the precomputed oversampled table of Section 2.2 by a function of
+ * the table's own coordinates.  Weight blob (device, FP32, gr_mlp_blob_floats()
+ * floats, 16-byte aligned):
+ *   [0] x0 offset, [1] x0 step per plane, [2] out_scale, [3] unused,
+ *   then W1 [64][64], b1 [64], W2 [64][64], b2 [64], W3 [64][64], b3 [64],
+ *   W4 [64][2], b4 [2]  (W stored [in][out], row-major), then padding.
+ * Inputs x (3 per sample): x0 = w_hat / w_hat_range, x1 = d_u / (S/2),
+ *   x2 = d_v / (S/2), where d = k - S/2 + 1 - s/O is the GCF argument of tap
+ *   k at phase s (a tap depends on k and s only through d) and w_hat_range is
+ *   chosen so that |x0| <= 1/2 (the encoding has period 2).
+ * Features e[12 i + 2 k] = sin(pi 2^k x_i), e[12 i + 2 k + 1] = cos(pi 2^k x_i)
+ *   for i < 3, k < 6, e[36..63] = 0;  h1 = relu(e W1 + b1), h2 = relu(h1 W2 + b2),
+ *   h3 = relu(h2 W3 + b3), y = h3 W4 + b4; tap = out_scale * (y0 + i y1),
+ *   and 0 where |d_u| or |d_v| >= S/2 (the support rule of the tables).
+ * The three 64-wide layers run on FP16 matrix cores (inputs rounded to FP16,
+ * FP32 accumulation); the output layer likewise. */
+int32_t gr_mlp_blob_floats(void);
+
+/* out[2 n] (re, im) = tap network at inputs[3 n]; n >= 0; all device pointers. */
+gr_status gr_mlp_eval(const float* weights, const float* inputs, int64_t n, float* out,
+                      void* stream);
+
+/* Training set from a complex FP32 GR_TABLE2D table (gr_make_wkernel2d_table
+ * output): for every entry i of [n_planes][O][O][S][S], inputs[3 i] are its
+ * network inputs with x0 = (w_hat_first + plane * w_hat_step) / w_hat_range,
+ * and targets[2 i] = tap / out_scale.  Device pointers, sized by the caller
+ * (3 and 2 floats per entry). */
+gr_status gr_mlp_dataset(const void* table2d, int32_t support, int32_t oversample,
+                         int32_t n_planes, double w_hat_first, double w_hat_step,
+                         double w_hat_range, float out_scale, float* inputs, float* targets,
+                         void* stream);
+
+/* Gradients of the loss (1/B) sum_b |y(inputs[idx[b]]) - targets[idx[b]]|^2
+ * over the batch b < batch (B = batch) with respect to every parameter of the
+ * blob, written to grads (same layout as the blob; the header floats get 0).
+ * Forward on FP16 matrix cores as in gr_mlp_eval; backward in FP32 on the
+ * rounded activations.  *loss_sum (device, may be NULL) receives the loss.
+ * idx values must index the inputs/targets arrays. */
+gr_status gr_mlp_grads(const float* weights, const float* inputs, const float* targets,
+                       const int32_t* idx, int32_t batch, float* grads, float* loss_sum,
+                       void* stream);
+
+/* One Adam step (Kingma & Ba 2015; beta1 0.9, beta2 0.999, eps 1e-8, step >= 1
+ * counting from 1) on every parameter after gr_mlp_grads; adam_m / adam_v are
+ * zero-initialised device arrays of the blob size kept by the caller; grads is
+ * device scratch of the blob size.  The blob header is not changed. */
+gr_status gr_mlp_train_step(float* weights, float* adam_m, float* adam_v, float* grads,
+                            const float* inputs, const float* targets, const int32_t* idx,
+                            int32_t batch, int32_t step, float lr, float* loss_sum, void* stream);
 
 /* Thread-local description of the last non-OK status ("" if none). */
 const char* gr_last_error(void);

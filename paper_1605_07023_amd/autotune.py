@@ -1,0 +1,160 @@
+"""Autotuning driver and memo (Merry 2016, Section 4: a small artificial data set
+is synthesised and benchmarked with a range of coarsening factors and
+work-group sizes, the best combination is remembered, and tuning is done
+separately per number of polarisations).
+
+The timing sweep runs in the library (gr_autotune); this module builds the
+candidate list, prepares the small data set on the device, and keeps the memo
+of chosen tunings as JSON.  The memo key is
+(device name, n_pol, support, tap kind, tap dtype, grid side class, variant
+set).  A missing or unreadable memo falls back to the library defaults.
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+from typing import Dict, Iterable, List, Optional, Tuple
+
+import torch
+
+from . import binding as B
+from . import runner
+
+DEFAULT_MEMO = os.environ.get(
+    "GR_TUNE_MEMO", os.path.join(os.path.expanduser("~"), ".cache", "paper_1605_07023_amd", "tuning.json"))
+
+SEG_LENS = (512, 1024, 2048, 4096, 8192, 16384)
+COARSEN = (1, 2, 4, 8)
+
+
+def candidates(n_pol: int, support: int, variants: Iterable[int] = (1, 2),
+               vis_per_wg: Iterable[int] = (1024,)) -> List[B.GrTuning]:
+    """Work decompositions to try.
+
+    variant 1 (work-item kernel): coarsening cu x cv in {1, 2, 4, 8}^2 (the
+    paper's range) with cu * cv * n_pol <= 64 (register budget), default tile
+    shape, the given visibilities per work-group.  variant 2 (MFMA kernel):
+    segment lengths SEG_LENS."""
+    out = []
+    if 1 in variants:
+        for cu in COARSEN:
+            for cv in COARSEN:
+                if cu * cv * n_pol > 64:
+                    continue
+                for vpw in vis_per_wg:
+                    out.append(B.GrTuning(cu, cv, 0, 0, vpw, 1))
+    if 2 in variants and support <= 56:
+        for sl in SEG_LENS:
+            out.append(B.GrTuning(0, 0, 0, 0, sl, 2))
+    return out
+
+
+def memo_key(device_name: str, n_pol: int, support: int, kind: str, tap_dtype: int, side: int,
+             variants: Iterable[int]) -> str:
+    side_class = 1 << max(0, (int(side) - 1).bit_length())
+    return f"{device_name}|P{n_pol}|S{support}|{kind}|t{tap_dtype}|g{side_class}|v{''.join(map(str, sorted(variants)))}"
+
+
+class Memo:
+    """JSON memo of chosen tunings; unreadable files are ignored (defaults apply)."""
+
+    def __init__(self, path: str = DEFAULT_MEMO):
+        self.path = path
+        self.data: Dict[str, dict] = {}
+        try:
+            with open(path) as fh:
+                raw = json.load(fh)
+            if isinstance(raw, dict):
+                self.data = {k: v for k, v in raw.items() if isinstance(v, dict) and "tuning" in v}
+        except FileNotFoundError:
+            pass
+        except (OSError, ValueError) as e:
+            print(f"[autotune] ignoring unreadable memo {path}: {e}", file=sys.stderr)
+
+    def get(self, key: str) -> Optional[B.GrTuning]:
+        e = self.data.get(key)
+        if e is None:
+            return None
+        try:
+            t = [int(x) for x in e["tuning"]]
+            if len(t) != 6:
+                return None
+            return B.GrTuning(*t)
+        except (TypeError, ValueError):
+            return None
+
+    def put(self, key: str, tuning: B.GrTuning, time_ms: float) -> None:
+        self.data[key] = {"tuning": [tuning.cu, tuning.cv, tuning.wg_u, tuning.wg_v,
+                                     tuning.vis_per_wg, tuning.variant], "time_ms": time_ms}
+
+    def save(self) -> None:
+        d = os.path.dirname(self.path)
+        if d:
+            os.makedirs(d, exist_ok=True)
+        tmp = self.path + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(self.data, fh, indent=1, sort_keys=True)
+        os.replace(tmp, self.path)
+
+
+def tune(dw: runner.DeviceWorkload, cands: List[B.GrTuning], reps: int = 3,
+         stream=None) -> Tuple[B.GrTuning, List[float]]:
+    """Time every candidate on a device workload; returns (best, times in ms)."""
+    wl = dw.wl
+    dev = dw.uvw.device
+    rec, wv = runner.preprocess(dw, stream=stream)
+    grid = torch.zeros((wl.n_pol, wl.height, wl.width), dtype=torch.complex64, device=dev)
+    seg = [c.vis_per_wg for c in cands if c.variant != 1] or [0]
+    nb = max(B.gr_bin_bytes(wl.n_vis, wl.n_pol, wl.support, wl.height, wl.width, s) for s in seg) \
+        if wl.support <= 56 else 0
+    bins = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+    best, times = B.gr_autotune(rec, wv, wl.n_vis, wl.n_pol, dw.kernel, grid, wl.height, wl.width,
+                                bins, bins.numel(), cands, reps, stream)
+    return cands[best], times
+
+
+def tune_and_remember(dw: runner.DeviceWorkload, variants: Iterable[int] = (2,), reps: int = 3,
+                      memo: Optional[Memo] = None, vis_per_wg: Iterable[int] = (1024,)) -> B.GrTuning:
+    """Tune on the given (small) workload and store the winner in the memo."""
+    wl = dw.wl
+    memo = memo if memo is not None else Memo()
+    cands = candidates(wl.n_pol, wl.support, variants, vis_per_wg)
+    best, times = tune(dw, cands, reps)
+    name = torch.cuda.get_device_name(dw.uvw.device)
+    key = memo_key(name, wl.n_pol, wl.support, wl.kernel, dw.tap_dtype, max(wl.height, wl.width), variants)
+    memo.put(key, best, min(times))
+    return best
+
+
+def tuning_for(device_name: str, n_pol: int, support: int, kind: str, tap_dtype: int, side: int,
+               variants: Iterable[int] = (2,), memo: Optional[Memo] = None) -> Optional[B.GrTuning]:
+    memo = memo if memo is not None else Memo()
+    return memo.get(memo_key(device_name, n_pol, support, kind, tap_dtype, side, variants))
+
+
+def main(argv=None) -> int:
+    """Tune the full-shape geometry (first baselines only) for S = 16 and 32 and
+    the tiny Kaiser-Bessel configuration; write the memo."""
+    import argparse
+    from synth import full_shape_workload, tiny_kb_workload
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--baselines", type=int, default=128)
+    ap.add_argument("--variants", default="1,2")
+    ap.add_argument("--memo", default=DEFAULT_MEMO)
+    args = ap.parse_args(argv)
+    variants = tuple(int(v) for v in args.variants.split(","))
+    memo = Memo(args.memo)
+    dev = torch.device("cuda:0")
+    for wl in [full_shape_workload(16, n_baselines=args.baselines),
+               full_shape_workload(32, n_baselines=args.baselines), tiny_kb_workload()]:
+        dw = runner.upload(wl, dev)
+        best = tune_and_remember(dw, variants, memo=memo)
+        print(f"{wl.name}: best {best.cu}x{best.cv} wg {best.wg_u}x{best.wg_v} "
+              f"vis/wg {best.vis_per_wg} variant {best.variant}", flush=True)
+    memo.save()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

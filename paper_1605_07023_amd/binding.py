@@ -18,7 +18,7 @@ _lib = None
 
 GR_OK, GR_EINVAL, GR_ENOMEM, GR_EDEVICE, GR_EUNSUPPORTED = 0, -1, -2, -3, -4
 GR_F32, GR_F16, GR_BF16, GR_F64 = 0, 1, 2, 3
-GR_SEPARABLE, GR_TABLE2D = 0, 1
+GR_SEPARABLE, GR_TABLE2D, GR_MLP = 0, 1, 2
 _STATUS = {GR_EINVAL: "EINVAL", GR_ENOMEM: "ENOMEM", GR_EDEVICE: "EDEVICE", GR_EUNSUPPORTED: "EUNSUPPORTED"}
 
 
@@ -65,6 +65,12 @@ def load_library():
         "gr_make_wkernel_table": [I32, I32, I32, D, D, I32, D, I32, I32, P, P],
         "gr_bin": [P, P, I64, I32, I32, I32, I32, I32, P, SZ, P],
         "gr_grid_binned": [P, I64, I32, KP, I32, P, I32, I32, P],
+        "gr_autotune": [P, P, I64, I32, KP, P, I32, I32, P, SZ, TP, I32, I32, P, P, P],
+        "gr_make_wkernel2d_table": [I32, I32, I32, D, D, D, I32, D, I32, I32, P, P],
+        "gr_mlp_eval": [P, P, I64, P, P],
+        "gr_mlp_dataset": [P, I32, I32, I32, D, D, D, ctypes.c_float, P, P, P],
+        "gr_mlp_grads": [P, P, P, P, I32, P, P, P],
+        "gr_mlp_train_step": [P, P, P, P, P, P, P, I32, I32, ctypes.c_float, P, P],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -76,6 +82,8 @@ def load_library():
     lib.gr_bin_bytes.restype = SZ
     lib.gr_last_error.argtypes = []
     lib.gr_last_error.restype = ctypes.c_char_p
+    lib.gr_mlp_blob_floats.argtypes = []
+    lib.gr_mlp_blob_floats.restype = I32
     lib.gr_version.argtypes = []
     lib.gr_version.restype = I32
     _lib = lib
@@ -179,3 +187,52 @@ def gr_make_wkernel_table(support, oversample, n_planes, w_hat_first, w_hat_step
     _check(load_library().gr_make_wkernel_table(support, oversample, n_planes, w_hat_first,
                                                 w_hat_step, support_aa, beta, n_samples,
                                                 out_dtype, _ptr(out), _stream(stream, out)))
+
+
+def gr_autotune(records, wvis, n_vis, n_pol, kernel: GrKernel, grid, height, width, bins,
+                bins_bytes, candidates, reps: int = 3, stream=None):
+    """Returns (best index, list of mean times in ms; inf for unsupported candidates)."""
+    n = len(candidates)
+    arr = (GrTuning * n)(*candidates)
+    times = (ctypes.c_float * n)()
+    best = ctypes.c_int32(-1)
+    _check(load_library().gr_autotune(_ptr(records), _ptr(wvis), n_vis, n_pol, ctypes.byref(kernel),
+                                      _ptr(grid), height, width, _ptr(bins), bins_bytes, arr, n, reps,
+                                      ctypes.cast(times, ctypes.c_void_p),
+                                      ctypes.cast(ctypes.pointer(best), ctypes.c_void_p),
+                                      _stream(stream, grid)))
+    return int(best.value), [float(t) for t in times]
+
+
+def gr_make_wkernel2d_table(support, oversample, n_planes, w_hat_first, w_hat_step, fov, support_aa,
+                            beta, n_samples, out_dtype, out, stream=None):
+    _check(load_library().gr_make_wkernel2d_table(support, oversample, n_planes, w_hat_first,
+                                                  w_hat_step, fov, support_aa, beta, n_samples,
+                                                  out_dtype, _ptr(out), _stream(stream, out)))
+
+
+def gr_mlp_blob_floats() -> int:
+    return int(load_library().gr_mlp_blob_floats())
+
+
+def gr_mlp_eval(weights, inputs, n, out, stream=None):
+    _check(load_library().gr_mlp_eval(_ptr(weights), _ptr(inputs), n, _ptr(out), _stream(stream, out)))
+
+
+def gr_mlp_dataset(table2d, support, oversample, n_planes, w_hat_first, w_hat_step, w_hat_max,
+                   out_scale, inputs, targets, stream=None):
+    _check(load_library().gr_mlp_dataset(_ptr(table2d), support, oversample, n_planes, w_hat_first,
+                                         w_hat_step, w_hat_max, out_scale, _ptr(inputs),
+                                         _ptr(targets), _stream(stream, inputs)))
+
+
+def gr_mlp_grads(weights, inputs, targets, idx, batch, grads, loss_sum, stream=None):
+    _check(load_library().gr_mlp_grads(_ptr(weights), _ptr(inputs), _ptr(targets), _ptr(idx), batch,
+                                       _ptr(grads), _ptr(loss_sum), _stream(stream, grads)))
+
+
+def gr_mlp_train_step(weights, adam_m, adam_v, grads, inputs, targets, idx, batch, step, lr,
+                      loss_sum, stream=None):
+    _check(load_library().gr_mlp_train_step(_ptr(weights), _ptr(adam_m), _ptr(adam_v), _ptr(grads),
+                                            _ptr(inputs), _ptr(targets), _ptr(idx), batch, step, lr,
+                                            _ptr(loss_sum), _stream(stream, weights)))

@@ -28,7 +28,12 @@ gr_status check_launch(const char* what) {
 
 gr_status validate_kernel(const gr_kernel* k, bool need_taps) {
   if (k == nullptr) return fail(GR_EINVAL, "kernel descriptor is NULL");
-  if (k->kind != GR_SEPARABLE) return fail(GR_EUNSUPPORTED, "only GR_SEPARABLE kernels are supported");
+  if (k->kind != GR_SEPARABLE && k->kind != GR_TABLE2D && k->kind != GR_MLP)
+    return fail(GR_EUNSUPPORTED, "kernel.kind must be GR_SEPARABLE, GR_TABLE2D or GR_MLP");
+  if (k->kind == GR_TABLE2D && !k->taps_complex)
+    return fail(GR_EUNSUPPORTED, "GR_TABLE2D kernels must have complex taps");
+  if (k->kind == GR_MLP && (!k->taps_complex || k->tap_dtype != GR_F32))
+    return fail(GR_EUNSUPPORTED, "GR_MLP kernels are complex with an FP32 weight blob");
   if (k->support < 2 || k->support > 64 || (k->support & 1))
     return fail(GR_EINVAL, "kernel.support must be even, 2..64");
   if (!pow2(k->oversample) || k->oversample > kMaxOversample)
@@ -69,6 +74,7 @@ int seg_len_of(const gr_tuning* t) { return t && t->vis_per_wg > 0 ? t->vis_per_
 // variant actually used by gr_grid: 1 = VALU work-item kernel on the input order,
 // 2 = MFMA kernel on the binned stream
 int pick_variant(const gr_kernel& k, int n_pol, const gr_tuning* t) {
+  if (k.kind != GR_SEPARABLE) return 2;        // only the binned path handles other kinds
   const int want = t ? t->variant : 0;
   if (want == 1 || want == 2) return want;
   size_t lds;
@@ -83,6 +89,16 @@ size_t pre_bytes(int64_t n_vis, int n_pol) {
 }
 
 }  // namespace
+
+namespace gr {
+// binned gridder for the kernel's kind
+gr_status launch_binned(const void* bins, const BinLayout& L, int n_pol, const gr_kernel& k,
+                        float2* grid, int height, int width, hipStream_t stream) {
+  if (k.kind == GR_TABLE2D) return launch_table2d(bins, L, n_pol, k, grid, height, width, stream);
+  if (k.kind == GR_MLP) return launch_grid_mlp(bins, L, n_pol, k, grid, height, width, stream);
+  return launch_mfma(bins, L, n_pol, k, grid, height, width, stream);
+}
+}  // namespace gr
 
 extern "C" size_t gr_bin_bytes(int64_t n_vis, int32_t n_pol, int32_t support, int32_t height,
                                int32_t width, int32_t seg_len) {
@@ -134,6 +150,8 @@ extern "C" gr_status gr_grid_records(const void* records, const void* wvis, int6
     return fail(GR_EINVAL, "records and wvis must be non-NULL");
   if (tuning && tuning->variant != 0 && tuning->variant != 1)
     return fail(GR_EUNSUPPORTED, "gr_grid_records runs the VALU work-item kernel (variant 0 or 1)");
+  if (kernel->kind != GR_SEPARABLE)
+    return fail(GR_EUNSUPPORTED, "gr_grid_records needs a separable kernel");
   RomeinPlan plan;
   if ((st = plan_romein(*kernel, n_pol, tuning, &plan)) != GR_OK) return st;
   return launch_romein(reinterpret_cast<const Record*>(records), reinterpret_cast<const float2*>(wvis),
@@ -164,12 +182,10 @@ extern "C" gr_status gr_grid_binned(const void* bins, int64_t n_vis, int32_t n_p
   if ((st = validate_grid(n_pol, height, width, kernel->support)) != GR_OK) return st;
   if (n_vis < 0 || n_vis > 0x7fffffffLL) return fail(GR_EINVAL, "n_vis must be in [0, 2^31)");
   if (grid == nullptr || bins == nullptr) return fail(GR_EINVAL, "grid and bins must be non-NULL");
-  size_t lds;
-  if ((st = plan_mfma(*kernel, n_pol, &lds)) != GR_OK) return st;
   const BinLayout L = bin_layout(n_vis, n_pol, kernel->support, height, width,
                                  seg_len > 0 ? seg_len : kDefaultSegLen);
-  return launch_mfma(bins, L, n_pol, *kernel, reinterpret_cast<float2*>(grid), height, width,
-                     (hipStream_t)stream);
+  return launch_binned(bins, L, n_pol, *kernel, reinterpret_cast<float2*>(grid), height, width,
+                       (hipStream_t)stream);
 }
 
 extern "C" gr_status gr_grid(const double* uvw, const void* vis, int32_t vis_dtype,
@@ -193,8 +209,9 @@ extern "C" gr_status gr_grid(const double* uvw, const void* vis, int32_t vis_dty
   size_t lds;
   if (variant == 1 && (st = plan_romein(*kernel, n_pol, tuning, &plan)) != GR_OK) return st;
   if (variant == 2) {
-    if ((st = plan_mfma(*kernel, n_pol, &lds)) != GR_OK) return st;
-    if (n_vis > 0x7fffffffLL) return fail(GR_EINVAL, "n_vis must be < 2^31 for the MFMA gridder");
+    if (kernel->kind == GR_SEPARABLE && (st = plan_mfma(*kernel, n_pol, &lds)) != GR_OK) return st;
+    if (kernel->support > 56) return fail(GR_EUNSUPPORTED, "the binned gridders need support <= 56");
+    if (n_vis > 0x7fffffffLL) return fail(GR_EINVAL, "n_vis must be < 2^31 for the binned gridders");
   }
   auto* rec = reinterpret_cast<Record*>(workspace);
   auto* wv = reinterpret_cast<float2*>(reinterpret_cast<char*>(workspace) +
@@ -208,6 +225,6 @@ extern "C" gr_status gr_grid(const double* uvw, const void* vis, int32_t vis_dty
   void* bins = reinterpret_cast<char*>(workspace) + pre_bytes(n_vis, n_pol);
   const BinLayout L = bin_layout(n_vis, n_pol, kernel->support, height, width, seg_len_of(tuning));
   if ((st = launch_bin(rec, wv, n_vis, n_pol, L, bins, (hipStream_t)stream)) != GR_OK) return st;
-  return launch_mfma(bins, L, n_pol, *kernel, reinterpret_cast<float2*>(grid), height, width,
-                     (hipStream_t)stream);
+  return launch_binned(bins, L, n_pol, *kernel, reinterpret_cast<float2*>(grid), height, width,
+                       (hipStream_t)stream);
 }

@@ -76,6 +76,14 @@ gr_status plan_mfma(const gr_kernel& k, int n_pol, size_t* lds_bytes);
 gr_status launch_mfma(const void* bins, const BinLayout& L, int n_pol, const gr_kernel& k,
                       float2* grid, int height, int width, hipStream_t stream);
 
+// Non-separable table gridder over the binned stream (grid_table2d.hip).
+gr_status launch_table2d(const void* bins, const BinLayout& L, int n_pol, const gr_kernel& k,
+                         float2* grid, int height, int width, hipStream_t stream);
+
+// Learned-tap (network) gridder over the binned stream (mlp.hip).
+gr_status launch_grid_mlp(const void* bins, const BinLayout& L, int n_pol, const gr_kernel& k,
+                          float2* grid, int height, int width, hipStream_t stream);
+
 constexpr int kDefaultSegLen = 4096;
 size_t align256(size_t v);
 

@@ -117,6 +117,89 @@ wkernel_table_kernel(int S, int O, int n_planes, double wh0, double whs, int aa,
   }
 }
 
+// Exact (non-paraxial) 2-D W kernel, one block per (plane, s_v, k_v):
+//   C(du, dv) = c^2 sum_a sum_b t(nu_a) t(nu_b) exp(2 pi i (w_hat / fov^2)
+//               (sqrt(1 - fov^2 (nu_a^2 + nu_b^2)) - 1)) exp(-2 pi i (du nu_a + dv nu_b)),
+// zero where |du| or |dv| >= S/2, computed as a row-column transform:
+// first half[a] = sum_b exp(-2 pi i dv nu_b) screen(b, a) for this block's dv,
+// then every (s_u, k_u) output of the block sums over a.
+// Output [plane][s_v][s_u][k_v][k_u] of (re, im).  Dynamic LDS: 4 M doubles + 256.
+__global__ void __launch_bounds__(256)
+wkernel2d_table_kernel(int S, int O, double wh0, double whs, double fov, int aa, double beta, int M,
+                       int dtype, void* out) {
+  extern __shared__ double sh2[];
+  double* taper = sh2;              // [M]
+  double* hre = sh2 + M;            // [M]
+  double* him = sh2 + 2 * M;        // [M]
+  double* red = sh2 + 3 * M;        // [256]
+  const int blk = blockIdx.x;       // (plane * O + s_v) * S + k_v
+  const int kv = blk % S, sv = (blk / S) % O, plane = blk / (S * O);
+  for (int j = threadIdx.x; j < M; j += blockDim.x) {
+    const double nu = ((double)j + 0.5) / (double)M - 0.5;
+    taper[j] = kb_taper(nu, aa, beta);
+  }
+  __syncthreads();
+  double part = 0.0;                // 1-D normalisation, as in the separable table
+  for (int q = threadIdx.x; q < S * M; q += blockDim.x) {
+    const int k = q / M, j = q % M;
+    const double d = (double)(k - S / 2 + 1);
+    if (fabs(d) < 0.5 * S) {
+      const double nu = ((double)j + 0.5) / (double)M - 0.5;
+      part += taper[j] * cospi(2.0 * d * nu);
+    }
+  }
+  red[threadIdx.x] = part;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double c = 1.0 / red[0];
+  const double wh = wh0 + (double)plane * whs;
+  const double dv = (double)(kv - S / 2 + 1) - (double)sv / (double)O;
+  const bool vin = fabs(dv) < 0.5 * S;
+  for (int a = threadIdx.x; a < M; a += blockDim.x) {
+    double re = 0.0, im = 0.0;
+    if (vin) {
+      const double nua = ((double)a + 0.5) / (double)M - 0.5;
+      for (int b = 0; b < M; ++b) {
+        const double nub = ((double)b + 0.5) / (double)M - 0.5;
+        const double rho2 = nua * nua + nub * nub;
+        // screen phase (turns) minus the dv term
+        const double ph = (wh / (fov * fov)) * (sqrt(1.0 - fov * fov * rho2) - 1.0) - dv * nub;
+        double sn, cs;
+        sincospi(2.0 * ph, &sn, &cs);
+        const double amp = taper[a] * taper[b];
+        re += amp * cs;
+        im += amp * sn;
+      }
+    }
+    hre[a] = re;
+    him[a] = im;
+  }
+  __syncthreads();
+  const double c2 = c * c;
+  for (int q = threadIdx.x; q < O * S; q += blockDim.x) {
+    const int su = q / S, ku = q % S;
+    const double du = (double)(ku - S / 2 + 1) - (double)su / (double)O;
+    double re = 0.0, im = 0.0;
+    if (vin && fabs(du) < 0.5 * S) {
+      for (int a = 0; a < M; ++a) {
+        const double nua = ((double)a + 0.5) / (double)M - 0.5;
+        double sn, cs;
+        sincospi(-2.0 * du * nua, &sn, &cs);
+        re += hre[a] * cs - him[a] * sn;
+        im += hre[a] * sn + him[a] * cs;
+      }
+      re *= c2;
+      im *= c2;
+    }
+    const int64_t idx = ((((int64_t)plane * O + sv) * O + su) * S + kv) * S + ku;
+    store_elem(out, 2 * idx, dtype, re);
+    store_elem(out, 2 * idx + 1, dtype, im);
+  }
+}
+
 bool dtype_ok(int d) { return d == GR_F64 || d == GR_F32 || d == GR_F16 || d == GR_BF16; }
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
@@ -163,4 +246,32 @@ extern "C" gr_status gr_make_wkernel_table(int32_t support, int32_t oversample, 
   wkernel_table_kernel<<<n_planes * oversample, 256, lds, (hipStream_t)stream>>>(
       support, oversample, n_planes, w_hat_first, w_hat_step, support_aa, beta, M, out_dtype, out);
   return check_launch("gr_make_wkernel_table");
+}
+
+extern "C" gr_status gr_make_wkernel2d_table(int32_t support, int32_t oversample, int32_t n_planes,
+                                             double w_hat_first, double w_hat_step, double fov,
+                                             int32_t support_aa, double beta, int32_t n_samples,
+                                             int32_t out_dtype, void* out, void* stream) {
+  if (out == nullptr) return fail(GR_EINVAL, "gr_make_wkernel2d_table: out is NULL");
+  if (support < 2 || support > 64 || (support & 1))
+    return fail(GR_EINVAL, "gr_make_wkernel2d_table: support must be even, 2..64");
+  if (!pow2(oversample) || oversample > kMaxOversample)
+    return fail(GR_EINVAL, "gr_make_wkernel2d_table: oversample must be a power of two <= 128");
+  if (n_planes < 1 || n_planes > kMaxPlanes)
+    return fail(GR_EINVAL, "gr_make_wkernel2d_table: n_planes out of range");
+  if (support_aa < 1 || support_aa > support)
+    return fail(GR_EINVAL, "gr_make_wkernel2d_table: support_aa must be in 1..support");
+  if (!std::isfinite(w_hat_first) || !std::isfinite(w_hat_step) || !std::isfinite(beta) || beta < 0.0)
+    return fail(GR_EINVAL, "gr_make_wkernel2d_table: non-finite parameter");
+  if (!(fov > 0.0) || !(fov < 1.4142))
+    return fail(GR_EINVAL, "gr_make_wkernel2d_table: fov must be in (0, sqrt 2)");
+  if (!dtype_ok(out_dtype)) return fail(GR_EINVAL, "gr_make_wkernel2d_table: bad out_dtype");
+  const int M = n_samples > 0 ? n_samples : 4 * support;
+  if (M > 2048) return fail(GR_EINVAL, "gr_make_wkernel2d_table: n_samples must be <= 2048");
+  const int64_t blocks = (int64_t)n_planes * oversample * support;
+  if (blocks > 0x7fffffff) return fail(GR_EINVAL, "gr_make_wkernel2d_table: table too large");
+  const size_t lds = sizeof(double) * (size_t)(3 * M + 256);
+  wkernel2d_table_kernel<<<(unsigned)blocks, 256, lds, (hipStream_t)stream>>>(
+      support, oversample, w_hat_first, w_hat_step, fov, support_aa, beta, M, out_dtype, out);
+  return check_launch("gr_make_wkernel2d_table");
 }

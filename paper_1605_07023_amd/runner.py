@@ -31,6 +31,12 @@ def make_taps(wl, device, tap_dtype: int = B.GR_F32, stream=None) -> torch.Tenso
         step = (whs[1] - whs[0]) if wl.n_planes > 1 else 0.0
         B.gr_make_wkernel_table(S, O, wl.n_planes, float(whs[0]), float(step), wl.support_aa,
                                 wl.beta, 0, tap_dtype, out, stream)
+    elif wl.kernel == "w2d":
+        out = torch.empty((wl.n_planes, O, O, S, S, 2), dtype=dt, device=device)
+        whs = wl.plane_w_hat()
+        step = (whs[1] - whs[0]) if wl.n_planes > 1 else 0.0
+        B.gr_make_wkernel2d_table(S, O, wl.n_planes, float(whs[0]), float(step), wl.fov,
+                                  wl.support_aa, wl.beta, 0, tap_dtype, out, stream)
     else:
         raise ValueError(f"unknown kernel kind {wl.kernel}")
     return out
@@ -73,7 +79,8 @@ def upload(wl, device="cuda:0", tap_dtype: int = B.GR_F32, taps: Optional[torch.
         taps = make_taps(wl, device, tap_dtype, stream)
     k = B.make_kernel(taps, wl.support, wl.oversample, wl.n_planes,
                       taps_complex=(wl.kernel != "kb"), tap_dtype=tap_dtype,
-                      w_min=wl.w_min, inv_dw=wl.inv_dw)
+                      w_min=wl.w_min, inv_dw=wl.inv_dw,
+                      kind=B.GR_TABLE2D if wl.kernel == "w2d" else B.GR_SEPARABLE)
     return DeviceWorkload(wl, uvw, vis, w, taps, k, tap_dtype,
                           B.GR_F32 if vis_f16 is None else B.GR_F16, scale)
 

@@ -91,7 +91,9 @@ class Workload:
     w_hat_scale: float = 0.0        # w (wavelengths) -> w in pixel units for the W kernel
     beta: float = 8.6               # Kaiser-Bessel shape
     support_aa: int = 8             # anti-aliasing kernel width inside the W kernel
-    kernel: str = "kb"              # "kb" (real separable) or "wsep" (complex separable W)
+    kernel: str = "kb"              # "kb" (real separable), "wsep" (complex separable W),
+                                    # "w2d" (exact 2-D W)
+    fov: float = 0.0                # field of view (direction cosines) of the exact 2-D W kernel
     meta: dict = dataclasses.field(default_factory=dict)
 
     @property
@@ -284,4 +286,16 @@ def random_point_workload(n_vis: int, n_pol: int, height: int, width: int, suppo
         w_min, inv_dw, whs = 0.0, 0.0, 0.0
     return Workload(f"points-{n_vis}", uvw, vis, wts, height, width, support, oversample,
                     inv_cell, inv_cell, n_planes=n_planes, w_min=w_min, inv_dw=inv_dw,
-                    w_hat_scale=whs, kernel=kernel)
+                    w_hat_scale=whs, kernel=kernel, fov=0.5 if kernel == "w2d" else 0.0)
+
+
+def learned_kernel_workload(seed: int = 0, n_baselines: Optional[int] = None,
+                            fov: float = 0.5) -> Workload:
+    """The full-shape visibilities with the exact (non-separable) 2-D W kernel:
+    support 32, 64 w-planes, oversampling 8 on both axes (a 33.5 MB complex64
+    table), field of view ``fov`` direction cosines."""
+    wl = full_shape_workload(32, seed=seed, n_baselines=n_baselines, n_planes=64)
+    wl.name = "learned-w2d-S32"
+    wl.kernel = "w2d"
+    wl.fov = fov
+    return wl

@@ -60,7 +60,7 @@ def _kernel(**kw):
     (dict(support=7), "support"), (dict(support=0), "support"), (dict(support=66), "support"),
     (dict(oversample=6), "oversample"), (dict(oversample=256), "oversample"),
     (dict(n_planes=0), "n_planes"), (dict(tap_dtype=9), "tap_dtype"),
-    (dict(taps=None), "taps"), (dict(kind=1), "SEPARABLE"),
+    (dict(taps=None), "taps"), (dict(kind=1), "separable"), (dict(kind=5), "kernel.kind"),
     (dict(w_min=float("nan")), "w_min"),
 ])
 def test_grid_records_rejects_bad_kernel(lib, bad, msg):

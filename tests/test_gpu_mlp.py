@@ -1,0 +1,218 @@
+"""GPU tests of the learned tap network (GR_MLP) through the C ABI.
+
+Bars (FP16 matrix-core layers, FP32 accumulation; derived from FP16's unit
+round-off 2^-11 ~ 4.9e-4 per rounding of features, weights and each layer's
+activations, compounded over four layers):
+  * forward taps vs the FP64 forward of the same weights: relative L2 <= 1e-2;
+  * gradients vs the FP64 backward on the same samples: relative L2 <= 2e-2
+    per tensor;
+  * Adam vs the FP64 update on the same gradients: 1e-5 relative plus the
+    FP32 storage rounding of the weights (6e-8 absolute);
+  * fused gridding vs the FP64 table gridder fed the FP64 network taps:
+    relative L2 <= 1e-2.
+The training trajectory itself is parity unpinned: only the tap and grid
+errors it reaches are checked.
+"""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import mlp as M  # noqa: E402
+from synth import random_point_workload  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def T():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1605_07023_amd import binding, tapnet
+    binding.load_library()
+    return tapnet
+
+
+def _rel(got, ref):
+    return float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+def _params(seed):
+    p = M.init_params(seed)
+    rng = np.random.default_rng(seed + 100)
+    for k in ("b1", "b2", "b3", "b4"):
+        p[k] = rng.uniform(-0.2, 0.2, p[k].shape)
+    return p
+
+
+def _inputs(n, seed, spill=1.1):
+    rng = np.random.default_rng(seed)
+    return np.stack([rng.uniform(-0.5, 0.5, n), rng.uniform(-spill, spill, n),
+                     rng.uniform(-spill, spill, n)], axis=1)
+
+
+@pytest.mark.parametrize("n", [1, 1000, 4099])
+def test_mlp_eval_matches_oracle(T, n):
+    _say(f"mlp eval n={n}")
+    p = _params(1)
+    net = T.TapNet(DEV, params=p)
+    net.set_header(0.0, 0.0, 1.7)
+    x = _inputs(n, 2)
+    got = net.eval(torch.from_numpy(x.astype(np.float32)).to(DEV)).cpu().numpy().astype(np.float64)
+    ref = M.taps(p, 1.7, x.astype(np.float32).astype(np.float64), 8)
+    got_c = got[:, 0] + 1j * got[:, 1]
+    assert np.all(got_c[ref == 0] == 0)               # the support rule is exact
+    err = _rel(got_c, ref)
+    _say(f"  rel L2 {err:.2e}")
+    assert err <= 1e-2
+
+
+def test_mlp_eval_empty_and_errors(T):
+    from paper_1605_07023_amd import binding as B
+    net = T.TapNet(DEV, seed=0)
+    out = torch.empty((1, 2), dtype=torch.float32, device=DEV)
+    B.gr_mlp_eval(net.blob, None, 0, None)            # n = 0: nothing to do
+    with pytest.raises(B.GridderError):
+        B.gr_mlp_eval(net.blob, None, 4, out)
+    with pytest.raises(B.GridderError):
+        B.gr_mlp_eval(net.blob, out, -1, out)
+
+
+def test_mlp_grads_match_oracle(T):
+    _say("mlp grads batch 200 of 1000")
+    p = _params(4)
+    net = T.TapNet(DEV, params=p)
+    x = _inputs(1000, 5, spill=0.95).astype(np.float32)
+    t = np.random.default_rng(6).uniform(-1, 1, (1000, 2)).astype(np.float32)
+    idx = np.random.default_rng(7).permutation(1000)[:200].astype(np.int32)
+    xd, td, idd = (torch.from_numpy(a).to(DEV) for a in (x, t, idx))
+    g = net.grads_of(xd, td, idd, 200).cpu().numpy().astype(np.float64)
+    loss_gpu = float(net.loss_buf.item())
+    xs = x[idx].astype(np.float64)
+    y, cache = M.forward(p, M.encode(xs))
+    ref = M.backward(p, cache, y, t[idx].astype(np.float64))
+    got = T.blob_to_params(g)
+    for k in ref:
+        err = _rel(got[k], ref[k])
+        _say(f"  {k}: rel L2 {err:.2e}")
+        assert err <= 2e-2, k
+    assert np.all(g[:4] == 0)
+    assert abs(loss_gpu - M.loss(y, t[idx])) <= 1e-2 * M.loss(y, t[idx])
+
+
+def test_adam_matches_oracle(T):
+    _say("mlp adam two steps")
+    from paper_1605_07023_amd import binding as B
+    p = _params(8)
+    net = T.TapNet(DEV, params=p)
+    net.set_header(0.25, 0.5, 2.0)
+    x = _inputs(256, 9, spill=0.9).astype(np.float32)
+    t = np.random.default_rng(10).uniform(-1, 1, (256, 2)).astype(np.float32)
+    idx = np.arange(256, dtype=np.int32)
+    xd, td, idd = (torch.from_numpy(a).to(DEV) for a in (x, t, idx))
+    cur = {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
+    m = {k: np.zeros_like(v) for k, v in cur.items()}
+    v = {k: np.zeros_like(vv) for k, vv in cur.items()}
+    for step, lr in ((1, 1e-2), (2, 5e-3)):
+        B.gr_mlp_train_step(net.blob, net.m, net.v, net.grads, xd, td, idd, 256, step, lr, net.loss_buf)
+        g = T.blob_to_params(net.grads.cpu().numpy())
+        M.adam_step(cur, g, m, v, step, lr)
+        got = net.params()
+        for k in cur:
+            # the blob stores FP32: half an ulp of a weight of magnitude <= 1 is 6e-8;
+            # a wrong update would be off by about lr
+            np.testing.assert_allclose(got[k], cur[k], rtol=1e-5, atol=6e-8, err_msg=k)
+    assert net.header() == (0.25, 0.5, 2.0)          # the header is not trained
+    with pytest.raises(B.GridderError):
+        B.gr_mlp_train_step(net.blob, net.m, net.v, net.grads, xd, td, idd, 256, 0, 1e-3, None)
+
+
+def _small_table(S=8, O=4, planes=8, fov=0.5, w_hat_max=6.0):
+    from paper_1605_07023_amd import binding as B
+    whs = np.linspace(-w_hat_max, w_hat_max, planes)
+    table = torch.empty((planes, O, O, S, S, 2), dtype=torch.float32, device=DEV)
+    B.gr_make_wkernel2d_table(S, O, planes, float(whs[0]), float(whs[1] - whs[0]), fov, 8, 8.6, 0,
+                              B.GR_F32, table)
+    return table, whs
+
+
+def test_dataset_layout(T):
+    _say("mlp dataset layout")
+    S, O = 8, 4
+    table, whs = _small_table(S, O, 3)
+    rng_ = 2 * 6.0
+    x, t = T.dataset_from_table(table, S, O, whs, rng_, 0.5)
+    ref_x = M.table_inputs(whs / rng_, S, O)
+    np.testing.assert_allclose(x.cpu().numpy(), ref_x, rtol=0, atol=1e-6)
+    tv = table.cpu().numpy().reshape(-1, 2) / 0.5
+    np.testing.assert_allclose(t.cpu().numpy(), tv, rtol=1e-6, atol=0)
+
+
+def test_training_reduces_loss_and_resumes(T, tmp_path):
+    _say("mlp training 2 x 200 steps with a checkpoint between")
+    S, O = 8, 4
+    table, whs = _small_table(S, O, 8)
+    scale = float(table.abs().max().item())
+    x, t = T.dataset_from_table(table, S, O, whs, 2 * 6.0, scale)
+    net = T.TapNet(DEV, seed=0)
+    log1 = net.train(x, t, 200, batch=1024, lr=3e-3, lr_final=1e-3, log_every=50)
+    path = str(tmp_path / "net.npz")
+    net.save(path)
+    net2 = T.TapNet.load(path, DEV)
+    assert net2.step == 200
+    assert torch.equal(net2.blob, net.blob) and torch.equal(net2.m, net.m) and torch.equal(net2.v, net.v)
+    log2 = net2.train(x, t, 200, batch=1024, lr=1e-3, lr_final=1e-4, log_every=50)
+    assert net2.step == 400
+    _say(f"  losses {log1.losses} {log2.losses}")
+    assert log2.losses[-1] < 0.2 * log1.losses[0]
+    assert all(np.isfinite(log1.losses + log2.losses))
+
+
+@pytest.mark.parametrize("P,seg,O", [(1, 0, 8), (4, 37, 8), (4, 0, 128)])
+def test_grid_mlp_matches_oracle_taps(T, P, seg, O):
+    """The fused gridder against the FP64 table gridder fed the FP64 network's taps."""
+    _say(f"fused network gridding P={P} seg={seg} O={O}")
+    from paper_1605_07023_amd import binding as B, runner
+    S, planes = 16, 5
+    wl = random_point_workload(1500, P, 80, 72, S, O, seed=P + seg, n_planes=planes, margin=5,
+                               weights=True, kernel="w2d")
+    p = _params(11)
+    net = T.TapNet(DEV, params=p)
+    wh = wl.plane_w_hat()
+    w_rng = 2 * max(abs(wh).max(), 1e-9)
+    off, step = T.header_for_planes(wl.w_min, wl.inv_dw, wl.w_hat_scale, w_rng)
+    net.set_header(off, step, 0.8)
+    dummy = torch.zeros(2, dtype=torch.float32, device=DEV)
+    dw = runner.upload(wl, DEV, taps=dummy)
+    dw = dataclasses.replace(dw, kernel=net.kernel(S, O, planes, wl.w_min, wl.inv_dw), taps=net.blob)
+    stats = torch.zeros(2, dtype=torch.int64, device=DEV)
+    g = runner.grid(dw, tune=runner.tuning(vis_per_wg=seg), stats=stats).cpu().numpy()
+    x0 = (np.float32(off) + np.arange(planes, dtype=np.float32) * np.float32(step)).astype(np.float64)
+    ref, dropped = M.grid_network(wl.vis, wl.uvw, wl.weights, p, 0.8, x0, 1.0, 1.0, O, S, 80, 72,
+                                  planes, wl.w_min, wl.inv_dw)
+    err = _rel(g, ref)
+    _say(f"  rel L2 {err:.2e}")
+    assert err <= 1e-2
+    assert stats.cpu().tolist() == [wl.n_vis - dropped, dropped]
+    assert B.GR_MLP == dw.kernel.kind
+
+
+def test_grid_mlp_rejects_bad_descriptors(T):
+    from paper_1605_07023_amd import binding as B, runner
+    wl = random_point_workload(10, 1, 64, 64, 8, 8, seed=0, n_planes=2, kernel="w2d")
+    net = T.TapNet(DEV, seed=0)
+    dw = runner.upload(wl, DEV, taps=torch.zeros(2, dtype=torch.float32, device=DEV))
+    for bad in (dict(tap_dtype=B.GR_F16), dict(taps_complex=0)):
+        k = net.kernel(8, 8, 2, wl.w_min, wl.inv_dw)
+        for f, val in bad.items():
+            setattr(k, f, val)
+        with pytest.raises(B.GridderError):
+            runner.grid(dataclasses.replace(dw, kernel=k, taps=net.blob))

@@ -44,6 +44,9 @@ def _oracle_grid(wl, taps):
 def _oracle_taps(wl):
     if wl.kernel == "kb":
         return G.kb_table(wl.support, wl.oversample, wl.beta)
+    if wl.kernel == "w2d":
+        return G.wkernel_2d_table(wl.support, wl.oversample, wl.plane_w_hat(), wl.fov,
+                                  wl.support_aa, wl.beta)
     return G.wkernel_table(wl.support, wl.oversample, wl.plane_w_hat(), wl.support_aa, wl.beta)
 
 
@@ -327,3 +330,54 @@ def test_full_shape_sampled_rows(R, c_oracle, S, variant, full_S16):
     err = _rel_l2(got, ref)
     _say(f"full shape S={S}: sampled-row rel L2 = {err:.3e}")
     assert err <= 1e-5
+
+
+# ------------------------------------------------------------------ autotuning
+
+def test_autotune_picks_fastest_valid_candidate(R, c_oracle):
+    from paper_1605_07023_amd import autotune as A
+    from paper_1605_07023_amd import binding as B
+    _say("autotune sweep on a small workload")
+    wl = full_shape_workload(16, n_baselines=16)
+    dw = R.upload(wl, DEV)
+    cands = [B.GrTuning(1, 1, 0, 0, 1024, 1), B.GrTuning(4, 2, 0, 0, 1024, 1),
+             B.GrTuning(8, 8, 0, 0, 1024, 1),            # over the register budget at P = 4
+             B.GrTuning(0, 0, 0, 0, 512, 2), B.GrTuning(0, 0, 0, 0, 4096, 2)]
+    best, times = A.tune(dw, cands, reps=2)
+    assert times[2] == float("inf")
+    finite = [t for t in times if t != float("inf")]
+    assert len(finite) == 4 and min(finite) == times[cands.index(best)]
+    g = R.grid(dw, tune=best).cpu().numpy()
+    ref, _ = c_oracle.grid_separable(wl.vis, wl.uvw, None, _oracle_taps(wl), wl.inv_cell_u,
+                                     wl.inv_cell_v, 8, wl.height, wl.width, wl.n_planes, wl.w_min,
+                                     wl.inv_dw)
+    assert _rel_l2(g, ref) <= 1e-5
+
+
+# ------------------------------------------------------------------ exact 2-D W kernel
+
+@pytest.mark.parametrize("S,O,planes,fov", [(8, 2, 3, 0.5), (16, 4, 2, 0.9)])
+def test_wkernel2d_table_fp64_matches_oracle(R, S, O, planes, fov):
+    from paper_1605_07023_amd import binding as B
+    _say(f"2-D W table S={S} O={O} planes={planes} fov={fov}")
+    w0, dw = -float(S - 8) or -3.0, 2.0 * (float(S - 8) or 3.0) / max(planes - 1, 1)
+    out = torch.empty((planes, O, O, S, S, 2), dtype=torch.float64, device=DEV)
+    B.gr_make_wkernel2d_table(S, O, planes, w0, dw, fov, 8, 8.6, 0, B.GR_F64, out)
+    got = out.cpu().numpy()
+    got = got[..., 0] + 1j * got[..., 1]
+    ref = G.wkernel_2d_table(S, O, w0 + dw * np.arange(planes), fov, 8, 8.6)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("P,seg", [(4, 0), (1, 37), (4, 5)])
+def test_grid_table2d(R, P, seg):
+    _say(f"grid with the 2-D table P={P} seg={seg}")
+    wl = random_point_workload(2500, P, 96, 72, 16, 4, seed=P + seg, n_planes=5, margin=5,
+                               weights=True, kernel="w2d")
+    dw = R.upload(wl, DEV)
+    stats = torch.zeros(2, dtype=torch.int64, device=DEV)
+    g = R.grid(dw, tune=R.tuning(vis_per_wg=seg), stats=stats).cpu().numpy()
+    ref, dropped = G.grid_table2d(wl.vis, wl.uvw, wl.weights, _oracle_taps(wl), 1.0, 1.0, 4, 96, 72,
+                                  5, wl.w_min, wl.inv_dw)
+    assert _rel_l2(g, ref) <= 1e-5
+    assert stats.cpu().tolist() == [wl.n_vis - dropped, dropped]

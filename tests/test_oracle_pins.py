@@ -335,3 +335,47 @@ def test_degrid_is_adjoint_of_grid():
     rhs_c = np.vdot(dgc, wl.vis.astype(np.complex128))
     assert lhs == pytest.approx(rhs_c, rel=1e-12)
     assert abs(lhs - rhs) > 1e-6 * abs(lhs)
+
+
+def test_wkernel_2d_at_matches_table_entries():
+    """The per-offset evaluation and the row-column table give the same taps."""
+    S, O = 16, 4
+    whs = [3.5, -2.0]
+    t = G.wkernel_2d_table(S, O, whs, 0.5)
+    d = G.tap_offsets(S, O)
+    for p, wh in enumerate(whs):
+        for sv in range(O):
+            for su in range(O):
+                np.testing.assert_allclose(G.wkernel_2d_at(wh, d[su], d[sv], 0.5, S), t[p, sv, su],
+                                           atol=1e-13, rtol=0)
+
+
+def test_continuous_w2d_grid_equals_table_grid_on_table_points():
+    """Visibilities placed exactly on a plane centre and an oversampled phase:
+    the continuous-kernel gridder and the 2-D table gridder agree, so the
+    continuous reference uses the same cells, signs and offsets."""
+    S, O, H, W, n_planes = 8, 4, 64, 64, 5
+    rng = np.random.default_rng(11)
+    n = 40
+    w_min, inv_dw, whs = -100.0, (n_planes - 1) / 200.0, 0.03
+    plane = rng.integers(0, n_planes, n)
+    w = w_min + plane / inv_dw
+    fx = rng.integers((S // 2 + 1) * O, (W - S // 2 - 1) * O, n)
+    fy = rng.integers((S // 2 + 1) * O, (H - S // 2 - 1) * O, n)
+    u = (fx - (W // 2) * O) / O
+    v = (fy - (H // 2) * O) / O
+    uvw = np.stack([u, v, w], axis=1)
+    vis = (rng.standard_normal((n, 1)) + 1j * rng.standard_normal((n, 1))).astype(np.complex64)
+    wh_planes = (w_min + np.arange(n_planes) / inv_dw) * whs
+    table = G.wkernel_2d_table(S, O, wh_planes, 0.5)
+    ref, drop_t = G.grid_table2d(vis, uvw, None, table, 1.0, 1.0, O, H, W, n_planes, w_min, inv_dw)
+    got, drop_c = G.grid_w2d_continuous(vis, uvw, None, 1.0, 1.0, O, S, H, W, n_planes, w_min, inv_dw,
+                                        whs, 0.5)
+    assert drop_t == drop_c == 0
+    np.testing.assert_allclose(got, ref, atol=1e-12 * np.abs(ref).max(), rtol=0)
+    # off a table point the two differ (the continuous reference is not the table)
+    uvw2 = uvw.copy()
+    uvw2[:, 2] += 0.3 / inv_dw
+    got2, _ = G.grid_w2d_continuous(vis, uvw2, None, 1.0, 1.0, O, S, H, W, n_planes, w_min, inv_dw,
+                                    whs, 0.5)
+    assert np.linalg.norm(got2 - ref) > 1e-3 * np.linalg.norm(ref)
