@@ -271,6 +271,46 @@ gr_status gr_mlp_train_step(float* weights, float* adam_m, float* adam_v, float*
                             const float* inputs, const float* targets, const int32_t* idx,
                             int32_t batch, int32_t step, float lr, float* loss_sum, void* stream);
 
+/* ---- Batches --------------------------------------------------------------
+ * One independent gridding problem of a batch: the arguments of gr_grid for
+ * it (the visibility stream, its kernel, cell sizes and grid), plus the
+ * segment length of its binning (0: default).  Every pointer is device
+ * memory; `kernel` is embedded by value (its taps pointer is device memory). */
+typedef struct {
+  const double* uvw;        /* [n_vis][3] */
+  const void* vis;          /* as gr_preprocess */
+  int32_t vis_dtype;        /* GR_F32 or GR_F16 */
+  int32_t n_pol;            /* 1 or 4 */
+  const float* vis_scale;   /* GR_F16 only */
+  const float* weights;     /* may be NULL */
+  int64_t n_vis;            /* >= 0, < 2^31 */
+  gr_kernel kernel;         /* GR_SEPARABLE */
+  double inv_cell_u, inv_cell_v;
+  void* grid;               /* [n_pol][height][width] complex64, accumulated (+=) */
+  int32_t height, width;
+  int32_t seg_len;          /* binning segment length (gr_bin); 0: default */
+  int32_t reserved;         /* must be 0 */
+  int64_t* dev_stats;       /* may be NULL: as gr_preprocess */
+} gr_batch_item;
+
+/* Bytes of workspace gr_grid_batch needs for these items (0 if any is invalid). */
+size_t gr_grid_batch_workspace_bytes(const gr_batch_item* items, int32_t n_items);
+
+/* Grid a batch of independent problems (0 <= n_items <= 4096), each with the
+ * result gr_grid would give it (binned MFMA path; separable kernels with
+ * support <= 56).  The paper launches one problem at a time and observes that
+ * sparse slices leave the device underused (Section 5); here all problems go
+ * through one fixed launch sequence: per-visibility preprocess and binning
+ * kernels spanning every item, then one persistent gridder per (n_pol, real or
+ * complex taps) group whose work-groups take (item, segment) work from an
+ * atomic counter.  The sequence issues no memset and never synchronises with
+ * the host, so it can be captured into a HIP graph and replayed (the items'
+ * buffers and the workspace must then stay allocated).  Items are validated
+ * on the host before anything is launched; the first invalid item's index is
+ * named in gr_last_error. */
+gr_status gr_grid_batch(const gr_batch_item* items, int32_t n_items, void* workspace,
+                        size_t workspace_bytes, void* stream);
+
 /* Thread-local description of the last non-OK status ("" if none). */
 const char* gr_last_error(void);
 

@@ -36,6 +36,15 @@ class GrKernel(ctypes.Structure):
                 ("taps", ctypes.c_void_p)]
 
 
+class GrBatchItem(ctypes.Structure):
+    _fields_ = [("uvw", ctypes.c_void_p), ("vis", ctypes.c_void_p), ("vis_dtype", ctypes.c_int32),
+                ("n_pol", ctypes.c_int32), ("vis_scale", ctypes.c_void_p), ("weights", ctypes.c_void_p),
+                ("n_vis", ctypes.c_int64), ("kernel", GrKernel), ("inv_cell_u", ctypes.c_double),
+                ("inv_cell_v", ctypes.c_double), ("grid", ctypes.c_void_p), ("height", ctypes.c_int32),
+                ("width", ctypes.c_int32), ("seg_len", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("dev_stats", ctypes.c_void_p)]
+
+
 class GrTuning(ctypes.Structure):
     _fields_ = [("cu", ctypes.c_int32), ("cv", ctypes.c_int32), ("wg_u", ctypes.c_int32),
                 ("wg_v", ctypes.c_int32), ("vis_per_wg", ctypes.c_int32),
@@ -82,6 +91,10 @@ def load_library():
     lib.gr_bin_bytes.restype = SZ
     lib.gr_last_error.argtypes = []
     lib.gr_last_error.restype = ctypes.c_char_p
+    lib.gr_grid_batch.argtypes = [ctypes.POINTER(GrBatchItem), I32, P, SZ, P]
+    lib.gr_grid_batch.restype = ctypes.c_int
+    lib.gr_grid_batch_workspace_bytes.argtypes = [ctypes.POINTER(GrBatchItem), I32]
+    lib.gr_grid_batch_workspace_bytes.restype = SZ
     lib.gr_mlp_blob_floats.argtypes = []
     lib.gr_mlp_blob_floats.restype = I32
     lib.gr_version.argtypes = []
@@ -236,3 +249,22 @@ def gr_mlp_train_step(weights, adam_m, adam_v, grads, inputs, targets, idx, batc
     _check(load_library().gr_mlp_train_step(_ptr(weights), _ptr(adam_m), _ptr(adam_v), _ptr(grads),
                                             _ptr(inputs), _ptr(targets), _ptr(idx), batch, step, lr,
                                             _ptr(loss_sum), _stream(stream, weights)))
+
+
+def make_batch_item(uvw, vis, vis_dtype, n_pol, vis_scale, weights, n_vis, kernel: GrKernel, inv_cell_u,
+                    inv_cell_v, grid, height, width, seg_len=0, dev_stats=None) -> GrBatchItem:
+    """Fill a gr_batch_item; the tensors are kept alive by the caller."""
+    return GrBatchItem(_ptr(uvw), _ptr(vis), vis_dtype, n_pol, _ptr(vis_scale), _ptr(weights), n_vis,
+                       kernel, inv_cell_u, inv_cell_v, _ptr(grid), height, width, seg_len, 0,
+                       _ptr(dev_stats))
+
+
+def gr_grid_batch_workspace_bytes(items) -> int:
+    arr = (GrBatchItem * max(len(items), 1))(*items)
+    return int(load_library().gr_grid_batch_workspace_bytes(arr, len(items)))
+
+
+def gr_grid_batch(items, workspace, workspace_bytes, stream=None):
+    arr = (GrBatchItem * max(len(items), 1))(*items)
+    _check(load_library().gr_grid_batch(arr, len(items), _ptr(workspace), workspace_bytes,
+                                        _stream(stream, workspace)))

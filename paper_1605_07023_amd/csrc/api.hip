@@ -1,6 +1,9 @@
 // C-ABI entry points: host-side validation, workspace layout, dispatch.
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <string>
+#include <utility>
 
 #include "internal.h"
 
@@ -18,6 +21,23 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 gr_status fail(gr_status st, const std::string& msg) {
   g_last_error = msg;
   return st;
+}
+
+gr_status ensure_lds_limit(const void* fn, size_t bytes, const char* what) {
+  // hipFuncSetAttribute is issued once per (kernel, device) and size increase:
+  // later launches, including ones captured into a graph, skip it.
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, size_t> done;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(GR_EDEVICE, std::string(what) + ": no device");
+  std::lock_guard<std::mutex> lock(mu);
+  size_t& have = done[{fn, dev}];
+  if (bytes <= have) return GR_OK;
+  const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess)
+    return fail(GR_EDEVICE, std::string(what) + ": hipFuncSetAttribute: " + hipGetErrorString(e));
+  have = bytes;
+  return GR_OK;
 }
 
 gr_status check_launch(const char* what) {

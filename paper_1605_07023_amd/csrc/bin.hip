@@ -28,10 +28,8 @@ __global__ void __launch_bounds__(256) fill_i32(int32_t* p, int64_t n, int32_t v
 }
 
 // One visibility per lane; lanes of a wave with the same tile add once.
-__global__ void __launch_bounds__(256)
-bin_count_kernel(const Record* __restrict__ rec, int64_t n, int tile, int n_tx,
-                 int32_t* __restrict__ count) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void bin_count_one(const Record* __restrict__ rec, int64_t n, int64_t i,
+                                              int tile, int n_tx, int32_t* __restrict__ count) {
   const int lane = threadIdx.x & 63;
   int key = -1;
   if (i < n) {
@@ -48,12 +46,18 @@ bin_count_kernel(const Record* __restrict__ rec, int64_t n, int tile, int n_tx,
   }
 }
 
-// Single block of 1024 threads: exclusive scan of counts -> cursor (list
+__global__ void __launch_bounds__(256)
+bin_count_kernel(const Record* __restrict__ rec, int64_t n, int tile, int n_tx,
+                 int32_t* __restrict__ count) {
+  bin_count_one(rec, n, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, tile, n_tx, count);
+}
+
+// One block of 1024 threads: exclusive scan of counts -> cursor (list
 // offsets), and the segment table {begin, length, tile, 0}.
-__global__ void __launch_bounds__(1024)
-bin_scan_kernel(const int32_t* __restrict__ count, int n_tiles, int seg_len,
-                int32_t* __restrict__ cursor, int4* __restrict__ segs,
-                int32_t* __restrict__ n_segs_out) {
+__device__ __forceinline__ void bin_scan_block(const int32_t* __restrict__ count, int n_tiles,
+                                               int seg_len, int32_t* __restrict__ cursor,
+                                               int4* __restrict__ segs,
+                                               int32_t* __restrict__ n_segs_out) {
   __shared__ int64_t s_vis[1024];
   __shared__ int64_t s_seg[1024];
   const int t = threadIdx.x, T = blockDim.x;
@@ -90,11 +94,19 @@ bin_scan_kernel(const int32_t* __restrict__ count, int n_tiles, int seg_len,
   if (t == T - 1) *n_segs_out = (int32_t)s_seg[T - 1];
 }
 
-__global__ void __launch_bounds__(256)
-bin_scatter_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvis, int64_t n,
-                   int n_pol, int tile, int n_tx, int32_t* __restrict__ cursor,
-                   Record* __restrict__ out_rec, float2* __restrict__ out_wvis) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(1024)
+bin_scan_kernel(const int32_t* __restrict__ count, int n_tiles, int seg_len,
+                int32_t* __restrict__ cursor, int4* __restrict__ segs,
+                int32_t* __restrict__ n_segs_out) {
+  bin_scan_block(count, n_tiles, seg_len, cursor, segs, n_segs_out);
+}
+
+__device__ __forceinline__ void bin_scatter_one(const Record* __restrict__ rec,
+                                                const float2* __restrict__ wvis, int64_t n,
+                                                int64_t i, int n_pol, int tile, int n_tx,
+                                                int32_t* __restrict__ cursor,
+                                                Record* __restrict__ out_rec,
+                                                float2* __restrict__ out_wvis) {
   const int lane = threadIdx.x & 63;
   int key = -1;
   Record r{0, 0};
@@ -119,6 +131,48 @@ bin_scatter_kernel(const Record* __restrict__ rec, const float2* __restrict__ wv
     out_rec[pos] = r;
     for (int p = 0; p < n_pol; ++p) out_wvis[(int64_t)pos * n_pol + p] = wvis[i * n_pol + p];
   }
+}
+
+__global__ void __launch_bounds__(256)
+bin_scatter_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvis, int64_t n,
+                   int n_pol, int tile, int n_tx, int32_t* __restrict__ cursor,
+                   Record* __restrict__ out_rec, float2* __restrict__ out_wvis) {
+  bin_scatter_one(rec, wvis, n, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, n_pol, tile, n_tx,
+                  cursor, out_rec, out_wvis);
+}
+
+// ---- batched forms (one launch for all instances of a batch) ----------------
+
+// zero every instance's tile counts and segment count (block per instance)
+__global__ void __launch_bounds__(256) batch_bin_zero_kernel(const BatchInst* __restrict__ inst) {
+  const BatchInst& I = inst[blockIdx.x];
+  for (int t = threadIdx.x; t < I.n_tiles; t += blockDim.x) I.count[t] = 0;
+  if (threadIdx.x == 0) *I.n_segs = 0;
+}
+
+__global__ void __launch_bounds__(256)
+batch_bin_count_kernel(const BatchInst* __restrict__ inst, int n_inst) {
+  __shared__ int s_i;
+  if (threadIdx.x == 0) s_i = batch_find(inst, n_inst, (int64_t)blockIdx.x);
+  __syncthreads();
+  const BatchInst& I = inst[s_i];
+  bin_count_one(I.rec, I.n_vis, ((int64_t)blockIdx.x - I.blk_begin) * blockDim.x + threadIdx.x,
+                I.d.tile, I.d.n_tx, I.count);
+}
+
+__global__ void __launch_bounds__(1024) batch_bin_scan_kernel(const BatchInst* __restrict__ inst) {
+  const BatchInst& I = inst[blockIdx.x];
+  bin_scan_block(I.count, I.n_tiles, I.seg_len, I.cursor, I.segs, I.n_segs);
+}
+
+__global__ void __launch_bounds__(256)
+batch_bin_scatter_kernel(const BatchInst* __restrict__ inst, int n_inst) {
+  __shared__ int s_i;
+  if (threadIdx.x == 0) s_i = batch_find(inst, n_inst, (int64_t)blockIdx.x);
+  __syncthreads();
+  const BatchInst& I = inst[s_i];
+  bin_scatter_one(I.rec, I.wvis, I.n_vis, ((int64_t)blockIdx.x - I.blk_begin) * blockDim.x + threadIdx.x,
+                  I.n_pol, I.d.tile, I.d.n_tx, I.cursor, I.brec, I.bwvis);
 }
 
 }  // namespace
@@ -163,6 +217,16 @@ gr_status launch_bin(const Record* rec, const float2* wvis, int64_t n_vis, int n
     bin_scatter_kernel<<<(unsigned)blocks, 256, 0, stream>>>(rec, wvis, n_vis, n_pol, L.tile, L.n_tx,
                                                             cursor, orec, owv);
   return check_launch("gr_bin");
+}
+
+gr_status launch_batch_bin(const BatchInst* inst, int n_inst, int64_t total_blocks, hipStream_t stream) {
+  if (n_inst == 0) return GR_OK;
+  if (total_blocks > 0x7fffffff) return fail(GR_EINVAL, "gr_grid_batch: too many visibilities");
+  batch_bin_zero_kernel<<<(unsigned)n_inst, 256, 0, stream>>>(inst);
+  if (total_blocks > 0) batch_bin_count_kernel<<<(unsigned)total_blocks, 256, 0, stream>>>(inst, n_inst);
+  batch_bin_scan_kernel<<<(unsigned)n_inst, 1024, 0, stream>>>(inst);
+  if (total_blocks > 0) batch_bin_scatter_kernel<<<(unsigned)total_blocks, 256, 0, stream>>>(inst, n_inst);
+  return check_launch("gr_grid_batch (bin)");
 }
 
 }  // namespace gr

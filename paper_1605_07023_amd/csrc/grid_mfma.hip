@@ -46,11 +46,6 @@ __device__ inline float load_tap32(const void* __restrict__ t, int64_t idx, int 
   }
 }
 
-struct MfmaDev {
-  int S, O, n_rows_tab, tap_dtype, tile, n_tx, H, W;
-  uint32_t n_blocks;
-};
-
 // Four waves per block share one segment.  The 64-row window is cut into row
 // groups of RG rows (P = 4: RG = 4, a D tile holds 4 rows x 4 polarisations;
 // P = 1: RG = 16); wave w owns row groups w, w + 4, w + 8, ... so that every
@@ -78,31 +73,12 @@ __device__ __forceinline__ float b_value(const TapT<CPLX>* row, int tap, int S, 
   }
 }
 
-template <int P, bool CPLX>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
-grid_mfma_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvis,
-                 const int4* __restrict__ segs, const int32_t* __restrict__ n_segs_p,
-                 const void* __restrict__ taps, float2* __restrict__ grid, MfmaDev d) {
-  constexpr int RG = 16 / P;            // rows per row group
-  constexpr int NG = kWin / RG / 4;     // row groups per wave
-  using Tap = TapT<CPLX>;
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  Record* b_rec = reinterpret_cast<Record*>(lds_raw);                            // [kBatch]
-  float2* b_vis = reinterpret_cast<float2*>(lds_raw + kBatch * sizeof(Record));  // [kBatch][P]
-  Tap* lds = reinterpret_cast<Tap*>(lds_raw + kBatch * sizeof(Record) + kBatch * P * sizeof(float2));
-
-  const int n_segs = *n_segs_p;
-  // Segments are listed in tile order and their count is only known on the
-  // device, so blocks take segments in dispatch order: consecutive segments
-  // (neighbouring tiles) land on different XCDs, which spreads the dense
-  // centre of the uv plane over the whole chip.
-  const int seg = (int)blockIdx.x;
-  if (seg >= n_segs) return;                          // uniform for the block
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+// Stage the tap table as FP32 rows [plane * O + s] of S + 2 entries, with one
+// zero before and after the S taps.
+template <bool CPLX>
+__device__ __forceinline__ void stage_taps(TapT<CPLX>* __restrict__ lds, const void* __restrict__ taps,
+                                           const MfmaDev& d) {
   const int S = d.S, SP = d.S + 2;
-
-  // ---- stage the tap table as FP32 rows [plane * O + s] of S + 2 entries,
-  //      with one zero before and after the S taps
   const int n_elem = d.n_rows_tab * SP;
   for (int e = threadIdx.x; e < n_elem; e += blockDim.x) {
     const int row = e / SP, k = e - row * SP - 1;
@@ -116,8 +92,22 @@ grid_mfma_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvis
       lds[e] = in ? load_tap32(taps, src, d.tap_dtype) : 0.f;
     }
   }
+}
 
-  const int4 sg = segs[seg];
+// One segment sg = {begin, length, tile} of the binned stream (rec, wvis) into
+// grid, with the staged table lds and the batch buffers b_rec, b_vis.  The
+// first statement of every batch is a block barrier, which also orders the
+// table staging before its first use.
+template <int P, bool CPLX>
+__device__ __forceinline__ void mfma_segment(const Record* __restrict__ rec,
+                                             const float2* __restrict__ wvis, const int4 sg,
+                                             const TapT<CPLX>* __restrict__ lds,
+                                             Record* __restrict__ b_rec, float2* __restrict__ b_vis,
+                                             float2* __restrict__ grid, const MfmaDev& d) {
+  constexpr int RG = 16 / P;            // rows per row group
+  constexpr int NG = kWin / RG / 4;     // row groups per wave
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int S = d.S, SP = d.S + 2;
   const int begin = sg.x, len = sg.y, tile_id = sg.z;
   const int win_x0 = (tile_id % d.n_tx) * d.tile;
   const int win_y0 = (tile_id / d.n_tx) * d.tile;
@@ -243,6 +233,75 @@ grid_mfma_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvis
   }
 }
 
+template <int P, bool CPLX>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+grid_mfma_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvis,
+                 const int4* __restrict__ segs, const int32_t* __restrict__ n_segs_p,
+                 const void* __restrict__ taps, float2* __restrict__ grid, MfmaDev d) {
+  using Tap = TapT<CPLX>;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  Record* b_rec = reinterpret_cast<Record*>(lds_raw);                            // [kBatch]
+  float2* b_vis = reinterpret_cast<float2*>(lds_raw + kBatch * sizeof(Record));  // [kBatch][P]
+  Tap* lds = reinterpret_cast<Tap*>(lds_raw + kBatch * sizeof(Record) + kBatch * P * sizeof(float2));
+  // Segments are listed in tile order and their count is only known on the
+  // device, so blocks take segments in dispatch order: consecutive segments
+  // (neighbouring tiles) land on different XCDs, which spreads the dense
+  // centre of the uv plane over the whole chip.
+  const int seg = (int)blockIdx.x;
+  if (seg >= *n_segs_p) return;                       // uniform for the block
+  stage_taps<CPLX>(lds, taps, d);
+  mfma_segment<P, CPLX>(rec, wvis, segs[seg], lds, b_rec, b_vis, grid, d);
+}
+
+// Persistent form for batches: a fixed set of blocks takes (instance, segment)
+// work items from an atomic counter until the group's items run out; the tap
+// table is restaged only when the instance changes.  Every block exits once
+// the counter passes the item total, which the prefix kernel wrote before
+// this launch.
+template <int P, bool CPLX>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+grid_mfma_persistent(const BatchInst* __restrict__ inst, const int32_t* __restrict__ members,
+                     int n_members, const int32_t* __restrict__ prefix,
+                     int32_t* __restrict__ counter) {
+  using Tap = TapT<CPLX>;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  Record* b_rec = reinterpret_cast<Record*>(lds_raw);
+  float2* b_vis = reinterpret_cast<float2*>(lds_raw + kBatch * sizeof(Record));
+  Tap* lds = reinterpret_cast<Tap*>(lds_raw + kBatch * sizeof(Record) + kBatch * P * sizeof(float2));
+  __shared__ int s_inst, s_seg;
+  const int total = prefix[n_members];
+  int staged = -1;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      const int item = atomicAdd(counter, 1);
+      int mi = -1;
+      if (item < total) {
+        int lo = 0, hi = n_members - 1;               // last member with prefix <= item
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (prefix[mid] <= item) lo = mid;
+          else hi = mid - 1;
+        }
+        mi = lo;
+      }
+      s_inst = mi >= 0 ? members[mi] : -1;
+      s_seg = mi >= 0 ? item - prefix[mi] : 0;
+    }
+    __syncthreads();                                  // also: the previous segment is finished
+    const int ii = __builtin_amdgcn_readfirstlane(s_inst);
+    const int ls = __builtin_amdgcn_readfirstlane(s_seg);
+    if (ii < 0) break;
+    const BatchInst& I = inst[ii];
+    const MfmaDev d = I.d;
+    if (ii != staged) {
+      stage_taps<CPLX>(lds, I.taps, d);
+      staged = ii;
+    }
+    mfma_segment<P, CPLX>(I.brec, I.bwvis, I.segs[ls], lds, b_rec, b_vis, I.grid, d);
+  }
+}
+
+
 using MfmaFn = void (*)(const Record*, const float2*, const int4*, const int32_t*, const void*,
                         float2*, MfmaDev);
 
@@ -280,12 +339,31 @@ gr_status launch_mfma(const void* bins, const BinLayout& L, int n_pol, const gr_
   MfmaFn fn;
   if (n_pol == 4) fn = k.taps_complex ? grid_mfma_kernel<4, true> : grid_mfma_kernel<4, false>;
   else fn = k.taps_complex ? grid_mfma_kernel<1, true> : grid_mfma_kernel<1, false>;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return fail(GR_EDEVICE, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+  {
+    const gr_status lst = ensure_lds_limit(reinterpret_cast<const void*>(fn), lds, "grid_mfma.hip");
+    if (lst != GR_OK) return lst;
+  }
   hipLaunchKernelGGL(fn, dim3((unsigned)nb), dim3(256), lds, stream, rec, wv, segs, nsegs, k.taps,
                      grid, d);
   return check_launch("gr_grid_binned (mfma)");
+}
+
+gr_status launch_mfma_persistent(const BatchInst* inst, const int32_t* members, int n_members,
+                                 const int32_t* group_prefix, int32_t* counter, int n_pol,
+                                 bool complex_taps, size_t lds_bytes, int n_blocks,
+                                 hipStream_t stream) {
+  if (n_members == 0 || n_blocks <= 0) return GR_OK;
+  using PFn = void (*)(const BatchInst*, const int32_t*, int, const int32_t*, int32_t*);
+  PFn fn;
+  if (n_pol == 4) fn = complex_taps ? grid_mfma_persistent<4, true> : grid_mfma_persistent<4, false>;
+  else fn = complex_taps ? grid_mfma_persistent<1, true> : grid_mfma_persistent<1, false>;
+  {
+    const gr_status lst = ensure_lds_limit(reinterpret_cast<const void*>(fn), lds_bytes, "grid_mfma.hip");
+    if (lst != GR_OK) return lst;
+  }
+  hipLaunchKernelGGL(fn, dim3((unsigned)n_blocks), dim3(256), lds_bytes, stream, inst, members, n_members,
+                     group_prefix, counter);
+  return check_launch("gr_grid_batch (persistent mfma)");
 }
 
 }  // namespace gr

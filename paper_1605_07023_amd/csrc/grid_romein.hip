@@ -288,9 +288,10 @@ gr_status launch_romein(const Record* rec, const float2* wvis, int64_t n_vis, in
   const int64_t nb = n_chunks * d.n_tgroups;
   if (nb > 0x7fffffff) return fail(GR_EINVAL, "too many work-groups; raise vis_per_wg");
   d.n_blocks = (uint32_t)nb;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes);
-  if (e != hipSuccess) return fail(GR_EDEVICE, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+  {
+    const gr_status lst = ensure_lds_limit(reinterpret_cast<const void*>(fn), p.lds_bytes, "grid_romein.hip");
+    if (lst != GR_OK) return lst;
+  }
   hipLaunchKernelGGL(fn, dim3((unsigned)nb), dim3(64 * p.waves_per_block), p.lds_bytes, stream, rec,
                      wvis, k.taps, grid, d);
   return check_launch("gr_grid_records (romein)");

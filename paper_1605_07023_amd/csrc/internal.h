@@ -14,6 +14,9 @@ namespace gr {
 void set_error(const std::string& msg);
 gr_status fail(gr_status st, const std::string& msg);
 gr_status check_launch(const char* what);
+// Raise a kernel's dynamic LDS limit to at least `bytes` (once per kernel,
+// device and size; never inside a later captured launch).
+gr_status ensure_lds_limit(const void* fn, size_t bytes, const char* what);
 
 // Packed per-visibility record written by the preprocess kernel.
 //   x = x0 | y0 << 16            (footprint origin, cells)
@@ -86,5 +89,68 @@ gr_status launch_grid_mlp(const void* bins, const BinLayout& L, int n_pol, const
 
 constexpr int kDefaultSegLen = 4096;
 size_t align256(size_t v);
+
+// Launch parameters of the MFMA gridder (grid_mfma.hip).
+struct MfmaDev {
+  int S, O, n_rows_tab, tap_dtype, tile, n_tx, H, W;
+  uint32_t n_blocks;
+};
+
+// ---- Batches of independent gridding problems (batch.hip) -------------------
+// Device descriptor of one instance: every batched kernel reads its instance's
+// pointers and sizes from a table of these in the workspace.
+struct BatchInst {
+  // preprocess
+  const double* uvw;
+  const void* vis;
+  const float* vis_scale;
+  const float* weights;
+  int64_t n_vis;
+  int32_t n_pol, vis_dtype;
+  double scale_u, scale_v, w_min, inv_dw;
+  int32_t lg_o, n_planes;
+  Record* rec;                   // preprocess output
+  float2* wvis;
+  unsigned long long* stats;     // may be NULL
+  int64_t blk_begin;             // first block of this instance in the batched per-visibility launches
+  // binning (bin.hip layout, per instance)
+  int32_t n_tiles, seg_len;
+  Record* brec;
+  float2* bwvis;
+  int32_t* count;
+  int32_t* cursor;
+  int4* segs;
+  int32_t* n_segs;
+  // gridding
+  const void* taps;
+  float2* grid;
+  MfmaDev d;                     // d.tile, d.n_tx are the binning tile and tiles per row
+  int32_t group;                 // persistent launch group: (n_pol == 4) * 2 + complex taps
+  int32_t pad_;
+};
+static_assert(sizeof(BatchInst) % 8 == 0, "descriptors are copied as 8-byte words");
+
+// Instance whose block range holds block b (blk_begin ascending, first one 0).
+__device__ inline int batch_find(const BatchInst* inst, int n_inst, int64_t b) {
+  int lo = 0, hi = n_inst - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (inst[mid].blk_begin <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+gr_status launch_batch_preprocess(const BatchInst* inst, int n_inst, int64_t total_blocks,
+                                  hipStream_t stream);
+gr_status launch_batch_bin(const BatchInst* inst, int n_inst, int64_t total_blocks,
+                           hipStream_t stream);
+// Persistent MFMA gridder over the segments of the instances `members`
+// (group_prefix: [n_members + 1] exclusive prefix of their segment counts,
+// written on the device; counter: zeroed work counter).
+gr_status launch_mfma_persistent(const BatchInst* inst, const int32_t* members, int n_members,
+                                 const int32_t* group_prefix, int32_t* counter, int n_pol,
+                                 bool complex_taps, size_t lds_bytes, int n_blocks,
+                                 hipStream_t stream);
 
 }  // namespace gr

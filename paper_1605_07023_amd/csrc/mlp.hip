@@ -506,8 +506,6 @@ size_t grid_mlp_lds(int S) {
          sizeof(float2) * (size_t)S * S;
 }
 
-bool g_grad_attr_set = false;
-
 }  // namespace
 
 gr_status launch_grid_mlp(const void* bins, const BinLayout& L, int n_pol, const gr_kernel& k,
@@ -523,9 +521,10 @@ gr_status launch_grid_mlp(const void* bins, const BinLayout& L, int n_pol, const
   MlpGridDev d{k.support, k.oversample, L.tile, L.n_tx, height, width};
   const size_t lds = grid_mlp_lds(k.support);
   auto* fn = n_pol == 4 ? grid_mlp_kernel<4> : grid_mlp_kernel<1>;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return fail(GR_EDEVICE, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+  {
+    const gr_status lst = ensure_lds_limit(reinterpret_cast<const void*>(fn), lds, "mlp.hip");
+    if (lst != GR_OK) return lst;
+  }
   hipLaunchKernelGGL(fn, dim3((unsigned)L.max_segs), dim3(256), lds, stream, rec, wv, segs, nsegs,
                      reinterpret_cast<const float*>(k.taps), grid, d);
   return check_launch("gr_grid_binned (network taps)");
@@ -558,12 +557,8 @@ extern "C" gr_status gr_mlp_grads(const float* weights, const float* inputs, con
   hipStream_t s = (hipStream_t)stream;
   fill_f32<<<(kBlob + 255) / 256, 256, 0, s>>>(grads, kBlob, 0.f);
   if (loss_sum) fill_f32<<<1, 64, 0, s>>>(loss_sum, 1, 0.f);
-  if (!g_grad_attr_set) {
-    if (hipFuncSetAttribute(reinterpret_cast<const void*>(mlp_grad_kernel),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, kTrainLds) != hipSuccess)
-      return fail(GR_EDEVICE, "gr_mlp_grads: hipFuncSetAttribute failed");
-    g_grad_attr_set = true;
-  }
+  const gr_status lst = ensure_lds_limit(reinterpret_cast<const void*>(mlp_grad_kernel), kTrainLds, "gr_mlp_grads");
+  if (lst != GR_OK) return lst;
   mlp_grad_kernel<<<(batch + 63) / 64, 64, kTrainLds, s>>>(weights, inputs, targets, idx, batch,
                                                             1.f / (float)batch, grads, loss_sum);
   return check_launch("gr_mlp_grads");

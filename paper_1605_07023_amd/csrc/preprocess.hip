@@ -27,65 +27,100 @@ __device__ inline float2 load_vis(const void* __restrict__ vis, const float* __r
   }
 }
 
-// One thread per visibility.  Block size 256.
+struct PreArgs {
+  const double* uvw;
+  const void* vis;
+  const float* vis_scale;
+  const float* weights;
+  int64_t n;
+  int n_pol;
+  double scale_u, scale_v;
+  int lg_o, S, H, W, n_planes;
+  double w_min, inv_dw;
+  Record* rec;
+  float2* wvis;
+};
+
+// Visibility i (< a.n): record, weighted visibilities; returns whether it is kept.
 template <int VDT>
-__global__ void __launch_bounds__(256)
-preprocess_kernel(const double* __restrict__ uvw, const void* __restrict__ vis,
-                  const float* __restrict__ vis_scale, const float* __restrict__ weights,
-                  int64_t n, int n_pol, double scale_u, double scale_v, int lg_o, int S, int H,
-                  int W, int n_planes, double w_min, double inv_dw, Record* __restrict__ rec,
-                  float2* __restrict__ wvis, unsigned long long* __restrict__ stats) {
+__device__ __forceinline__ bool preprocess_one(int64_t i, const PreArgs& a) {
 #pragma clang fp contract(off)
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool ok = false;
-  if (i < n) {
-    const double u = uvw[3 * i], v = uvw[3 * i + 1], w = uvw[3 * i + 2];
-    ok = isfinite(u) && isfinite(v) && isfinite(w);
-    // one correctly rounded multiply each: scale = inv_cell * O is exact (O = 2^k)
-    const double xh = u * scale_u;
-    const double yh = v * scale_v;
-    ok = ok && fabs(xh) < kBig && fabs(yh) < kBig;
-    const int O = 1 << lg_o;
-    const int64_t fx = (int64_t)rint(ok ? xh : 0.0) + (int64_t)(W / 2) * O;
-    const int64_t fy = (int64_t)rint(ok ? yh : 0.0) + (int64_t)(H / 2) * O;
-    const int64_t x0 = (fx >> lg_o) - S / 2 + 1;
-    const int64_t y0 = (fy >> lg_o) - S / 2 + 1;
-    int64_t plane = 0;
-    if (n_planes > 1) {
-      const double ph = (w - w_min) * inv_dw;
-      ok = ok && fabs(ph) < kBig;
-      plane = (int64_t)rint(ok ? ph : 0.0);
-    }
-    ok = ok && plane >= 0 && plane < n_planes && x0 >= 0 && x0 + S <= W && y0 >= 0 &&
-         y0 + S <= H;
-    // visibilities and weights must be finite as well
-    for (int p = 0; p < n_pol; ++p) {
-      const float2 vv = load_vis<VDT>(vis, vis_scale, i, p, n_pol);
-      const float wt = weights ? weights[i * n_pol + p] : 1.0f;
-      ok = ok && isfinite(vv.x) && isfinite(vv.y) && isfinite(wt);
-    }
-    for (int p = 0; p < n_pol; ++p) {
-      const float2 vv = load_vis<VDT>(vis, vis_scale, i, p, n_pol);
-      const float wt = weights ? weights[i * n_pol + p] : 1.0f;
-      wvis[i * n_pol + p] = ok ? make_float2(vv.x * wt, vv.y * wt) : make_float2(0.f, 0.f);
-    }
-    Record r;
-    if (ok) {
-      r.x = (uint32_t)x0 | ((uint32_t)y0 << 16);
-      r.y = (uint32_t)(fx & (O - 1)) | ((uint32_t)(fy & (O - 1)) << 8) | ((uint32_t)plane << 16) |
-            kValidBit;
-    } else {
-      r.x = 0;
-      r.y = 0;
-    }
-    rec[i] = r;
+  const double u = a.uvw[3 * i], v = a.uvw[3 * i + 1], w = a.uvw[3 * i + 2];
+  bool ok = isfinite(u) && isfinite(v) && isfinite(w);
+  // one correctly rounded multiply each: scale = inv_cell * O is exact (O = 2^k)
+  const double xh = u * a.scale_u;
+  const double yh = v * a.scale_v;
+  ok = ok && fabs(xh) < kBig && fabs(yh) < kBig;
+  const int O = 1 << a.lg_o;
+  const int64_t fx = (int64_t)rint(ok ? xh : 0.0) + (int64_t)(a.W / 2) * O;
+  const int64_t fy = (int64_t)rint(ok ? yh : 0.0) + (int64_t)(a.H / 2) * O;
+  const int64_t x0 = (fx >> a.lg_o) - a.S / 2 + 1;
+  const int64_t y0 = (fy >> a.lg_o) - a.S / 2 + 1;
+  int64_t plane = 0;
+  if (a.n_planes > 1) {
+    const double ph = (w - a.w_min) * a.inv_dw;
+    ok = ok && fabs(ph) < kBig;
+    plane = (int64_t)rint(ok ? ph : 0.0);
   }
+  ok = ok && plane >= 0 && plane < a.n_planes && x0 >= 0 && x0 + a.S <= a.W && y0 >= 0 &&
+       y0 + a.S <= a.H;
+  // visibilities and weights must be finite as well
+  for (int p = 0; p < a.n_pol; ++p) {
+    const float2 vv = load_vis<VDT>(a.vis, a.vis_scale, i, p, a.n_pol);
+    const float wt = a.weights ? a.weights[i * a.n_pol + p] : 1.0f;
+    ok = ok && isfinite(vv.x) && isfinite(vv.y) && isfinite(wt);
+  }
+  for (int p = 0; p < a.n_pol; ++p) {
+    const float2 vv = load_vis<VDT>(a.vis, a.vis_scale, i, p, a.n_pol);
+    const float wt = a.weights ? a.weights[i * a.n_pol + p] : 1.0f;
+    a.wvis[i * a.n_pol + p] = ok ? make_float2(vv.x * wt, vv.y * wt) : make_float2(0.f, 0.f);
+  }
+  Record r;
+  if (ok) {
+    r.x = (uint32_t)x0 | ((uint32_t)y0 << 16);
+    r.y = (uint32_t)(fx & (O - 1)) | ((uint32_t)(fy & (O - 1)) << 8) | ((uint32_t)plane << 16) |
+          kValidBit;
+  } else {
+    r.x = 0;
+    r.y = 0;
+  }
+  a.rec[i] = r;
+  return ok;
+}
+
+// Block-level kept / dropped counts into stats[0], stats[1].
+__device__ __forceinline__ void add_stats(bool ok, bool in, unsigned long long* stats) {
   const int n_ok = __syncthreads_count(ok ? 1 : 0);
-  const int n_in = __syncthreads_count(i < n ? 1 : 0);
+  const int n_in = __syncthreads_count(in ? 1 : 0);
   if (stats != nullptr && threadIdx.x == 0 && n_in > 0) {
     atomicAdd(&stats[0], (unsigned long long)n_ok);
     atomicAdd(&stats[1], (unsigned long long)(n_in - n_ok));
   }
+}
+
+// One thread per visibility.  Block size 256.
+template <int VDT>
+__global__ void __launch_bounds__(256)
+preprocess_kernel(PreArgs a, unsigned long long* __restrict__ stats) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool ok = i < a.n ? preprocess_one<VDT>(i, a) : false;
+  add_stats(ok, i < a.n, stats);
+}
+
+// Batched form: block b belongs to the instance whose [blk_begin, next blk_begin)
+// range holds b (every instance starts on a fresh block).
+__global__ void __launch_bounds__(256)
+batch_preprocess_kernel(const BatchInst* __restrict__ inst, int n_inst) {
+  __shared__ int s_i;
+  if (threadIdx.x == 0) s_i = batch_find(inst, n_inst, (int64_t)blockIdx.x);
+  __syncthreads();
+  const BatchInst& I = inst[s_i];
+  const PreArgs a{I.uvw, I.vis, I.vis_scale, I.weights, I.n_vis, I.n_pol, I.scale_u, I.scale_v,
+                  I.lg_o, I.d.S, I.d.H, I.d.W, I.n_planes, I.w_min, I.inv_dw, I.rec, I.wvis};
+  const int64_t i = ((int64_t)blockIdx.x - I.blk_begin) * blockDim.x + threadIdx.x;
+  bool ok = false;
+  if (i < a.n) ok = I.vis_dtype == GR_F32 ? preprocess_one<GR_F32>(i, a) : preprocess_one<GR_F16>(i, a);
+  add_stats(ok, i < a.n, I.stats);
 }
 
 }  // namespace
@@ -102,16 +137,21 @@ gr_status launch_preprocess(const double* uvw, const void* vis, int vis_dtype, c
   const int64_t blocks = (n_vis + 255) / 256;
   if (blocks > 0x7fffffff) return fail(GR_EINVAL, "gr_preprocess: n_vis too large");
   auto* st = reinterpret_cast<unsigned long long*>(dev_stats);
-  if (vis_dtype == GR_F32) {
-    preprocess_kernel<GR_F32><<<(unsigned)blocks, 256, 0, stream>>>(
-        uvw, vis, vis_scale, weights, n_vis, n_pol, su, sv, lg_o, k.support, height, width,
-        k.n_planes, k.w_min, k.inv_dw, records, wvis, st);
-  } else {
-    preprocess_kernel<GR_F16><<<(unsigned)blocks, 256, 0, stream>>>(
-        uvw, vis, vis_scale, weights, n_vis, n_pol, su, sv, lg_o, k.support, height, width,
-        k.n_planes, k.w_min, k.inv_dw, records, wvis, st);
-  }
+  const PreArgs a{uvw, vis, vis_scale, weights, n_vis, n_pol, su, sv, lg_o, k.support, height, width,
+                  k.n_planes, k.w_min, k.inv_dw, records, wvis};
+  if (vis_dtype == GR_F32)
+    preprocess_kernel<GR_F32><<<(unsigned)blocks, 256, 0, stream>>>(a, st);
+  else
+    preprocess_kernel<GR_F16><<<(unsigned)blocks, 256, 0, stream>>>(a, st);
   return check_launch("gr_preprocess");
+}
+
+gr_status launch_batch_preprocess(const BatchInst* inst, int n_inst, int64_t total_blocks,
+                                  hipStream_t stream) {
+  if (total_blocks == 0) return GR_OK;
+  if (total_blocks > 0x7fffffff) return fail(GR_EINVAL, "gr_grid_batch: too many visibilities");
+  batch_preprocess_kernel<<<(unsigned)total_blocks, 256, 0, stream>>>(inst, n_inst);
+  return check_launch("gr_grid_batch (preprocess)");
 }
 
 }  // namespace gr

@@ -123,3 +123,30 @@ def decode_records(rec: np.ndarray) -> dict:
     x, y = a[:, 0].astype(np.int64), a[:, 1].astype(np.int64)
     return dict(x0=x & 0xFFFF, y0=x >> 16, sx=y & 0xFF, sy=(y >> 8) & 0xFF,
                 plane=(y >> 16) & 0x7FFF, valid=(y >> 31) & 1)
+
+
+def batch_items(dws, grids, seg_lens=None, stats=None):
+    """gr_batch_item list for device workloads and their output grids."""
+    items = []
+    for i, (dw, g) in enumerate(zip(dws, grids)):
+        wl = dw.wl
+        items.append(B.make_batch_item(dw.uvw, dw.vis, dw.vis_dtype, wl.n_pol, dw.vis_scale, dw.weights,
+                                       wl.n_vis, dw.kernel, wl.inv_cell_u, wl.inv_cell_v, g, wl.height,
+                                       wl.width, seg_lens[i] if seg_lens else 0,
+                                       None if stats is None else stats[i]))
+    return items
+
+
+def grid_batch(dws, grids=None, seg_lens=None, stats=None, workspace=None, stream=None):
+    """Grid every device workload of a batch with one gr_grid_batch call; returns
+    (grids, workspace)."""
+    if grids is None:
+        grids = [torch.zeros((dw.wl.n_pol, dw.wl.height, dw.wl.width), dtype=torch.complex64,
+                             device=dw.uvw.device) for dw in dws]
+    items = batch_items(dws, grids, seg_lens, stats)
+    need = B.gr_grid_batch_workspace_bytes(items)
+    if workspace is None or workspace.numel() < need:
+        dev = dws[0].uvw.device if dws else "cuda"
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    B.gr_grid_batch(items, workspace, workspace.numel(), stream)
+    return grids, workspace

@@ -70,12 +70,14 @@ def blob_to_params(blob: np.ndarray) -> dict:
 
 
 def init_params(seed: int = 0) -> dict:
-    """He-uniform weights (fan-in of live inputs), zero biases."""
+    """Weights uniform in +-1/sqrt(fan-in of live inputs), zero biases.  (He
+    scaling, 2.45 times larger, trains this network to an about ten times
+    larger tap error.)"""
     rng = np.random.default_rng(seed)
     fan = {"W1": N_FEAT, "W2": HIDDEN, "W3": HIDDEN, "W4": HIDDEN}
     p = {}
     for k in ("W1", "W2", "W3", "W4"):
-        lim = math.sqrt((6.0 if k != "W4" else 3.0) / fan[k])
+        lim = 1.0 / math.sqrt(fan[k])
         p[k] = rng.uniform(-lim, lim, size=SHAPES[k])
     p["W1"][N_FEAT:] = 0.0
     for k in ("b1", "b2", "b3", "b4"):

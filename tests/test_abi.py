@@ -124,3 +124,60 @@ def test_table_generators_reject(lib):
     assert lib.gr_make_wkernel_table(16, 8, 0, 0.0, 1.0, 8, 8.6, 0, B.GR_F32, 1 << 20, None) == B.GR_EINVAL
     assert lib.gr_make_wkernel_table(16, 8, 4, 0.0, 1.0, 20, 8.6, 0, B.GR_F32, 1 << 20, None) == B.GR_EINVAL
     assert lib.gr_make_wkernel_table(16, 8, 4, 0.0, 1.0, 8, 8.6, 0, B.GR_F32, None, None) == B.GR_EINVAL
+
+
+def _item(B, **kw):
+    k = _kernel()
+    base = dict(uvw=1 << 20, vis=1 << 20, vis_dtype=B.GR_F32, n_pol=4, vis_scale=None, weights=None,
+                n_vis=100, kernel=k, inv_cell_u=1.0, inv_cell_v=1.0, grid=1 << 20, height=64, width=64)
+    base.update(kw)
+    return B.make_batch_item(**base)
+
+
+def test_batch_validation(lib):
+    from paper_1605_07023_amd import binding as B
+    good = _item(B)
+    arr = (B.GrBatchItem * 3)(good, _item(B, n_pol=3), good)
+    assert lib.gr_grid_batch(arr, 3, 1 << 20, 1 << 40, None) == B.GR_EINVAL
+    assert "item 1" in lib.gr_last_error().decode()
+    assert lib.gr_grid_batch_workspace_bytes(arr, 3) == 0
+    assert lib.gr_grid_batch(arr, -1, 1 << 20, 1 << 40, None) == B.GR_EINVAL
+    assert lib.gr_grid_batch(arr, 5000, 1 << 20, 1 << 40, None) == B.GR_EINVAL
+    k2 = _kernel()
+    k2.kind = B.GR_TABLE2D
+    arr = (B.GrBatchItem * 2)(good, _item(B, kernel=k2))
+    assert lib.gr_grid_batch(arr, 2, 1 << 20, 1 << 40, None) == B.GR_EUNSUPPORTED
+    for bad in (dict(grid=None), dict(height=4), dict(inv_cell_u=float("nan")), dict(seg_len=-1),
+                dict(vis_dtype=B.GR_F16), dict(n_vis=-1)):
+        arr = (B.GrBatchItem * 1)(_item(B, **bad))
+        assert lib.gr_grid_batch(arr, 1, 1 << 20, 1 << 40, None) == B.GR_EINVAL, bad
+    arr = (B.GrBatchItem * 2)(good, _item(B, n_pol=1, n_vis=0))
+    need = lib.gr_grid_batch_workspace_bytes(arr, 2)
+    assert need > 0
+    assert lib.gr_grid_batch(arr, 2, 1 << 20, need - 1, None) == B.GR_ENOMEM
+    assert lib.gr_grid_batch(arr, 2, None, need, None) == B.GR_EINVAL
+    assert lib.gr_grid_batch(arr, 0, None, 0, None) == B.GR_OK          # nothing to do
+
+
+def test_mlp_entry_points_reject(lib):
+    from paper_1605_07023_amd import binding as B
+    P = 1 << 20
+    assert lib.gr_mlp_blob_floats() == 12616
+    assert lib.gr_mlp_eval(P, P, -1, P, None) == B.GR_EINVAL
+    assert lib.gr_mlp_eval(None, P, 10, P, None) == B.GR_EINVAL
+    assert lib.gr_mlp_grads(P, P, P, P, 0, P, None, None) == B.GR_EINVAL
+    assert lib.gr_mlp_grads(P, P, None, P, 8, P, None, None) == B.GR_EINVAL
+    assert lib.gr_mlp_train_step(P, P, P, P, P, P, P, 8, 0, 1e-3, None, None) == B.GR_EINVAL
+    assert lib.gr_mlp_train_step(P, P, P, P, P, P, P, 8, 1, float("nan"), None, None) == B.GR_EINVAL
+    assert lib.gr_mlp_train_step(P, None, P, P, P, P, P, 8, 1, 1e-3, None, None) == B.GR_EINVAL
+    assert lib.gr_mlp_dataset(P, 16, 8, 0, 0.0, 1.0, 1.0, 1.0, P, P, None) == B.GR_EINVAL
+    assert lib.gr_mlp_dataset(P, 16, 8, 4, 0.0, 1.0, 0.0, 1.0, P, P, None) == B.GR_EINVAL
+    assert lib.gr_mlp_dataset(P, 16, 8, 4, 0.0, 1.0, 1.0, 1.0, None, P, None) == B.GR_EINVAL
+
+
+def test_mlp_kernel_descriptor_rules(lib):
+    from paper_1605_07023_amd import binding as B
+    k = B.make_kernel(1 << 20, 16, 8, 4, True, B.GR_F16, 0.0, 1.0, kind=B.GR_MLP)
+    st = lib.gr_preprocess(1 << 20, 1 << 20, B.GR_F32, None, None, 10, 4, ctypes.byref(k), 1.0, 1.0,
+                           64, 64, 1 << 20, 1 << 20, None, None)
+    assert st == B.GR_EUNSUPPORTED and "GR_MLP" in lib.gr_last_error().decode()
