@@ -133,6 +133,42 @@ def tuning_for(device_name: str, n_pol: int, support: int, kind: str, tap_dtype:
     return memo.get(memo_key(device_name, n_pol, support, kind, tap_dtype, side, variants))
 
 
+def batch_seg_lens(dws, memo: Optional[Memo] = None, max_vis: int = 131072, reps: int = 3) -> List[int]:
+    """Segment length per instance of a batch (gr_grid_batch items).  Instances
+    that share (n_pol, support, tap kind, tap dtype, grid side class) share one
+    tuning, swept on the first max_vis visibilities of the largest of them and
+    kept in the memo."""
+    import copy
+    memo = memo if memo is not None else Memo()
+    out, chosen = [], {}
+    name = torch.cuda.get_device_name(dws[0].uvw.device) if dws else ""
+    groups: Dict[str, list] = {}
+    for i, dw in enumerate(dws):
+        wl = dw.wl
+        key = memo_key(name, wl.n_pol, wl.support, wl.kernel, dw.tap_dtype, max(wl.height, wl.width), (2,))
+        groups.setdefault(key, []).append(i)
+    for key, members in groups.items():
+        hit = memo.get(key)
+        if hit is None:
+            big = max(members, key=lambda j: dws[j].wl.n_vis)
+            dw = dws[big]
+            if dw.wl.n_vis > max_vis:
+                wl = copy.copy(dw.wl)
+                wl.uvw, wl.vis = dw.wl.uvw[:max_vis], dw.wl.vis[:max_vis]
+                wl.weights = None if dw.wl.weights is None else dw.wl.weights[:max_vis]
+                dw = runner.upload(wl, dw.uvw.device, tap_dtype=dw.tap_dtype, taps=dw.taps)
+                dw.kernel = dws[big].kernel
+            best, times = tune(dw, candidates(dw.wl.n_pol, dw.wl.support, (2,)), reps)
+            memo.put(key, best, min(times))
+            hit = best
+        chosen[key] = hit.vis_per_wg
+    for i, dw in enumerate(dws):
+        wl = dw.wl
+        out.append(chosen[memo_key(name, wl.n_pol, wl.support, wl.kernel, dw.tap_dtype,
+                                   max(wl.height, wl.width), (2,))])
+    return out
+
+
 def main(argv=None) -> int:
     """Tune the full-shape geometry (first baselines only) for S = 16 and 32 and
     the tiny Kaiser-Bessel configuration; write the memo."""

@@ -202,3 +202,22 @@ def test_batch_empty_and_all_dropped(R):
     assert stats[1].cpu().tolist() == [0, 300]
     ref, _ = _oracle(wl)
     assert _rel(grids[0].cpu().numpy(), ref) <= 1e-5
+
+
+def test_batch_with_autotuned_segment_lengths(R, tmp_path):
+    """Per-instance segment lengths from the autotuner (one sweep per instance
+    class, remembered in a memo), then one batched call."""
+    from paper_1605_07023_amd import autotune
+    _say("batch with autotuned segment lengths")
+    wls, _ = _mixed()
+    dws = [R.upload(wl, DEV) for wl in wls]
+    memo = autotune.Memo(str(tmp_path / "memo.json"))
+    segs = autotune.batch_seg_lens(dws, memo)
+    assert len(segs) == len(wls) and all(s in autotune.SEG_LENS for s in segs)
+    assert len(memo.data) == len({(w.n_pol, w.support, w.kernel, max(w.height, w.width)) for w in wls})
+    again = autotune.batch_seg_lens(dws, memo)            # served from the memo
+    assert again == segs
+    grids, _ = R.grid_batch(dws, seg_lens=segs)
+    for wl, g in zip(wls, grids):
+        if wl.n_vis:
+            assert _rel(g.cpu().numpy(), _oracle(wl)[0]) <= 1e-5
