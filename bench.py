@@ -318,7 +318,8 @@ def main() -> int:
     if variant == 2:
         roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": FP32_MFMA_PEAK / 1e12,
                     "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK, "traffic": traffic,
-                    "kernel": f"grid_mfma_kernel<4, complex> (S={dom}), FP32 MFMA 16x16x4"}
+                    "kernel": f"grid_mfma_waves<4, complex, {48 if int(dom) <= 32 else 64}> (S={dom}), "
+                              "FP32 MFMA 16x16x4"}
     else:
         roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": FP32_VALU_PEAK / 1e12,
                     "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK, "traffic": traffic,

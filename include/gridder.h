@@ -127,9 +127,9 @@ size_t gr_bin_bytes(int64_t n_vis, int32_t n_pol, int32_t support, int32_t heigh
                     int32_t seg_len);
 
 /* Bin preprocessed visibilities by footprint position.  The grid is cut into
- * square tiles of T = 64 - S cells; each valid visibility goes to the tile that
- * holds its footprint origin (x0, y0), so every footprint of a tile lies in a
- * 64 x 64-cell window.  The input order (the baseline-ordered stream of
+ * square tiles of T = W - S cells, W = 32 for S <= 16, 48 for S <= 32, else 64;
+ * each valid visibility goes to the tile that holds its footprint origin
+ * (x0, y0), so every footprint of a tile lies in a W x W-cell window.  The input order (the baseline-ordered stream of
  * Section 4) is kept within each run of 64 consecutive visibilities of a
  * tile; each tile's list is cut into segments of at most seg_len entries.
  * bins (device, gr_bin_bytes) receives the reordered records, the reordered
@@ -139,11 +139,15 @@ gr_status gr_bin(const void* records, const void* wvis, int64_t n_vis, int32_t n
                  size_t bins_bytes, void* stream);
 
 /* Grid a binned stream (gr_bin output; the same n_vis, n_pol, support,
- * height, width and seg_len) onto grid (+=).  Per segment, the 64 x 64-cell
+ * height, width and seg_len) onto grid (+=).  Per segment, the W x W-cell
  * window is accumulated in matrix-core registers: the separable tile update
  * of Section 4, in the factored form G^u_i (G^v_j V_p) of Section 6, is a
  * rank-2 product per pair of visibilities (v_mfma_f32_16x16x4_f32), and the
  * window is added to the grid once with FP32 atomic adds (Section 2.2).
+ * The tap table is staged in LDS once per block: one 1024-thread block per
+ * compute unit whose 16 waves take (segment, row part) work from a counter in
+ * the bins workspace, or, when the table leaves too little LDS for that,
+ * one 256-thread block per segment.
  * support <= 56; the FP32 tap table [planes][O][S] must fit in 160 KiB.
  * With a GR_TABLE2D kernel the non-separable taps are read per visibility
  * from the [planes][O][O][S][S] table instead: each work-item keeps a 4 x 4

@@ -178,6 +178,7 @@ extern "C" gr_status gr_grid_batch(const gr_batch_item* items, int32_t n_items, 
   int n_members[kGroups] = {0, 0, 0, 0};
   size_t lds_group[kGroups] = {0, 0, 0, 0};
   int64_t segs_group[kGroups] = {0, 0, 0, 0};
+  int max_support[kGroups] = {0, 0, 0, 0};
   for (int i = 0; i < n_items; ++i) {
     const gr_batch_item& it = items[i];
     const BinLayout& L = p.bins[i];
@@ -228,6 +229,7 @@ extern "C" gr_status gr_grid_batch(const gr_batch_item* items, int32_t n_items, 
     I.group = g;
     ++n_members[g];
     lds_group[g] = std::max(lds_group[g], p.lds[i]);
+    max_support[g] = std::max(max_support[g], (int)it.kernel.support);
     segs_group[g] += L.max_segs;
   }
   for (int first = 0; first < n_items; first += kSetupChunk) {
@@ -247,7 +249,8 @@ extern "C" gr_status gr_grid_batch(const gr_batch_item* items, int32_t n_items, 
     if (n_members[g] == 0) continue;
     const int n_blocks = (int)std::min<int64_t>(resident, std::max<int64_t>(segs_group[g], 1));
     st = launch_mfma_persistent(table, members + g * n_items, n_members[g], prefix + g * (n_items + 1),
-                                counters + g, (g & 2) ? 4 : 1, (g & 1) != 0, lds_group[g], n_blocks, s);
+                                counters + g, (g & 2) ? 4 : 1, (g & 1) != 0, lds_group[g], max_support[g],
+                                n_blocks, s);
     if (st != GR_OK) return st;
   }
   return GR_OK;

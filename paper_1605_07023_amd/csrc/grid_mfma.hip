@@ -9,13 +9,12 @@
 // formed as G^u_i (G^v_j V_p) (Section 6).
 //
 // gfx950 form.  A segment holds visibilities whose footprints all lie inside
-// one 64 x 64-cell window.  The window's accumulators live in MFMA result
-// registers for the whole segment; each of the block's 4 waves owns a 16-row
-// band (P = 4: D tiles of 4 rows x 4 polarisations by 8 columns x (re, im);
-// P = 1: D tiles of 16 rows by 8 columns).  As in Section 4, records and
-// weighted visibilities are staged through LDS in batches, each work-item
-// loading its share; the tap table is staged once per block.
-// For a pair of visibilities v, the update of D tile (rows R, cols C) is
+// one window of WR x WR cells (WR = 32 for S <= 16, 48 for S <= 32, else 64;
+// the binning tile is WR - S).  The window is cut into row groups of RG rows
+// (P = 4: RG = 4, a D tile holds 4 rows x 4 polarisations; P = 1: RG = 16)
+// and column groups of 8 cells; a D tile of the MFMA holds one row group by
+// one column group, (re, im) interleaved along the columns.  For a pair of
+// visibilities v, the update of D tile (rows R, cols C) is
 //     D[(r, p), (x, re|im)] += sum_v A[(r, p), (v, re|im)] B[(v, re|im), (x, re|im)]
 // with A = G^v_v[r] V_{v,p} (the factor shared by a whole row) and B built from
 // G^u_v[x] so that the real product yields the complex one:
@@ -24,9 +23,24 @@
 // One v_mfma_f32_16x16x4_f32 therefore applies two visibilities to 32 cells
 // of P = 4 polarisations (or 128 cells of P = 1).  D tiles that neither
 // footprint touches are skipped by uniform branches; each lane builds one A
-// value per touched row group and one B value per touched column group.
-// The window is added to the grid once per segment with FP32 atomic adds,
-// skipping cells that received nothing.
+// value per touched row group and one B value per column group.  The window
+// is added to the grid with FP32 atomic adds, skipping cells that received
+// nothing.
+//
+// Three launch forms share that update:
+//  * grid_mfma_waves (single problem, default): one 1024-thread block per CU
+//    stages the tap table once (Section 4 stages the GCF in local memory);
+//    its 16 waves then work without block barriers, each taking
+//    (segment, part) items from an atomic counter, where part p of a window is
+//    the row groups p, p + parts, p + 2 parts, ...  Each wave stages its own
+//    batches of 64 visibilities in its own LDS slice.
+//  * grid_mfma_kernel: one 256-thread block per segment, its 4 waves sharing
+//    the segment's window rows (the form used when the table leaves too little
+//    LDS for 16 wave slices).
+//  * grid_mfma_persistent (batches): blocks of the second form taking
+//    (instance, segment) items from an atomic counter.
+#include <algorithm>
+
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
@@ -46,17 +60,14 @@ __device__ inline float load_tap32(const void* __restrict__ t, int64_t idx, int 
   }
 }
 
-// Four waves per block share one segment.  The 64-row window is cut into row
-// groups of RG rows (P = 4: RG = 4, a D tile holds 4 rows x 4 polarisations;
-// P = 1: RG = 16); wave w owns row groups w, w + 4, w + 8, ... so that every
-// footprint gives the four waves (and the four SIMDs) nearly equal work.
-constexpr int kBatch = 256;        // visibilities staged in LDS per batch
-constexpr int kWin = 64;           // window edge (cells)
-constexpr int kNC = 8;             // column groups of 8 cells per window
+constexpr int kBatch = 256;        // visibilities staged per batch (block forms)
+constexpr int kWaveBatch = 64;     // visibilities staged per batch (wave form)
+constexpr int kWaveThreads = 1024; // wave form: 16 waves per block
 
 template <bool CPLX>
 using TapT = typename std::conditional<CPLX, float2, float>::type;
 
+// clamp to [-1, S] and shift by one: rows carry a zero before and after the S taps
 __device__ __forceinline__ int clamp_tap(int tap, int S) { return min(max(tap, -1), S) + 1; }
 
 // B fragment (lane: K = (v, comp), N = (x, bcomp)) from a tap g of G^u:
@@ -64,7 +75,7 @@ __device__ __forceinline__ int clamp_tap(int tap, int S) { return min(max(tap, -
 template <bool CPLX>
 __device__ __forceinline__ float b_value(const TapT<CPLX>* row, int tap, int S, bool sel_re,
                                          float sgn) {
-  const int idx = clamp_tap(tap, S);                 // rows are zero-padded at 0 and S + 1
+  const int idx = clamp_tap(tap, S);
   if constexpr (CPLX) {
     const float2 t = row[idx];
     return sel_re ? t.x : sgn * t.y;
@@ -94,26 +105,19 @@ __device__ __forceinline__ void stage_taps(TapT<CPLX>* __restrict__ lds, const v
   }
 }
 
-// One segment sg = {begin, length, tile} of the binned stream (rec, wvis) into
-// grid, with the staged table lds and the batch buffers b_rec, b_vis.  The
-// first statement of every batch is a block barrier, which also orders the
-// table staging before its first use.
-template <int P, bool CPLX>
-__device__ __forceinline__ void mfma_segment(const Record* __restrict__ rec,
-                                             const float2* __restrict__ wvis, const int4 sg,
-                                             const TapT<CPLX>* __restrict__ lds,
-                                             Record* __restrict__ b_rec, float2* __restrict__ b_vis,
-                                             float2* __restrict__ grid, const MfmaDev& d) {
-  constexpr int RG = 16 / P;            // rows per row group
-  constexpr int NG = kWin / RG / 4;     // row groups per wave
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+// The work of one wave on one batch of a segment: the window rows of the NG
+// row groups whose first rows are row0 + j * GSTRIDE (j < NG), all WCG column
+// groups of the window at columns win_x0 + 8 c.  b_rec / b_vis hold nb
+// staged visibilities.
+template <int P, bool CPLX, int WCG, int NG, int GSTRIDE>
+__device__ __forceinline__ void mfma_batch(const Record* __restrict__ b_rec,
+                                           const float2* __restrict__ b_vis, int nb,
+                                           const TapT<CPLX>* __restrict__ lds, int row0, int win_x0,
+                                           const MfmaDev& d, f4 (&acc)[NG][WCG]) {
+  constexpr int RG = 16 / P;
+  const int lane = threadIdx.x & 63;
   const int S = d.S, SP = d.S + 2;
-  const int begin = sg.x, len = sg.y, tile_id = sg.z;
-  const int win_x0 = (tile_id % d.n_tx) * d.tile;
-  const int win_y0 = (tile_id / d.n_tx) * d.tile;
-  const int row0 = win_y0 + wave * RG;                // first row of this wave's first row group
   const int srow0 = __builtin_amdgcn_readfirstlane(row0);
-
   // lane roles in the 16x16x4 operand layouts
   const int kk = lane >> 4;              // K index: (v, re|im)
   const int v = kk >> 1, comp = kk & 1;
@@ -123,12 +127,120 @@ __device__ __forceinline__ void mfma_segment(const Record* __restrict__ rec,
   const int bx = m >> 1, bcomp = m & 1;
   const bool sel_re = comp == bcomp;
   const float sgn = comp == 0 ? 1.f : -1.f;
+  for (int q = 0; q < nb; q += 2) {
+    const bool hb = q + 1 < nb;
+    const Record la = b_rec[q];
+    const Record lb = b_rec[hb ? q + 1 : q];
+    // the pair's records are wave-uniform: move them to scalar registers
+    const Record ra{(uint32_t)__builtin_amdgcn_readfirstlane(la.x),
+                    (uint32_t)__builtin_amdgcn_readfirstlane(la.y)};
+    const Record rb{(uint32_t)__builtin_amdgcn_readfirstlane(lb.x),
+                    (uint32_t)__builtin_amdgcn_readfirstlane(lb.y)};
+    const int xa = rec_x0(ra), ya = rec_y0(ra), xb = rec_x0(rb), yb = rec_y0(rb);
+    const int lo = min(ya, yb), hi = max(ya, yb) + S - 1;
+    const int c_lo = (min(xa, xb) - win_x0) >> 3;
+    const int c_hi = (max(xa, xb) + S - 1 - win_x0) >> 3;
 
-  f4 acc[NG][kNC];
+    // this lane's visibility of the pair (a missing second one has V = 0)
+    const Record rv = v ? rb : ra;
+    const int x0v = rec_x0(rv), y0v = rec_y0(rv);
+    const int tabu = (rec_plane(rv) * d.O + rec_sx(rv)) * SP;
+    const int tabv = (rec_plane(rv) * d.O + rec_sy(rv)) * SP;
+    const float2 vv = ((v == 0) || hb) ? b_vis[(q + v) * P + ap] : make_float2(0.f, 0.f);
+    // A = G^v V: component 0 is t.x vr - t.y vi, component 1 is t.x vi + t.y vr
+    const float va = comp == 0 ? vv.x : vv.y;
+    const float vb = comp == 0 ? -vv.y : vv.x;
+
+    // A fragments for this wave's row groups and B fragments for every column
+    // group, branch-free (all LDS reads in flight together)
+    float afr[NG];
+#pragma unroll
+    for (int j = 0; j < NG; ++j) {
+      const int idx = clamp_tap(row0 + j * GSTRIDE + ar - y0v, S);
+      if constexpr (CPLX) {
+        const float2 t = lds[tabv + idx];
+        afr[j] = t.x * va + t.y * vb;                 // component of G^v V
+      } else {
+        afr[j] = lds[tabv + idx] * va;
+      }
+    }
+    float bfr[WCG];
+#pragma unroll
+    for (int c = 0; c < WCG; ++c)
+      bfr[c] = b_value<CPLX>(lds + tabu, win_x0 + c * 8 + bx - x0v, S, sel_re, sgn);
+    // wave-uniform masks of the D tiles either footprint touches
+    uint32_t rmask = 0;
+#pragma unroll
+    for (int j = 0; j < NG; ++j) {
+      const int r0 = srow0 + j * GSTRIDE;
+      rmask |= (r0 + RG - 1 >= lo && r0 <= hi) ? (1u << j) : 0u;
+    }
+    const uint32_t cmask = ((2u << c_hi) - 1u) & ~((1u << c_lo) - 1u);
+#pragma unroll
+    for (int j = 0; j < NG; ++j) {
+      if (__builtin_expect((rmask >> j) & 1u, 1)) {
+#pragma unroll
+        for (int c = 0; c < WCG; ++c) {
+          if (__builtin_expect((cmask >> c) & 1u, 1))
+            acc[j][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[j], bfr[c], acc[j][c], 0, 0, 0);
+        }
+      }
+    }
+  }
+}
+
+// Add a wave's window rows to the grid (D layout: lane holds rows 4 (lane / 16) + i,
+// column lane % 16 of each tile).
+template <int P, int WCG, int NG, int GSTRIDE>
+__device__ __forceinline__ void flush_window(const f4 (&acc)[NG][WCG], int row0, int win_x0,
+                                             float2* __restrict__ grid, const MfmaDev& d) {
+  const int lane = threadIdx.x & 63;
+  const int kk = lane >> 4, m = lane & 15;
+  float* gridf = reinterpret_cast<float*>(grid);
+  const int col_in = m >> 1, ccomp = m & 1;
+#pragma unroll
+  for (int j = 0; j < NG; ++j) {
+#pragma unroll
+    for (int c = 0; c < WCG; ++c) {
+      const int col = win_x0 + c * 8 + col_in;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = (P == 4) ? kk : 4 * kk + i;
+        const int p = (P == 4) ? i : 0;
+        const int row = row0 + j * GSTRIDE + r;
+        const float val = acc[j][c][i];
+        if (val != 0.f && row < d.H && col < d.W)
+          unsafeAtomicAdd(gridf + (((int64_t)p * d.H + row) * d.W + col) * 2 + ccomp, val);
+      }
+    }
+  }
+}
+
+// Block form: the 4 waves of a 256-thread block share one segment; wave w owns
+// row groups w, w + 4, w + 8, ... so that every footprint gives the four waves
+// (and the four SIMDs) nearly equal work.  Batches of 256 visibilities are
+// staged by the whole block; the first statement of every batch is a block
+// barrier, which also orders the table staging before its first use.
+template <int P, bool CPLX, int WR, int WCG>
+__device__ __forceinline__ void mfma_segment(const Record* __restrict__ rec,
+                                             const float2* __restrict__ wvis, const int4 sg,
+                                             const TapT<CPLX>* __restrict__ lds,
+                                             Record* __restrict__ b_rec, float2* __restrict__ b_vis,
+                                             float2* __restrict__ grid, const MfmaDev& d) {
+  constexpr int RG = 16 / P;            // rows per row group
+  constexpr int NG = WR / RG / 4;       // row groups per wave
+  static_assert(NG * RG * 4 == WR, "window rows must split into row groups over 4 waves");
+  const int wave = threadIdx.x >> 6;
+  const int begin = sg.x, len = sg.y, tile_id = sg.z;
+  const int win_x0 = (tile_id % d.n_tx) * d.tile;
+  const int win_y0 = (tile_id / d.n_tx) * d.tile;
+  const int row0 = win_y0 + wave * RG;                // first row of this wave's first row group
+
+  f4 acc[NG][WCG];
 #pragma unroll
   for (int j = 0; j < NG; ++j)
 #pragma unroll
-    for (int c = 0; c < kNC; ++c) acc[j][c] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int c = 0; c < WCG; ++c) acc[j][c] = f4{0.f, 0.f, 0.f, 0.f};
 
   for (int b0 = 0; b0 < len; b0 += kBatch) {
     const int nb = min(kBatch, len - b0);
@@ -149,91 +261,12 @@ __device__ __forceinline__ void mfma_segment(const Record* __restrict__ rec,
         if (t + j * 256 < nb * P) b_vis[t + j * 256] = w[j];
     }
     __syncthreads();
-
-    for (int q = 0; q < nb; q += 2) {
-      const bool hb = q + 1 < nb;
-      const Record la = b_rec[q];
-      const Record lb = b_rec[hb ? q + 1 : q];
-      // the pair's records are wave-uniform: move them to scalar registers
-      const Record ra{(uint32_t)__builtin_amdgcn_readfirstlane(la.x),
-                      (uint32_t)__builtin_amdgcn_readfirstlane(la.y)};
-      const Record rb{(uint32_t)__builtin_amdgcn_readfirstlane(lb.x),
-                      (uint32_t)__builtin_amdgcn_readfirstlane(lb.y)};
-      const int xa = rec_x0(ra), ya = rec_y0(ra), xb = rec_x0(rb), yb = rec_y0(rb);
-      const int lo = min(ya, yb), hi = max(ya, yb) + S - 1;
-      const int c_lo = (min(xa, xb) - win_x0) >> 3;
-      const int c_hi = (max(xa, xb) + S - 1 - win_x0) >> 3;
-
-      // this lane's visibility of the pair (a missing second one has V = 0)
-      const Record rv = v ? rb : ra;
-      const int x0v = rec_x0(rv), y0v = rec_y0(rv);
-      const int tabu = (rec_plane(rv) * d.O + rec_sx(rv)) * SP;
-      const int tabv = (rec_plane(rv) * d.O + rec_sy(rv)) * SP;
-      const float2 vv = ((v == 0) || hb) ? b_vis[(q + v) * P + ap] : make_float2(0.f, 0.f);
-      // A = G^v V: component 0 is t.x vr - t.y vi, component 1 is t.x vi + t.y vr
-      const float va = comp == 0 ? vv.x : vv.y;
-      const float vb = comp == 0 ? -vv.y : vv.x;
-
-      // A fragments for this wave's row groups and B fragments for every column
-      // group, branch-free (all LDS reads in flight together)
-      float afr[NG];
-#pragma unroll
-      for (int j = 0; j < NG; ++j) {
-        const int idx = clamp_tap(row0 + j * 4 * RG + ar - y0v, S);
-        if constexpr (CPLX) {
-          const float2 t = lds[tabv + idx];
-          afr[j] = t.x * va + t.y * vb;                 // component of G^v V
-        } else {
-          afr[j] = lds[tabv + idx] * va;
-        }
-      }
-      float bfr[kNC];
-#pragma unroll
-      for (int c = 0; c < kNC; ++c)
-        bfr[c] = b_value<CPLX>(lds + tabu, win_x0 + c * 8 + bx - x0v, S, sel_re, sgn);
-      // wave-uniform mask of the D tiles either footprint touches
-      uint32_t rmask = 0;
-#pragma unroll
-      for (int j = 0; j < NG; ++j) {
-        const int r0 = srow0 + j * 4 * RG;
-        rmask |= (r0 + RG - 1 >= lo && r0 <= hi) ? (1u << j) : 0u;
-      }
-      const uint32_t cmask = ((2u << c_hi) - 1u) & ~((1u << c_lo) - 1u);
-#pragma unroll
-      for (int j = 0; j < NG; ++j) {
-        if (rmask & (1u << j)) {
-#pragma unroll
-          for (int c = 0; c < kNC; ++c) {
-            if (cmask & (1u << c))
-              acc[j][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[j], bfr[c], acc[j][c], 0, 0, 0);
-          }
-        }
-      }
-    }
+    mfma_batch<P, CPLX, WCG, NG, 4 * RG>(b_rec, b_vis, nb, lds, row0, win_x0, d, acc);
   }
-
-  // ---- add the window to the grid (D layout: lane holds rows 4*(lane>>4)+i, column lane&15)
-  float* gridf = reinterpret_cast<float*>(grid);
-  const int col_in = m >> 1, ccomp = m & 1;
-#pragma unroll
-  for (int j = 0; j < NG; ++j) {
-#pragma unroll
-    for (int c = 0; c < kNC; ++c) {
-      const int col = win_x0 + c * 8 + col_in;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int r = (P == 4) ? kk : 4 * kk + i;
-        const int p = (P == 4) ? i : 0;
-        const int row = row0 + j * 4 * RG + r;
-        const float val = acc[j][c][i];
-        if (val != 0.f && row < d.H && col < d.W)
-          unsafeAtomicAdd(gridf + (((int64_t)p * d.H + row) * d.W + col) * 2 + ccomp, val);
-      }
-    }
-  }
+  flush_window<P, WCG, NG, 4 * RG>(acc, row0, win_x0, grid, d);
 }
 
-template <int P, bool CPLX>
+template <int P, bool CPLX, int WR, int WCG>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 grid_mfma_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvis,
                  const int4* __restrict__ segs, const int32_t* __restrict__ n_segs_p,
@@ -250,15 +283,74 @@ grid_mfma_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvis
   const int seg = (int)blockIdx.x;
   if (seg >= *n_segs_p) return;                       // uniform for the block
   stage_taps<CPLX>(lds, taps, d);
-  mfma_segment<P, CPLX>(rec, wvis, segs[seg], lds, b_rec, b_vis, grid, d);
+  mfma_segment<P, CPLX, WR, WCG>(rec, wvis, segs[seg], lds, b_rec, b_vis, grid, d);
 }
 
-// Persistent form for batches: a fixed set of blocks takes (instance, segment)
-// work items from an atomic counter until the group's items run out; the tap
-// table is restaged only when the instance changes.  Every block exits once
-// the counter passes the item total, which the prefix kernel wrote before
+// Wave form (see the file header).  PARTS = (WR / RG) / NG items per segment.
+template <int P, bool CPLX, int WR, int WCG, int NG>
+__global__ void __launch_bounds__(kWaveThreads)
+grid_mfma_waves(const Record* __restrict__ rec, const float2* __restrict__ wvis,
+                const int4* __restrict__ segs, const int32_t* __restrict__ n_segs_p,
+                int32_t* __restrict__ counter, const void* __restrict__ taps,
+                float2* __restrict__ grid, MfmaDev d, uint32_t tap_bytes) {
+  constexpr int RG = 16 / P;
+  constexpr int PARTS = WR / RG / NG;
+  static_assert(PARTS * NG * RG == WR, "window rows must split into parts of NG row groups");
+  using Tap = TapT<CPLX>;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  Tap* lds = reinterpret_cast<Tap*>(lds_raw);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  Record* b_rec = reinterpret_cast<Record*>(lds_raw + tap_bytes +
+                                            (size_t)wave * kWaveBatch * (sizeof(Record) + P * sizeof(float2)));
+  float2* b_vis = reinterpret_cast<float2*>(b_rec + kWaveBatch);
+  stage_taps<CPLX>(lds, taps, d);
+  __syncthreads();                                    // the only block barrier
+  const int n_items = *n_segs_p * PARTS;
+  for (;;) {
+    int item = 0;
+    if (lane == 0) item = atomicAdd(counter, 1);
+    item = __builtin_amdgcn_readlane(item, 0);
+    if (item >= n_items) break;                        // wave-uniform; every wave reaches it
+    const int seg = item / PARTS, part = item - seg * PARTS;
+    const int4 sg = segs[seg];
+    const int begin = sg.x, len = sg.y, tile_id = sg.z;
+    const int win_x0 = (tile_id % d.n_tx) * d.tile;
+    const int win_y0 = (tile_id / d.n_tx) * d.tile;
+    const int row0 = win_y0 + part * RG;
+    f4 acc[NG][WCG];
+#pragma unroll
+    for (int j = 0; j < NG; ++j)
+#pragma unroll
+      for (int c = 0; c < WCG; ++c) acc[j][c] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int b0 = 0; b0 < len; b0 += kWaveBatch) {
+      const int nb = min(kWaveBatch, len - b0);
+      // the wave's own slice: LDS operations of one wave execute in order, so
+      // only the compiler must be kept from moving accesses across these points
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      const Record r = lane < nb ? rec[begin + b0 + lane] : Record{0, 0};
+      float2 w[P];
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        const int e = lane + j * 64;
+        w[j] = e < nb * P ? wvis[(int64_t)(begin + b0) * P + e] : make_float2(0.f, 0.f);
+      }
+      if (lane < nb) b_rec[lane] = r;
+#pragma unroll
+      for (int j = 0; j < P; ++j)
+        if (lane + j * 64 < nb * P) b_vis[lane + j * 64] = w[j];
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      mfma_batch<P, CPLX, WCG, NG, PARTS * RG>(b_rec, b_vis, nb, lds, row0, win_x0, d, acc);
+    }
+    flush_window<P, WCG, NG, PARTS * RG>(acc, row0, win_x0, grid, d);
+  }
+}
+
+// Persistent block form for batches: a fixed set of blocks takes (instance,
+// segment) work items from an atomic counter until the group's items run out;
+// the tap table is restaged only when the instance changes.  Every block exits
+// once the counter passes the item total, which the prefix kernel wrote before
 // this launch.
-template <int P, bool CPLX>
+template <int P, bool CPLX, int WR, int WCG>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 grid_mfma_persistent(const BatchInst* __restrict__ inst, const int32_t* __restrict__ members,
                      int n_members, const int32_t* __restrict__ prefix,
@@ -297,23 +389,85 @@ grid_mfma_persistent(const BatchInst* __restrict__ inst, const int32_t* __restri
       stage_taps<CPLX>(lds, I.taps, d);
       staged = ii;
     }
-    mfma_segment<P, CPLX>(I.brec, I.bwvis, I.segs[ls], lds, b_rec, b_vis, I.grid, d);
+    mfma_segment<P, CPLX, WR, WCG>(I.brec, I.bwvis, I.segs[ls], lds, b_rec, b_vis, I.grid, d);
   }
 }
 
+__global__ void __launch_bounds__(64) zero_counter(int32_t* c) {
+  if (threadIdx.x == 0) *c = 0;
+}
 
 using MfmaFn = void (*)(const Record*, const float2*, const int4*, const int32_t*, const void*,
                         float2*, MfmaDev);
+using WaveFn = void (*)(const Record*, const float2*, const int4*, const int32_t*, int32_t*,
+                        const void*, float2*, MfmaDev, uint32_t);
+using PersistFn = void (*)(const BatchInst*, const int32_t*, int, const int32_t*, int32_t*);
+
+// window edge (cells) for a support: footprints of a tile of edge WR - S fit it
+int window_of(int support) { return support <= 16 ? 32 : support <= 32 ? 48 : 64; }
+
+// Block forms: 4 waves share the window rows, so P = 1 (16-row groups) needs 64 rows.
+template <int P, bool CPLX>
+MfmaFn block_fn(int wr) {
+  if constexpr (P == 4) {
+    if (wr == 32) return grid_mfma_kernel<4, CPLX, 32, 4>;
+    if (wr == 48) return grid_mfma_kernel<4, CPLX, 48, 6>;
+  }
+  return grid_mfma_kernel<P, CPLX, 64, 8>;
+}
+
+template <int P, bool CPLX>
+PersistFn persist_fn(int wr) {
+  if constexpr (P == 4) {
+    if (wr == 32) return grid_mfma_persistent<4, CPLX, 32, 4>;
+    if (wr == 48) return grid_mfma_persistent<4, CPLX, 48, 6>;
+  }
+  return grid_mfma_persistent<P, CPLX, 64, 8>;
+}
+
+// Wave-form configurations: NG row groups per wave, chosen so that the
+// accumulators (NG x WCG x 4 registers) leave room for 4 waves per SIMD.
+template <int P, bool CPLX>
+WaveFn wave_fn(int wr) {
+  if constexpr (P == 4) {
+    if (wr == 32) return grid_mfma_waves<4, CPLX, 32, 4, 2>;
+    if (wr == 48) return grid_mfma_waves<4, CPLX, 48, 6, 3>;
+    return grid_mfma_waves<4, CPLX, 64, 8, 2>;
+  } else {
+    if (wr == 32) return grid_mfma_waves<1, CPLX, 32, 4, 1>;
+    if (wr == 48) return grid_mfma_waves<1, CPLX, 48, 6, 1>;
+    return grid_mfma_waves<1, CPLX, 64, 8, 1>;
+  }
+}
+
+int wave_parts(int n_pol, int wr) {
+  const int rg = 16 / n_pol;
+  const int ng = n_pol == 4 ? (wr == 48 ? 3 : 2) : 1;
+  return wr / rg / ng;
+}
+
+size_t tap_lds_bytes(const gr_kernel& k) {
+  return align256((size_t)k.n_planes * k.oversample * (k.support + 2) * (k.taps_complex ? 8 : 4));
+}
+
+int g_cus = 0;
+
+int device_cus() {
+  if (g_cus > 0) return g_cus;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+    g_cus = cus;
+  return g_cus > 0 ? g_cus : 256;
+}
 
 }  // namespace
 
-int binned_tile(int support) { return 64 - support; }
+int binned_tile(int support) { return window_of(support) - support; }
 
 gr_status plan_mfma(const gr_kernel& k, int n_pol, size_t* lds_bytes) {
   if (k.support > 56) return fail(GR_EUNSUPPORTED, "MFMA gridder needs support <= 56");
-  const size_t elem = k.taps_complex ? 8 : 4;
-  const size_t lds = (size_t)k.n_planes * k.oversample * (k.support + 2) * elem +
-                     (size_t)kBatch * (sizeof(Record) + (size_t)n_pol * sizeof(float2));
+  const size_t lds = tap_lds_bytes(k) + (size_t)kBatch * (sizeof(Record) + (size_t)n_pol * sizeof(float2));
   if (lds > 160 * 1024) return fail(GR_EUNSUPPORTED, "tap table does not fit in LDS");
   *lds_bytes = lds;
   return GR_OK;
@@ -333,16 +487,33 @@ gr_status launch_mfma(const void* bins, const BinLayout& L, int n_pol, const gr_
   d.S = k.support; d.O = k.oversample; d.n_rows_tab = k.n_planes * k.oversample;
   d.tap_dtype = k.tap_dtype; d.tile = L.tile; d.n_tx = L.n_tx; d.H = height; d.W = width;
   const int64_t nb = L.max_segs;
-  if (nb > 0x7fffffff) return fail(GR_EINVAL, "too many segments");
+  if (nb > 0x7fffffff / 8) return fail(GR_EINVAL, "too many segments");
   if (nb == 0) return GR_OK;
   d.n_blocks = (uint32_t)nb;
-  MfmaFn fn;
-  if (n_pol == 4) fn = k.taps_complex ? grid_mfma_kernel<4, true> : grid_mfma_kernel<4, false>;
-  else fn = k.taps_complex ? grid_mfma_kernel<1, true> : grid_mfma_kernel<1, false>;
-  {
-    const gr_status lst = ensure_lds_limit(reinterpret_cast<const void*>(fn), lds, "grid_mfma.hip");
-    if (lst != GR_OK) return lst;
+  const int wr = window_of(k.support);
+  if (L.tile + k.support > wr) return fail(GR_EINVAL, "binning tile does not fit the gridder window");
+  // wave form when the table leaves room for 16 wave slices
+  const size_t wave_lds =
+      tap_lds_bytes(k) + (size_t)(kWaveThreads / 64) * kWaveBatch * (sizeof(Record) + n_pol * sizeof(float2));
+  if (wave_lds <= 160 * 1024) {
+    WaveFn fn;
+    if (n_pol == 4) fn = k.taps_complex ? wave_fn<4, true>(wr) : wave_fn<4, false>(wr);
+    else fn = k.taps_complex ? wave_fn<1, true>(wr) : wave_fn<1, false>(wr);
+    if ((st = ensure_lds_limit(reinterpret_cast<const void*>(fn), wave_lds, "gr_grid_binned")) != GR_OK)
+      return st;
+    // the work counter sits after the segment count in the bins workspace
+    int32_t* counter = const_cast<int32_t*>(nsegs) + 16;
+    zero_counter<<<1, 64, 0, stream>>>(counter);
+    const int64_t items = nb * wave_parts(n_pol, wr);
+    const int blocks = (int)std::min<int64_t>(device_cus(), (items + 15) / 16);
+    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kWaveThreads), wave_lds, stream, rec, wv, segs,
+                       nsegs, counter, k.taps, grid, d, (uint32_t)tap_lds_bytes(k));
+    return check_launch("gr_grid_binned (mfma waves)");
   }
+  MfmaFn fn;
+  if (n_pol == 4) fn = k.taps_complex ? block_fn<4, true>(wr) : block_fn<4, false>(wr);
+  else fn = k.taps_complex ? block_fn<1, true>(wr) : block_fn<1, false>(wr);
+  if ((st = ensure_lds_limit(reinterpret_cast<const void*>(fn), lds, "gr_grid_binned")) != GR_OK) return st;
   hipLaunchKernelGGL(fn, dim3((unsigned)nb), dim3(256), lds, stream, rec, wv, segs, nsegs, k.taps,
                      grid, d);
   return check_launch("gr_grid_binned (mfma)");
@@ -350,17 +521,15 @@ gr_status launch_mfma(const void* bins, const BinLayout& L, int n_pol, const gr_
 
 gr_status launch_mfma_persistent(const BatchInst* inst, const int32_t* members, int n_members,
                                  const int32_t* group_prefix, int32_t* counter, int n_pol,
-                                 bool complex_taps, size_t lds_bytes, int n_blocks,
+                                 bool complex_taps, size_t lds_bytes, int max_support, int n_blocks,
                                  hipStream_t stream) {
   if (n_members == 0 || n_blocks <= 0) return GR_OK;
-  using PFn = void (*)(const BatchInst*, const int32_t*, int, const int32_t*, int32_t*);
-  PFn fn;
-  if (n_pol == 4) fn = complex_taps ? grid_mfma_persistent<4, true> : grid_mfma_persistent<4, false>;
-  else fn = complex_taps ? grid_mfma_persistent<1, true> : grid_mfma_persistent<1, false>;
-  {
-    const gr_status lst = ensure_lds_limit(reinterpret_cast<const void*>(fn), lds_bytes, "grid_mfma.hip");
-    if (lst != GR_OK) return lst;
-  }
+  const int wr = window_of(max_support);
+  PersistFn fn;
+  if (n_pol == 4) fn = complex_taps ? persist_fn<4, true>(wr) : persist_fn<4, false>(wr);
+  else fn = complex_taps ? persist_fn<1, true>(wr) : persist_fn<1, false>(wr);
+  gr_status st = ensure_lds_limit(reinterpret_cast<const void*>(fn), lds_bytes, "gr_grid_batch");
+  if (st != GR_OK) return st;
   hipLaunchKernelGGL(fn, dim3((unsigned)n_blocks), dim3(256), lds_bytes, stream, inst, members, n_members,
                      group_prefix, counter);
   return check_launch("gr_grid_batch (persistent mfma)");

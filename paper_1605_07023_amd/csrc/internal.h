@@ -69,7 +69,9 @@ struct BinLayout {
   int64_t n_tiles, max_segs;
   size_t off_rec, off_wvis, off_count, off_cursor, off_segs, off_nsegs, bytes;
 };
-int binned_tile(int support);   // tile edge T (cells): every footprint of the tile fits 64 cells
+// tile edge T (cells): footprints of a tile fit the MFMA gridder's window of T + S
+// cells (32, 48 or 64), and always the 64-cell window of the other binned gridders
+int binned_tile(int support);
 BinLayout bin_layout(int64_t n_vis, int n_pol, int support, int height, int width, int seg_len);
 gr_status launch_bin(const Record* rec, const float2* wvis, int64_t n_vis, int n_pol,
                      const BinLayout& L, void* bins, hipStream_t stream);
@@ -148,9 +150,10 @@ gr_status launch_batch_bin(const BatchInst* inst, int n_inst, int64_t total_bloc
 // Persistent MFMA gridder over the segments of the instances `members`
 // (group_prefix: [n_members + 1] exclusive prefix of their segment counts,
 // written on the device; counter: zeroed work counter).
+// max_support: the largest support among the members (it sets the window).
 gr_status launch_mfma_persistent(const BatchInst* inst, const int32_t* members, int n_members,
                                  const int32_t* group_prefix, int32_t* counter, int n_pol,
-                                 bool complex_taps, size_t lds_bytes, int n_blocks,
+                                 bool complex_taps, size_t lds_bytes, int max_support, int n_blocks,
                                  hipStream_t stream);
 
 }  // namespace gr

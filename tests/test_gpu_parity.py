@@ -182,7 +182,7 @@ def test_bin_is_a_grouping_of_the_valid_stream(R):
     # records can repeat in principle; this draw has unique records
     assert len(order) == nv
     np.testing.assert_array_equal(w_out, w_in[[order[int(k)] for k in r_out]])
-    T = 64 - S
+    T = (32 if S <= 16 else 48 if S <= 32 else 64) - S      # the binning tile documented for gr_bin
     n_tx, n_ty = -(-192 // T), -(-256 // T)
     off = off_w + (32 * wl.n_vis + 255) // 256 * 256
     off += 2 * ((4 * n_tx * n_ty + 255) // 256 * 256)
