@@ -29,8 +29,9 @@
 //
 // Three launch forms share that update:
 //  * grid_mfma_waves (single problem, default): one 1024-thread block per CU
-//    stages the tap table once (Section 4 stages the GCF in local memory);
-//    its 16 waves then work without block barriers, each taking
+//    (two 768-thread blocks for the 32-cell window) stages the tap table once
+//    (Section 4 stages the GCF in local memory); its waves then work without
+//    block barriers, each taking
 //    (segment, part) items from an atomic counter, where part p of a window is
 //    the row groups p, p + parts, p + 2 parts, ...  Each wave stages its own
 //    batches of 64 visibilities in its own LDS slice.
@@ -62,13 +63,17 @@ __device__ inline float load_tap32(const void* __restrict__ t, int64_t idx, int 
 
 constexpr int kBatch = 256;        // visibilities staged per batch (block forms)
 constexpr int kWaveBatch = 64;     // visibilities staged per batch (wave form)
-constexpr int kWaveThreads = 1024; // wave form: 16 waves per block
 
 template <bool CPLX>
 using TapT = typename std::conditional<CPLX, float2, float>::type;
 
 // clamp to [-1, S] and shift by one: rows carry a zero before and after the S taps
-__device__ __forceinline__ int clamp_tap(int tap, int S) { return min(max(tap, -1), S) + 1; }
+// (one v_med3_i32 instead of a max and a min)
+__device__ __forceinline__ int clamp_tap(int tap, int S) {
+  int r;
+  asm("v_med3_i32 %0, %1, -1, %2" : "=v"(r) : "v"(tap), "s"(S));
+  return r + 1;
+}
 
 // B fragment (lane: K = (v, comp), N = (x, bcomp)) from a tap g of G^u:
 //   (comp, bcomp) = (0,0): Re g, (0,1): Im g, (1,0): -Im g, (1,1): Re g.
@@ -287,8 +292,8 @@ grid_mfma_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvis
 }
 
 // Wave form (see the file header).  PARTS = (WR / RG) / NG items per segment.
-template <int P, bool CPLX, int WR, int WCG, int NG>
-__global__ void __launch_bounds__(kWaveThreads)
+template <int P, bool CPLX, int WR, int WCG, int NG, int THREADS>
+__global__ void __launch_bounds__(THREADS)
 grid_mfma_waves(const Record* __restrict__ rec, const float2* __restrict__ wvis,
                 const int4* __restrict__ segs, const int32_t* __restrict__ n_segs_p,
                 int32_t* __restrict__ counter, const void* __restrict__ taps,
@@ -401,6 +406,14 @@ using MfmaFn = void (*)(const Record*, const float2*, const int4*, const int32_t
                         float2*, MfmaDev);
 using WaveFn = void (*)(const Record*, const float2*, const int4*, const int32_t*, int32_t*,
                         const void*, float2*, MfmaDev, uint32_t);
+
+// Wave-form launch shape per window: threads per block and blocks per CU.  The
+// 32-cell window's kernel needs few registers and a small table, so two
+// 768-thread blocks share a CU (24 waves); the others run one 1024-thread block.
+struct WaveShape {
+  int threads, blocks_per_cu;
+};
+WaveShape wave_shape(int wr) { return wr == 32 ? WaveShape{768, 2} : WaveShape{1024, 1}; }
 using PersistFn = void (*)(const BatchInst*, const int32_t*, int, const int32_t*, int32_t*);
 
 // window edge (cells) for a support: footprints of a tile of edge WR - S fit it
@@ -430,13 +443,13 @@ PersistFn persist_fn(int wr) {
 template <int P, bool CPLX>
 WaveFn wave_fn(int wr) {
   if constexpr (P == 4) {
-    if (wr == 32) return grid_mfma_waves<4, CPLX, 32, 4, 2>;
-    if (wr == 48) return grid_mfma_waves<4, CPLX, 48, 6, 3>;
-    return grid_mfma_waves<4, CPLX, 64, 8, 2>;
+    if (wr == 32) return grid_mfma_waves<4, CPLX, 32, 4, 2, 768>;
+    if (wr == 48) return grid_mfma_waves<4, CPLX, 48, 6, 3, 1024>;
+    return grid_mfma_waves<4, CPLX, 64, 8, 2, 1024>;
   } else {
-    if (wr == 32) return grid_mfma_waves<1, CPLX, 32, 4, 1>;
-    if (wr == 48) return grid_mfma_waves<1, CPLX, 48, 6, 1>;
-    return grid_mfma_waves<1, CPLX, 64, 8, 1>;
+    if (wr == 32) return grid_mfma_waves<1, CPLX, 32, 4, 1, 768>;
+    if (wr == 48) return grid_mfma_waves<1, CPLX, 48, 6, 1, 1024>;
+    return grid_mfma_waves<1, CPLX, 64, 8, 1, 1024>;
   }
 }
 
@@ -492,9 +505,10 @@ gr_status launch_mfma(const void* bins, const BinLayout& L, int n_pol, const gr_
   d.n_blocks = (uint32_t)nb;
   const int wr = window_of(k.support);
   if (L.tile + k.support > wr) return fail(GR_EINVAL, "binning tile does not fit the gridder window");
-  // wave form when the table leaves room for 16 wave slices
+  // wave form when the table leaves room for the wave slices
+  const WaveShape ws = wave_shape(wr);
   const size_t wave_lds =
-      tap_lds_bytes(k) + (size_t)(kWaveThreads / 64) * kWaveBatch * (sizeof(Record) + n_pol * sizeof(float2));
+      tap_lds_bytes(k) + (size_t)(ws.threads / 64) * kWaveBatch * (sizeof(Record) + n_pol * sizeof(float2));
   if (wave_lds <= 160 * 1024) {
     WaveFn fn;
     if (n_pol == 4) fn = k.taps_complex ? wave_fn<4, true>(wr) : wave_fn<4, false>(wr);
@@ -505,8 +519,9 @@ gr_status launch_mfma(const void* bins, const BinLayout& L, int n_pol, const gr_
     int32_t* counter = const_cast<int32_t*>(nsegs) + 16;
     zero_counter<<<1, 64, 0, stream>>>(counter);
     const int64_t items = nb * wave_parts(n_pol, wr);
-    const int blocks = (int)std::min<int64_t>(device_cus(), (items + 15) / 16);
-    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kWaveThreads), wave_lds, stream, rec, wv, segs,
+    const int waves = ws.threads / 64;
+    const int blocks = (int)std::min<int64_t>((int64_t)device_cus() * ws.blocks_per_cu, (items + waves - 1) / waves);
+    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(ws.threads), wave_lds, stream, rec, wv, segs,
                        nsegs, counter, k.taps, grid, d, (uint32_t)tap_lds_bytes(k));
     return check_launch("gr_grid_binned (mfma waves)");
   }
