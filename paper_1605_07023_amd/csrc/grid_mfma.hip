@@ -29,12 +29,12 @@
 //
 // Three launch forms share that update:
 //  * grid_mfma_waves (single problem, default): one 1024-thread block per CU
-//    (two 768-thread blocks for the 32-cell window) stages the tap table once
-//    (Section 4 stages the GCF in local memory); its waves then work without
-//    block barriers, each taking
+//    stages the tap table once (Section 4 stages the GCF in local memory); its
+//    16 waves then work without block barriers, each taking
 //    (segment, part) items from an atomic counter, where part p of a window is
 //    the row groups p, p + parts, p + 2 parts, ...  Each wave stages its own
-//    batches of 64 visibilities in its own LDS slice.
+//    batches of 64 visibilities in its own LDS slice, each as its footprint
+//    origin and the offsets of its two tap rows (decoded once, not per use).
 //  * grid_mfma_kernel: one 256-thread block per segment, its 4 waves sharing
 //    the segment's window rows (the form used when the table leaves too little
 //    LDS for 16 wave slices).
@@ -110,18 +110,26 @@ __device__ __forceinline__ void stage_taps(TapT<CPLX>* __restrict__ lds, const v
   }
 }
 
+// Staged form of one visibility: {x0, y0, offset of its G^u row, offset of its
+// G^v row} (row offsets in table entries), decoded once when the batch is staged.
+__device__ __forceinline__ int4 stage_info(const Record r, const MfmaDev& d) {
+  const int sp = d.S + 2;
+  return make_int4(rec_x0(r), rec_y0(r), (rec_plane(r) * d.O + rec_sx(r)) * sp,
+                   (rec_plane(r) * d.O + rec_sy(r)) * sp);
+}
+
 // The work of one wave on one batch of a segment: the window rows of the NG
 // row groups whose first rows are row0 + j * GSTRIDE (j < NG), all WCG column
-// groups of the window at columns win_x0 + 8 c.  b_rec / b_vis hold nb
+// groups of the window at columns win_x0 + 8 c.  b_inf / b_vis hold nb
 // staged visibilities.
 template <int P, bool CPLX, int WCG, int NG, int GSTRIDE>
-__device__ __forceinline__ void mfma_batch(const Record* __restrict__ b_rec,
+__device__ __forceinline__ void mfma_batch(const int4* __restrict__ b_inf,
                                            const float2* __restrict__ b_vis, int nb,
                                            const TapT<CPLX>* __restrict__ lds, int row0, int win_x0,
                                            const MfmaDev& d, f4 (&acc)[NG][WCG]) {
   constexpr int RG = 16 / P;
   const int lane = threadIdx.x & 63;
-  const int S = d.S, SP = d.S + 2;
+  const int S = d.S;
   const int srow0 = __builtin_amdgcn_readfirstlane(row0);
   // lane roles in the 16x16x4 operand layouts
   const int kk = lane >> 4;              // K index: (v, re|im)
@@ -134,23 +142,15 @@ __device__ __forceinline__ void mfma_batch(const Record* __restrict__ b_rec,
   const float sgn = comp == 0 ? 1.f : -1.f;
   for (int q = 0; q < nb; q += 2) {
     const bool hb = q + 1 < nb;
-    const Record la = b_rec[q];
-    const Record lb = b_rec[hb ? q + 1 : q];
-    // the pair's records are wave-uniform: move them to scalar registers
-    const Record ra{(uint32_t)__builtin_amdgcn_readfirstlane(la.x),
-                    (uint32_t)__builtin_amdgcn_readfirstlane(la.y)};
-    const Record rb{(uint32_t)__builtin_amdgcn_readfirstlane(lb.x),
-                    (uint32_t)__builtin_amdgcn_readfirstlane(lb.y)};
-    const int xa = rec_x0(ra), ya = rec_y0(ra), xb = rec_x0(rb), yb = rec_y0(rb);
+    // this lane's visibility of the pair; lanes 0 and 32 hold the two (a
+    // missing second one repeats the first and gets V = 0)
+    const int4 inf = b_inf[(v && hb) ? q + 1 : q];
+    const int xa = __builtin_amdgcn_readlane(inf.x, 0), ya = __builtin_amdgcn_readlane(inf.y, 0);
+    const int xb = __builtin_amdgcn_readlane(inf.x, 32), yb = __builtin_amdgcn_readlane(inf.y, 32);
     const int lo = min(ya, yb), hi = max(ya, yb) + S - 1;
     const int c_lo = (min(xa, xb) - win_x0) >> 3;
     const int c_hi = (max(xa, xb) + S - 1 - win_x0) >> 3;
-
-    // this lane's visibility of the pair (a missing second one has V = 0)
-    const Record rv = v ? rb : ra;
-    const int x0v = rec_x0(rv), y0v = rec_y0(rv);
-    const int tabu = (rec_plane(rv) * d.O + rec_sx(rv)) * SP;
-    const int tabv = (rec_plane(rv) * d.O + rec_sy(rv)) * SP;
+    const int x0v = inf.x, y0v = inf.y, tabu = inf.z, tabv = inf.w;
     const float2 vv = ((v == 0) || hb) ? b_vis[(q + v) * P + ap] : make_float2(0.f, 0.f);
     // A = G^v V: component 0 is t.x vr - t.y vi, component 1 is t.x vi + t.y vr
     const float va = comp == 0 ? vv.x : vv.y;
@@ -230,7 +230,7 @@ template <int P, bool CPLX, int WR, int WCG>
 __device__ __forceinline__ void mfma_segment(const Record* __restrict__ rec,
                                              const float2* __restrict__ wvis, const int4 sg,
                                              const TapT<CPLX>* __restrict__ lds,
-                                             Record* __restrict__ b_rec, float2* __restrict__ b_vis,
+                                             int4* __restrict__ b_inf, float2* __restrict__ b_vis,
                                              float2* __restrict__ grid, const MfmaDev& d) {
   constexpr int RG = 16 / P;            // rows per row group
   constexpr int NG = WR / RG / 4;       // row groups per wave
@@ -260,13 +260,13 @@ __device__ __forceinline__ void mfma_segment(const Record* __restrict__ rec,
         const int e = t + j * 256;
         w[j] = e < nb * P ? wvis[(int64_t)(begin + b0) * P + e] : make_float2(0.f, 0.f);
       }
-      if (t < nb) b_rec[t] = r;
+      if (t < nb) b_inf[t] = stage_info(r, d);
 #pragma unroll
       for (int j = 0; j < P; ++j)
         if (t + j * 256 < nb * P) b_vis[t + j * 256] = w[j];
     }
     __syncthreads();
-    mfma_batch<P, CPLX, WCG, NG, 4 * RG>(b_rec, b_vis, nb, lds, row0, win_x0, d, acc);
+    mfma_batch<P, CPLX, WCG, NG, 4 * RG>(b_inf, b_vis, nb, lds, row0, win_x0, d, acc);
   }
   flush_window<P, WCG, NG, 4 * RG>(acc, row0, win_x0, grid, d);
 }
@@ -278,9 +278,9 @@ grid_mfma_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvis
                  const void* __restrict__ taps, float2* __restrict__ grid, MfmaDev d) {
   using Tap = TapT<CPLX>;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  Record* b_rec = reinterpret_cast<Record*>(lds_raw);                            // [kBatch]
-  float2* b_vis = reinterpret_cast<float2*>(lds_raw + kBatch * sizeof(Record));  // [kBatch][P]
-  Tap* lds = reinterpret_cast<Tap*>(lds_raw + kBatch * sizeof(Record) + kBatch * P * sizeof(float2));
+  int4* b_inf = reinterpret_cast<int4*>(lds_raw);                               // [kBatch]
+  float2* b_vis = reinterpret_cast<float2*>(lds_raw + kBatch * sizeof(int4));    // [kBatch][P]
+  Tap* lds = reinterpret_cast<Tap*>(lds_raw + kBatch * sizeof(int4) + kBatch * P * sizeof(float2));
   // Segments are listed in tile order and their count is only known on the
   // device, so blocks take segments in dispatch order: consecutive segments
   // (neighbouring tiles) land on different XCDs, which spreads the dense
@@ -288,7 +288,7 @@ grid_mfma_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvis
   const int seg = (int)blockIdx.x;
   if (seg >= *n_segs_p) return;                       // uniform for the block
   stage_taps<CPLX>(lds, taps, d);
-  mfma_segment<P, CPLX, WR, WCG>(rec, wvis, segs[seg], lds, b_rec, b_vis, grid, d);
+  mfma_segment<P, CPLX, WR, WCG>(rec, wvis, segs[seg], lds, b_inf, b_vis, grid, d);
 }
 
 // Wave form (see the file header).  PARTS = (WR / RG) / NG items per segment.
@@ -305,9 +305,9 @@ grid_mfma_waves(const Record* __restrict__ rec, const float2* __restrict__ wvis,
   extern __shared__ __align__(16) unsigned char lds_raw[];
   Tap* lds = reinterpret_cast<Tap*>(lds_raw);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  Record* b_rec = reinterpret_cast<Record*>(lds_raw + tap_bytes +
-                                            (size_t)wave * kWaveBatch * (sizeof(Record) + P * sizeof(float2)));
-  float2* b_vis = reinterpret_cast<float2*>(b_rec + kWaveBatch);
+  int4* b_inf = reinterpret_cast<int4*>(lds_raw + tap_bytes +
+                                        (size_t)wave * kWaveBatch * (sizeof(int4) + P * sizeof(float2)));
+  float2* b_vis = reinterpret_cast<float2*>(b_inf + kWaveBatch);
   stage_taps<CPLX>(lds, taps, d);
   __syncthreads();                                    // the only block barrier
   const int n_items = *n_segs_p * PARTS;
@@ -339,12 +339,12 @@ grid_mfma_waves(const Record* __restrict__ rec, const float2* __restrict__ wvis,
         const int e = lane + j * 64;
         w[j] = e < nb * P ? wvis[(int64_t)(begin + b0) * P + e] : make_float2(0.f, 0.f);
       }
-      if (lane < nb) b_rec[lane] = r;
+      if (lane < nb) b_inf[lane] = stage_info(r, d);
 #pragma unroll
       for (int j = 0; j < P; ++j)
         if (lane + j * 64 < nb * P) b_vis[lane + j * 64] = w[j];
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      mfma_batch<P, CPLX, WCG, NG, PARTS * RG>(b_rec, b_vis, nb, lds, row0, win_x0, d, acc);
+      mfma_batch<P, CPLX, WCG, NG, PARTS * RG>(b_inf, b_vis, nb, lds, row0, win_x0, d, acc);
     }
     flush_window<P, WCG, NG, PARTS * RG>(acc, row0, win_x0, grid, d);
   }
@@ -362,9 +362,9 @@ grid_mfma_persistent(const BatchInst* __restrict__ inst, const int32_t* __restri
                      int32_t* __restrict__ counter) {
   using Tap = TapT<CPLX>;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  Record* b_rec = reinterpret_cast<Record*>(lds_raw);
-  float2* b_vis = reinterpret_cast<float2*>(lds_raw + kBatch * sizeof(Record));
-  Tap* lds = reinterpret_cast<Tap*>(lds_raw + kBatch * sizeof(Record) + kBatch * P * sizeof(float2));
+  int4* b_inf = reinterpret_cast<int4*>(lds_raw);
+  float2* b_vis = reinterpret_cast<float2*>(lds_raw + kBatch * sizeof(int4));
+  Tap* lds = reinterpret_cast<Tap*>(lds_raw + kBatch * sizeof(int4) + kBatch * P * sizeof(float2));
   __shared__ int s_inst, s_seg;
   const int total = prefix[n_members];
   int staged = -1;
@@ -394,7 +394,7 @@ grid_mfma_persistent(const BatchInst* __restrict__ inst, const int32_t* __restri
       stage_taps<CPLX>(lds, I.taps, d);
       staged = ii;
     }
-    mfma_segment<P, CPLX, WR, WCG>(I.brec, I.bwvis, I.segs[ls], lds, b_rec, b_vis, I.grid, d);
+    mfma_segment<P, CPLX, WR, WCG>(I.brec, I.bwvis, I.segs[ls], lds, b_inf, b_vis, I.grid, d);
   }
 }
 
@@ -407,13 +407,11 @@ using MfmaFn = void (*)(const Record*, const float2*, const int4*, const int32_t
 using WaveFn = void (*)(const Record*, const float2*, const int4*, const int32_t*, int32_t*,
                         const void*, float2*, MfmaDev, uint32_t);
 
-// Wave-form launch shape per window: threads per block and blocks per CU.  The
-// 32-cell window's kernel needs few registers and a small table, so two
-// 768-thread blocks share a CU (24 waves); the others run one 1024-thread block.
+// Wave-form launch shape: threads per block and blocks per CU (16 waves per CU).
 struct WaveShape {
   int threads, blocks_per_cu;
 };
-WaveShape wave_shape(int wr) { return wr == 32 ? WaveShape{768, 2} : WaveShape{1024, 1}; }
+WaveShape wave_shape(int) { return WaveShape{1024, 1}; }
 using PersistFn = void (*)(const BatchInst*, const int32_t*, int, const int32_t*, int32_t*);
 
 // window edge (cells) for a support: footprints of a tile of edge WR - S fit it
@@ -443,11 +441,11 @@ PersistFn persist_fn(int wr) {
 template <int P, bool CPLX>
 WaveFn wave_fn(int wr) {
   if constexpr (P == 4) {
-    if (wr == 32) return grid_mfma_waves<4, CPLX, 32, 4, 2, 768>;
+    if (wr == 32) return grid_mfma_waves<4, CPLX, 32, 4, 4, 1024>;
     if (wr == 48) return grid_mfma_waves<4, CPLX, 48, 6, 3, 1024>;
     return grid_mfma_waves<4, CPLX, 64, 8, 2, 1024>;
   } else {
-    if (wr == 32) return grid_mfma_waves<1, CPLX, 32, 4, 1, 768>;
+    if (wr == 32) return grid_mfma_waves<1, CPLX, 32, 4, 1, 1024>;
     if (wr == 48) return grid_mfma_waves<1, CPLX, 48, 6, 1, 1024>;
     return grid_mfma_waves<1, CPLX, 64, 8, 1, 1024>;
   }
@@ -455,7 +453,7 @@ WaveFn wave_fn(int wr) {
 
 int wave_parts(int n_pol, int wr) {
   const int rg = 16 / n_pol;
-  const int ng = n_pol == 4 ? (wr == 48 ? 3 : 2) : 1;
+  const int ng = n_pol == 4 ? (wr == 48 ? 3 : wr == 32 ? 4 : 2) : 1;
   return wr / rg / ng;
 }
 
@@ -480,7 +478,7 @@ int binned_tile(int support) { return window_of(support) - support; }
 
 gr_status plan_mfma(const gr_kernel& k, int n_pol, size_t* lds_bytes) {
   if (k.support > 56) return fail(GR_EUNSUPPORTED, "MFMA gridder needs support <= 56");
-  const size_t lds = tap_lds_bytes(k) + (size_t)kBatch * (sizeof(Record) + (size_t)n_pol * sizeof(float2));
+  const size_t lds = tap_lds_bytes(k) + (size_t)kBatch * (sizeof(int4) + (size_t)n_pol * sizeof(float2));
   if (lds > 160 * 1024) return fail(GR_EUNSUPPORTED, "tap table does not fit in LDS");
   *lds_bytes = lds;
   return GR_OK;
@@ -508,7 +506,7 @@ gr_status launch_mfma(const void* bins, const BinLayout& L, int n_pol, const gr_
   // wave form when the table leaves room for the wave slices
   const WaveShape ws = wave_shape(wr);
   const size_t wave_lds =
-      tap_lds_bytes(k) + (size_t)(ws.threads / 64) * kWaveBatch * (sizeof(Record) + n_pol * sizeof(float2));
+      tap_lds_bytes(k) + (size_t)(ws.threads / 64) * kWaveBatch * (sizeof(int4) + n_pol * sizeof(float2));
   if (wave_lds <= 160 * 1024) {
     WaveFn fn;
     if (n_pol == 4) fn = k.taps_complex ? wave_fn<4, true>(wr) : wave_fn<4, false>(wr);
