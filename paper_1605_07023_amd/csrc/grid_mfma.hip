@@ -35,6 +35,8 @@
 //    the row groups p, p + parts, p + 2 parts, ...  Each wave stages its own
 //    batches of 64 visibilities in its own LDS slice, each as its footprint
 //    origin and the offsets of its two tap rows (decoded once, not per use).
+//    With complex taps the staged table carries the negated imaginary parts
+//    as well, so that each lane reads its B value with one 4-byte load.
 //  * grid_mfma_kernel: one 256-thread block per segment, its 4 waves sharing
 //    the segment's window rows (the form used when the table leaves too little
 //    LDS for 16 wave slices).
@@ -91,7 +93,10 @@ __device__ __forceinline__ float b_value(const TapT<CPLX>* row, int tap, int S, 
 
 // Stage the tap table as FP32 rows [plane * O + s] of S + 2 entries, with one
 // zero before and after the S taps.
-template <bool CPLX>
+// With NEG (complex taps, wave form) the rows are followed by a second table of
+// the negated imaginary parts, [row][S + 2] floats, so that every B value is a
+// single 4-byte read (see mfma_batch).
+template <bool CPLX, bool NEG = false>
 __device__ __forceinline__ void stage_taps(TapT<CPLX>* __restrict__ lds, const void* __restrict__ taps,
                                            const MfmaDev& d) {
   const int S = d.S, SP = d.S + 2;
@@ -101,9 +106,10 @@ __device__ __forceinline__ void stage_taps(TapT<CPLX>* __restrict__ lds, const v
     const bool in = k >= 0 && k < S;
     const int64_t src = (int64_t)row * S + (in ? k : 0);
     if constexpr (CPLX) {
-      lds[e] = in ? make_float2(load_tap32(taps, 2 * src, d.tap_dtype),
-                                load_tap32(taps, 2 * src + 1, d.tap_dtype))
-                  : make_float2(0.f, 0.f);
+      const float re = in ? load_tap32(taps, 2 * src, d.tap_dtype) : 0.f;
+      const float im = in ? load_tap32(taps, 2 * src + 1, d.tap_dtype) : 0.f;
+      lds[e] = make_float2(re, im);
+      if constexpr (NEG) reinterpret_cast<float*>(lds + n_elem)[e] = -im;
     } else {
       lds[e] = in ? load_tap32(taps, src, d.tap_dtype) : 0.f;
     }
@@ -122,7 +128,7 @@ __device__ __forceinline__ int4 stage_info(const Record r, const MfmaDev& d) {
 // row groups whose first rows are row0 + j * GSTRIDE (j < NG), all WCG column
 // groups of the window at columns win_x0 + 8 c.  b_inf / b_vis hold nb
 // staged visibilities.
-template <int P, bool CPLX, int WCG, int NG, int GSTRIDE>
+template <int P, bool CPLX, int WCG, int NG, int GSTRIDE, bool NEG = false>
 __device__ __forceinline__ void mfma_batch(const int4* __restrict__ b_inf,
                                            const float2* __restrict__ b_vis, int nb,
                                            const TapT<CPLX>* __restrict__ lds, int row0, int win_x0,
@@ -140,18 +146,23 @@ __device__ __forceinline__ void mfma_batch(const int4* __restrict__ b_inf,
   const int bx = m >> 1, bcomp = m & 1;
   const bool sel_re = comp == bcomp;
   const float sgn = comp == 0 ? 1.f : -1.f;
+  // NEG layout: (comp, bcomp) = (0,0) Re from the (re, im) rows, (0,1) Im,
+  // (1,0) -Im from the negated-imaginary rows, (1,1) Re; byte base and stride
+  const bool use_neg = comp == 1 && bcomp == 0;
+  const int bstride = use_neg ? 4 : 8;
+  const int bbase = use_neg ? d.n_rows_tab * (S + 2) * 8 : (comp == 0 && bcomp == 1 ? 4 : 0);
+  // an odd batch carries a zero visibility with the last one's footprint in
+  // slot nb, so every pair is whole
   for (int q = 0; q < nb; q += 2) {
-    const bool hb = q + 1 < nb;
-    // this lane's visibility of the pair; lanes 0 and 32 hold the two (a
-    // missing second one repeats the first and gets V = 0)
-    const int4 inf = b_inf[(v && hb) ? q + 1 : q];
+    // this lane's visibility of the pair; lanes 0 and 32 hold the two
+    const int4 inf = b_inf[q + v];
     const int xa = __builtin_amdgcn_readlane(inf.x, 0), ya = __builtin_amdgcn_readlane(inf.y, 0);
     const int xb = __builtin_amdgcn_readlane(inf.x, 32), yb = __builtin_amdgcn_readlane(inf.y, 32);
     const int lo = min(ya, yb), hi = max(ya, yb) + S - 1;
     const int c_lo = (min(xa, xb) - win_x0) >> 3;
     const int c_hi = (max(xa, xb) + S - 1 - win_x0) >> 3;
     const int x0v = inf.x, y0v = inf.y, tabu = inf.z, tabv = inf.w;
-    const float2 vv = ((v == 0) || hb) ? b_vis[(q + v) * P + ap] : make_float2(0.f, 0.f);
+    const float2 vv = b_vis[(q + v) * P + ap];
     // A = G^v V: component 0 is t.x vr - t.y vi, component 1 is t.x vi + t.y vr
     const float va = comp == 0 ? vv.x : vv.y;
     const float vb = comp == 0 ? -vv.y : vv.x;
@@ -170,9 +181,18 @@ __device__ __forceinline__ void mfma_batch(const int4* __restrict__ b_inf,
       }
     }
     float bfr[WCG];
+    if constexpr (NEG && CPLX) {
+      const int rowbase = bbase + tabu * bstride;
 #pragma unroll
-    for (int c = 0; c < WCG; ++c)
-      bfr[c] = b_value<CPLX>(lds + tabu, win_x0 + c * 8 + bx - x0v, S, sel_re, sgn);
+      for (int c = 0; c < WCG; ++c) {
+        const int idx = clamp_tap(win_x0 + c * 8 + bx - x0v, S);
+        bfr[c] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(lds) + rowbase + idx * bstride);
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < WCG; ++c)
+        bfr[c] = b_value<CPLX>(lds + tabu, win_x0 + c * 8 + bx - x0v, S, sel_re, sgn);
+    }
     // wave-uniform masks of the D tiles either footprint touches
     uint32_t rmask = 0;
 #pragma unroll
@@ -264,6 +284,10 @@ __device__ __forceinline__ void mfma_segment(const Record* __restrict__ rec,
 #pragma unroll
       for (int j = 0; j < P; ++j)
         if (t + j * 256 < nb * P) b_vis[t + j * 256] = w[j];
+      if (nb & 1) {                                    // pad an odd batch (nb <= 255 here)
+        if (t == 0) b_inf[nb] = stage_info(rec[begin + b0 + nb - 1], d);
+        if (t < P) b_vis[nb * P + t] = make_float2(0.f, 0.f);
+      }
     }
     __syncthreads();
     mfma_batch<P, CPLX, WCG, NG, 4 * RG>(b_inf, b_vis, nb, lds, row0, win_x0, d, acc);
@@ -308,7 +332,7 @@ grid_mfma_waves(const Record* __restrict__ rec, const float2* __restrict__ wvis,
   int4* b_inf = reinterpret_cast<int4*>(lds_raw + tap_bytes +
                                         (size_t)wave * kWaveBatch * (sizeof(int4) + P * sizeof(float2)));
   float2* b_vis = reinterpret_cast<float2*>(b_inf + kWaveBatch);
-  stage_taps<CPLX>(lds, taps, d);
+  stage_taps<CPLX, CPLX>(lds, taps, d);
   __syncthreads();                                    // the only block barrier
   const int n_items = *n_segs_p * PARTS;
   for (;;) {
@@ -343,8 +367,12 @@ grid_mfma_waves(const Record* __restrict__ rec, const float2* __restrict__ wvis,
 #pragma unroll
       for (int j = 0; j < P; ++j)
         if (lane + j * 64 < nb * P) b_vis[lane + j * 64] = w[j];
+      if (nb & 1) {                                    // pad an odd batch (nb <= 63 here)
+        if (lane == 0) b_inf[nb] = stage_info(rec[begin + b0 + nb - 1], d);
+        if (lane < P) b_vis[nb * P + lane] = make_float2(0.f, 0.f);
+      }
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      mfma_batch<P, CPLX, WCG, NG, PARTS * RG>(b_inf, b_vis, nb, lds, row0, win_x0, d, acc);
+      mfma_batch<P, CPLX, WCG, NG, PARTS * RG, CPLX>(b_inf, b_vis, nb, lds, row0, win_x0, d, acc);
     }
     flush_window<P, WCG, NG, PARTS * RG>(acc, row0, win_x0, grid, d);
   }
@@ -457,8 +485,9 @@ int wave_parts(int n_pol, int wr) {
   return wr / rg / ng;
 }
 
-size_t tap_lds_bytes(const gr_kernel& k) {
-  return align256((size_t)k.n_planes * k.oversample * (k.support + 2) * (k.taps_complex ? 8 : 4));
+size_t tap_lds_bytes(const gr_kernel& k, bool neg = false) {
+  const size_t per = k.taps_complex ? (neg ? 12 : 8) : 4;
+  return align256((size_t)k.n_planes * k.oversample * (k.support + 2) * per);
 }
 
 int g_cus = 0;
@@ -505,8 +534,8 @@ gr_status launch_mfma(const void* bins, const BinLayout& L, int n_pol, const gr_
   if (L.tile + k.support > wr) return fail(GR_EINVAL, "binning tile does not fit the gridder window");
   // wave form when the table leaves room for the wave slices
   const WaveShape ws = wave_shape(wr);
-  const size_t wave_lds =
-      tap_lds_bytes(k) + (size_t)(ws.threads / 64) * kWaveBatch * (sizeof(int4) + n_pol * sizeof(float2));
+  const size_t wave_lds = tap_lds_bytes(k, true) +
+                          (size_t)(ws.threads / 64) * kWaveBatch * (sizeof(int4) + n_pol * sizeof(float2));
   if (wave_lds <= 160 * 1024) {
     WaveFn fn;
     if (n_pol == 4) fn = k.taps_complex ? wave_fn<4, true>(wr) : wave_fn<4, false>(wr);
@@ -520,7 +549,7 @@ gr_status launch_mfma(const void* bins, const BinLayout& L, int n_pol, const gr_
     const int waves = ws.threads / 64;
     const int blocks = (int)std::min<int64_t>((int64_t)device_cus() * ws.blocks_per_cu, (items + waves - 1) / waves);
     hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(ws.threads), wave_lds, stream, rec, wv, segs,
-                       nsegs, counter, k.taps, grid, d, (uint32_t)tap_lds_bytes(k));
+                       nsegs, counter, k.taps, grid, d, (uint32_t)tap_lds_bytes(k, true));
     return check_launch("gr_grid_binned (mfma waves)");
   }
   MfmaFn fn;
