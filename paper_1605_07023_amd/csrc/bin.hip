@@ -114,20 +114,28 @@ __device__ __forceinline__ void bin_scatter_one(const Record* __restrict__ rec,
     r = rec[i];
     if (rec_valid(r)) key = tile_of(r, tile, n_tx);
   }
+  // group the wave's lanes by tile: each lane learns its group's first lane,
+  // its rank in the group and (for the first lane) the group size; then all
+  // groups reserve their list space with one atomic instruction
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  int pos = -1;
+  int leader = lane, rank = 0, count = 0;
   uint64_t todo = __ballot(key >= 0);
   while (todo) {
-    const int leader = __ffsll((unsigned long long)todo) - 1;
-    const int k = __shfl(key, leader);
+    const int l = __ffsll((unsigned long long)todo) - 1;
+    const int k = __shfl(key, l);
     const uint64_t same = __ballot(key == k);
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&cursor[k], (int32_t)__popcll(same));
-    base = __shfl(base, leader);
-    if (key == k) pos = base + (int)__popcll(same & below);
+    if (key == k) {
+      leader = l;
+      rank = (int)__popcll(same & below);
+      count = (int)__popcll(same);
+    }
     todo &= ~same;
   }
-  if (pos >= 0) {
+  int base = 0;
+  if (key >= 0 && lane == leader) base = atomicAdd(&cursor[key], count);
+  base = __shfl(base, leader);
+  if (key >= 0) {
+    const int pos = base + rank;
     out_rec[pos] = r;
     for (int p = 0; p < n_pol; ++p) out_wvis[(int64_t)pos * n_pol + p] = wvis[i * n_pol + p];
   }
