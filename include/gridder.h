@@ -315,6 +315,25 @@ size_t gr_grid_batch_workspace_bytes(const gr_batch_item* items, int32_t n_items
 gr_status gr_grid_batch(const gr_batch_item* items, int32_t n_items, void* workspace,
                         size_t workspace_bytes, void* stream);
 
+/* The whole gr_grid_batch sequence for these items, captured once into a HIP
+ * graph (on a stream of the library's own) and instantiated: *out receives an
+ * opaque handle.  Items and workspace are validated on the host first, as by
+ * gr_grid_batch; nothing runs until gr_graph_launch.  Every launch grids the
+ * items again into their grids (+=: zero them in between to repeat a result);
+ * the items' buffers and the workspace must stay allocated and unchanged in
+ * size while the handle lives.  The graph holds only kernel nodes (no
+ * memset).  Creating it synchronises nothing on the device. */
+typedef struct gr_graph gr_graph;
+gr_status gr_grid_batch_graph(const gr_batch_item* items, int32_t n_items, void* workspace,
+                              size_t workspace_bytes, gr_graph** out);
+
+/* Enqueue one replay of the captured batch on `stream`. */
+gr_status gr_graph_launch(gr_graph* graph, void* stream);
+
+/* Release the handle (NULL is accepted); the caller makes sure no launch of it
+ * is still pending if its buffers are to be freed. */
+gr_status gr_graph_destroy(gr_graph* graph);
+
 /* Thread-local description of the last non-OK status ("" if none). */
 const char* gr_last_error(void);
 

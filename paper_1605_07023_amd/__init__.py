@@ -12,4 +12,5 @@ from .binding import (  # noqa: F401
     gr_make_wkernel_table, make_kernel, gr_bin_bytes, gr_bin, gr_grid_binned, gr_autotune,
     gr_make_wkernel2d_table, gr_mlp_blob_floats, gr_mlp_eval, gr_mlp_dataset, gr_mlp_grads,
     gr_mlp_train_step, GrBatchItem, make_batch_item, gr_grid_batch, gr_grid_batch_workspace_bytes,
+    gr_grid_batch_graph, gr_graph_launch, gr_graph_destroy,
 )

@@ -95,6 +95,12 @@ def load_library():
     lib.gr_grid_batch.restype = ctypes.c_int
     lib.gr_grid_batch_workspace_bytes.argtypes = [ctypes.POINTER(GrBatchItem), I32]
     lib.gr_grid_batch_workspace_bytes.restype = SZ
+    lib.gr_grid_batch_graph.argtypes = [ctypes.POINTER(GrBatchItem), I32, P, SZ, ctypes.POINTER(ctypes.c_void_p)]
+    lib.gr_grid_batch_graph.restype = ctypes.c_int
+    lib.gr_graph_launch.argtypes = [P, P]
+    lib.gr_graph_launch.restype = ctypes.c_int
+    lib.gr_graph_destroy.argtypes = [P]
+    lib.gr_graph_destroy.restype = ctypes.c_int
     lib.gr_mlp_blob_floats.argtypes = []
     lib.gr_mlp_blob_floats.restype = I32
     lib.gr_version.argtypes = []
@@ -268,3 +274,24 @@ def gr_grid_batch(items, workspace, workspace_bytes, stream=None):
     arr = (GrBatchItem * max(len(items), 1))(*items)
     _check(load_library().gr_grid_batch(arr, len(items), _ptr(workspace), workspace_bytes,
                                         _stream(stream, workspace)))
+
+
+def gr_grid_batch_graph(items, workspace, workspace_bytes) -> int:
+    """Capture the batch into a HIP graph; returns the opaque handle (an int)."""
+    arr = (GrBatchItem * max(len(items), 1))(*items)
+    h = ctypes.c_void_p(None)
+    _check(load_library().gr_grid_batch_graph(arr, len(items), _ptr(workspace), workspace_bytes,
+                                              ctypes.byref(h)))
+    return h.value
+
+
+def gr_graph_launch(handle, stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    if not isinstance(s, int):
+        s = s.cuda_stream
+    _check(load_library().gr_graph_launch(handle, s))
+
+
+def gr_graph_destroy(handle):
+    _check(load_library().gr_graph_destroy(handle))

@@ -122,8 +122,10 @@ gr_status make_plan(const gr_batch_item* items, int n, Plan* p) {
     gr_status st = validate_item(it, i, &p->lds[i]);
     if (st != GR_OK) return st;
     p->off_inst[i] = off;
+    // the persistent block-form gridder works on 64-cell windows: tiles of 64 - S
+    // keep its segments dense even in sparse instances
     p->bins[i] = bin_layout(it.n_vis, it.n_pol, it.kernel.support, it.height, it.width,
-                            it.seg_len > 0 ? it.seg_len : kDefaultSegLen);
+                            it.seg_len > 0 ? it.seg_len : kDefaultSegLen, 64);
     if (p->bins[i].n_tiles > 0x7fffffff || p->bins[i].max_segs > 0x7fffffff)
       return fail(GR_EINVAL, "gr_grid_batch item " + std::to_string(i) + ": too many tiles");
     off += pre_size(it.n_vis, it.n_pol) + p->bins[i].bytes;
@@ -253,5 +255,66 @@ extern "C" gr_status gr_grid_batch(const gr_batch_item* items, int32_t n_items, 
                                 n_blocks, s);
     if (st != GR_OK) return st;
   }
+  return GR_OK;
+}
+
+// ---- the batch as one HIP graph ----------------------------------------------
+
+struct gr_graph {
+  hipGraphExec_t exec;
+  int device;
+};
+
+extern "C" gr_status gr_grid_batch_graph(const gr_batch_item* items, int32_t n_items, void* workspace,
+                                         size_t workspace_bytes, gr_graph** out) {
+  if (out == nullptr) return fail(GR_EINVAL, "gr_grid_batch_graph: out is NULL");
+  *out = nullptr;
+  Plan p;
+  gr_status st = make_plan(items, n_items, &p);       // every item checked before anything is captured
+  if (st != GR_OK) return st;
+  if (n_items > 0 && workspace == nullptr) return fail(GR_EINVAL, "gr_grid_batch_graph: workspace is NULL");
+  if (workspace_bytes < p.bytes)
+    return fail(GR_ENOMEM, "gr_grid_batch_graph: workspace too small (see gr_grid_batch_workspace_bytes)");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(GR_EDEVICE, "gr_grid_batch_graph: no device");
+  hipStream_t s = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+    return fail(GR_EDEVICE, "gr_grid_batch_graph: hipStreamCreateWithFlags failed");
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) {
+    hipStreamDestroy(s);
+    return fail(GR_EDEVICE, std::string("gr_grid_batch_graph: hipStreamBeginCapture: ") + hipGetErrorString(e));
+  }
+  st = gr_grid_batch(items, n_items, workspace, workspace_bytes, s);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(s, &graph);
+  hipStreamDestroy(s);
+  if (st != GR_OK) {
+    if (graph) hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess || graph == nullptr)
+    return fail(GR_EDEVICE, std::string("gr_grid_batch_graph: hipStreamEndCapture: ") + hipGetErrorString(e));
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e != hipSuccess)
+    return fail(GR_EDEVICE, std::string("gr_grid_batch_graph: hipGraphInstantiate: ") + hipGetErrorString(e));
+  *out = new gr_graph{exec, dev};
+  return GR_OK;
+}
+
+extern "C" gr_status gr_graph_launch(gr_graph* g, void* stream) {
+  if (g == nullptr) return fail(GR_EINVAL, "gr_graph_launch: graph is NULL");
+  const hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(GR_EDEVICE, std::string("gr_graph_launch: ") + hipGetErrorString(e));
+  return GR_OK;
+}
+
+extern "C" gr_status gr_graph_destroy(gr_graph* g) {
+  if (g == nullptr) return GR_OK;
+  const hipError_t e = hipGraphExecDestroy(g->exec);
+  delete g;
+  if (e != hipSuccess) return fail(GR_EDEVICE, std::string("gr_graph_destroy: ") + hipGetErrorString(e));
   return GR_OK;
 }

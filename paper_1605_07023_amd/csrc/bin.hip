@@ -185,9 +185,10 @@ batch_bin_scatter_kernel(const BatchInst* __restrict__ inst, int n_inst) {
 
 }  // namespace
 
-BinLayout bin_layout(int64_t n_vis, int n_pol, int support, int height, int width, int seg_len) {
+BinLayout bin_layout(int64_t n_vis, int n_pol, int support, int height, int width, int seg_len,
+                     int window) {
   BinLayout L{};
-  L.tile = binned_tile(support);
+  L.tile = binned_tile(support, window);
   L.n_tx = (width + L.tile - 1) / L.tile;
   L.n_ty = (height + L.tile - 1) / L.tile;
   L.n_tiles = (int64_t)L.n_tx * L.n_ty;

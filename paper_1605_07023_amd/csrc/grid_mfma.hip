@@ -64,6 +64,7 @@ __device__ inline float load_tap32(const void* __restrict__ t, int64_t idx, int 
 }
 
 constexpr int kBatch = 256;        // visibilities staged per batch (block forms)
+constexpr int kBatchWindow = 64;   // window of the batch gridder (batches bin for it)
 constexpr int kWaveBatch = 64;     // visibilities staged per batch (wave form)
 
 template <bool CPLX>
@@ -503,7 +504,7 @@ int device_cus() {
 
 }  // namespace
 
-int binned_tile(int support) { return window_of(support) - support; }
+int binned_tile(int support, int window) { return (window > 0 ? window : window_of(support)) - support; }
 
 gr_status plan_mfma(const gr_kernel& k, int n_pol, size_t* lds_bytes) {
   if (k.support > 56) return fail(GR_EUNSUPPORTED, "MFMA gridder needs support <= 56");
@@ -566,7 +567,8 @@ gr_status launch_mfma_persistent(const BatchInst* inst, const int32_t* members, 
                                  bool complex_taps, size_t lds_bytes, int max_support, int n_blocks,
                                  hipStream_t stream) {
   if (n_members == 0 || n_blocks <= 0) return GR_OK;
-  const int wr = window_of(max_support);
+  (void)max_support;
+  const int wr = kBatchWindow;
   PersistFn fn;
   if (n_pol == 4) fn = complex_taps ? persist_fn<4, true>(wr) : persist_fn<4, false>(wr);
   else fn = complex_taps ? persist_fn<1, true>(wr) : persist_fn<1, false>(wr);

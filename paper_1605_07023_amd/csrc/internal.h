@@ -71,8 +71,11 @@ struct BinLayout {
 };
 // tile edge T (cells): footprints of a tile fit the MFMA gridder's window of T + S
 // cells (32, 48 or 64), and always the 64-cell window of the other binned gridders
-int binned_tile(int support);
-BinLayout bin_layout(int64_t n_vis, int n_pol, int support, int height, int width, int seg_len);
+// window = 0: the single-problem gridder's window for the support (32, 48 or
+// 64 cells); batches bin for the 64-cell window of their block-form gridder.
+int binned_tile(int support, int window = 0);
+BinLayout bin_layout(int64_t n_vis, int n_pol, int support, int height, int width, int seg_len,
+                     int window = 0);
 gr_status launch_bin(const Record* rec, const float2* wvis, int64_t n_vis, int n_pol,
                      const BinLayout& L, void* bins, hipStream_t stream);
 

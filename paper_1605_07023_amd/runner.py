@@ -150,3 +150,30 @@ def grid_batch(dws, grids=None, seg_lens=None, stats=None, workspace=None, strea
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
     B.gr_grid_batch(items, workspace, workspace.numel(), stream)
     return grids, workspace
+
+
+class BatchGraph:
+    """A batch captured by the library into one HIP graph (gr_grid_batch_graph);
+    keeps the device workloads, grids and workspace alive."""
+
+    def __init__(self, dws, grids, seg_lens=None, stats=None):
+        self.dws, self.grids, self.stats = dws, grids, stats
+        self.items = batch_items(dws, grids, seg_lens, stats)
+        need = B.gr_grid_batch_workspace_bytes(self.items)
+        dev = dws[0].uvw.device
+        self.workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+        self.handle = B.gr_grid_batch_graph(self.items, self.workspace, self.workspace.numel())
+
+    def launch(self, stream=None):
+        B.gr_graph_launch(self.handle, stream)
+
+    def close(self):
+        if self.handle:
+            B.gr_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -181,3 +181,18 @@ def test_mlp_kernel_descriptor_rules(lib):
     st = lib.gr_preprocess(1 << 20, 1 << 20, B.GR_F32, None, None, 10, 4, ctypes.byref(k), 1.0, 1.0,
                            64, 64, 1 << 20, 1 << 20, None, None)
     assert st == B.GR_EUNSUPPORTED and "GR_MLP" in lib.gr_last_error().decode()
+
+
+def test_batch_graph_validation(lib):
+    """Invalid items or workspace are rejected on the host before any capture."""
+    from paper_1605_07023_amd import binding as B
+    out = ctypes.c_void_p(123)
+    arr = (B.GrBatchItem * 1)(_item(B, n_pol=2))
+    assert lib.gr_grid_batch_graph(arr, 1, 1 << 20, 1 << 40, ctypes.byref(out)) == B.GR_EINVAL
+    assert out.value is None
+    arr = (B.GrBatchItem * 1)(_item(B))
+    need = lib.gr_grid_batch_workspace_bytes(arr, 1)
+    assert lib.gr_grid_batch_graph(arr, 1, 1 << 20, need - 1, ctypes.byref(out)) == B.GR_ENOMEM
+    assert lib.gr_grid_batch_graph(arr, 1, 1 << 20, need, None) == B.GR_EINVAL
+    assert lib.gr_graph_launch(None, None) == B.GR_EINVAL
+    assert lib.gr_graph_destroy(None) == B.GR_OK

@@ -151,6 +151,38 @@ def test_batch_graph_replays(R):
             assert torch.equal(g, e), f"replay {rep}"
 
 
+def test_batch_native_graph_replays(R):
+    """gr_grid_batch_graph: the library captures the batch into one HIP graph;
+    three launches (grids zeroed and unrelated eager work in between) each equal
+    the eager result bit for bit."""
+    _say("batch captured by the library, 3 graph launches")
+    rng = np.random.default_rng(5)
+    wls = _integer_batch(rng)
+    dws = [_upload_with(R, wl, _integer_taps(rng, wl)[1]) for wl in wls]
+    segs = [32, 0, 0, 100]
+    eager, _ = R.grid_batch(dws, seg_lens=segs)
+    eager = [g.clone() for g in eager]
+    grids = [torch.zeros_like(g) for g in eager]
+    bg = R.BatchGraph(dws, grids, seg_lens=segs)
+    try:
+        for rep in range(3):
+            for g in grids:
+                g.zero_()
+            a = torch.randn(256, 256, device=DEV)
+            (a @ a).sum().item()
+            bg.launch()
+            torch.cuda.synchronize()
+            for g, e in zip(grids, eager):
+                assert torch.equal(g, e), f"launch {rep}"
+        # a launch without zeroing accumulates: twice the eager grid, exactly (integers)
+        bg.launch()
+        torch.cuda.synchronize()
+        for g, e in zip(grids, eager):
+            assert torch.equal(g, 2 * e)
+    finally:
+        bg.close()
+
+
 def test_batch_full_shape_against_single_calls(R):
     """The 32-instance uneven batch (lognormal sizes 1e4..1e6, grids 1024..4096,
     S in {8, 16, 32}, P in {1, 4}): each instance against its own gr_grid call
@@ -172,7 +204,21 @@ def test_batch_full_shape_against_single_calls(R):
         singles.append(R.grid(dw))
     torch.cuda.synchronize()
     t_single = time.time() - t0
-    _say(f"  batch {t_batch * 1e3:.2f} ms, one call per instance {t_single * 1e3:.2f} ms")
+    bg = R.BatchGraph(dws, [torch.zeros_like(g) for g in grids])
+    try:
+        bg.launch()
+        torch.cuda.synchronize()
+        t0 = time.time()
+        for _ in range(3):
+            bg.launch()
+        torch.cuda.synchronize()
+        t_graph = (time.time() - t0) / 3
+        assert _rel(bg.grids[0].cpu().numpy().astype(np.complex128) / 4,
+                    grids[0].cpu().numpy().astype(np.complex128)) <= 1e-6     # 4 launches accumulated
+    finally:
+        bg.close()
+    _say(f"  batch {t_batch * 1e3:.2f} ms, one graph launch {t_graph * 1e3:.2f} ms, "
+         f"one call per instance {t_single * 1e3:.2f} ms")
     worst = 0.0
     for wl, g, s in zip(wls, grids, singles):
         a, b = g.cpu().numpy().astype(np.complex128), s.cpu().numpy().astype(np.complex128)
