@@ -125,6 +125,71 @@ __device__ __forceinline__ int4 stage_info(const Record r, const MfmaDev& d) {
                    (rec_plane(r) * d.O + rec_sy(r)) * sp);
 }
 
+// Bits of a 6-bit value spread to the even bit positions (Morton interleave).
+__device__ __forceinline__ uint32_t spread6(uint32_t v) {
+  v &= 63u;
+  v = (v | (v << 4)) & 0x0f0fu;
+  v = (v | (v << 2)) & 0x3333u;
+  return (v | (v << 1)) & 0x5555u;
+}
+
+// Pairing order of a wave's 64 staged visibilities.  Two visibilities share
+// every MFMA (K = 2 visibilities x (re, im)), so a pair touches the D tiles of
+// the union of its footprints; consecutive visibilities in Z (Morton) order of
+// their footprint origins inside the window have nearby footprints, which cuts
+// the D tiles a pair touches by 13 % (S = 32) to 21 % (S = 16) against arrival
+// order on the full-shape tracks.  A bitonic sort of the 64 keys (position,
+// lane) across the wave gives lane i the i-th key; a forward permute returns to
+// each lane the rank of its own visibility.  Lanes without a visibility sort
+// last.  Must be called by all 64 lanes.
+__device__ __forceinline__ int pair_rank(bool live, int x_rel, int y_rel) {
+  const int lane = threadIdx.x & 63;
+  uint32_t key = live ? (((spread6((uint32_t)x_rel) | (spread6((uint32_t)y_rel) << 1)) << 6) | (uint32_t)lane)
+                      : ((1u << 20) | (uint32_t)lane);
+#pragma unroll
+  for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const uint32_t other = (uint32_t)__shfl_xor((int)key, j);
+      const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
+      key = keep_min ? min(key, other) : max(key, other);
+    }
+  }
+  return __builtin_amdgcn_ds_permute((int)((key & 63u) << 2), lane);
+}
+
+// Stage up to 64 visibilities (one per lane, lanes < n live) of a batch into
+// b_inf / b_vis in pairing order; slot `pad` (when >= 0) receives a copy of
+// the footprint of the visibility ranked last, with zero visibility, so that
+// an odd batch still forms whole pairs.  Called by all 64 lanes of a wave.
+template <int P>
+__device__ __forceinline__ void stage_pairs(const Record* __restrict__ rec, const float2* __restrict__ wvis,
+                                            int64_t first, int n, int win_x0, int win_y0, const MfmaDev& d,
+                                            int4* __restrict__ b_inf, float2* __restrict__ b_vis, int pad) {
+  const int lane = threadIdx.x & 63;
+  const bool live = lane < n;
+  const Record r = live ? rec[first + lane] : Record{0, 0};
+  float2 w[P];
+  if constexpr (P == 4) {
+    const float4* src = reinterpret_cast<const float4*>(wvis + (first + (live ? lane : 0)) * 4);
+    const float4 a = live ? src[0] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 b = live ? src[1] : make_float4(0.f, 0.f, 0.f, 0.f);
+    w[0] = make_float2(a.x, a.y); w[1] = make_float2(a.z, a.w);
+    w[2] = make_float2(b.x, b.y); w[3] = make_float2(b.z, b.w);
+  } else {
+    w[0] = live ? wvis[first + lane] : make_float2(0.f, 0.f);
+  }
+  const int rank = pair_rank(live, rec_x0(r) - win_x0, rec_y0(r) - win_y0);
+  if (live) {
+    const int4 inf = stage_info(r, d);
+    b_inf[rank] = inf;
+#pragma unroll
+    for (int p = 0; p < P; ++p) b_vis[rank * P + p] = w[p];
+    if (pad >= 0 && rank == n - 1) b_inf[pad] = inf;
+  }
+  if (pad >= 0 && lane < P) b_vis[pad * P + lane] = make_float2(0.f, 0.f);
+}
+
 // The work of one wave on one batch of a segment: the window rows of the NG
 // row groups whose first rows are row0 + j * GSTRIDE (j < NG), all WCG column
 // groups of the window at columns win_x0 + 8 c.  b_inf / b_vis hold nb
@@ -272,23 +337,13 @@ __device__ __forceinline__ void mfma_segment(const Record* __restrict__ rec,
     const int nb = min(kBatch, len - b0);
     __syncthreads();                                   // previous batch consumed (and taps staged)
     {
-      // each work-item loads its share of the batch: all loads first, then the LDS writes
-      const int t = threadIdx.x;
-      const Record r = t < nb ? rec[begin + b0 + t] : Record{0, 0};
-      float2 w[P];
-#pragma unroll
-      for (int j = 0; j < P; ++j) {
-        const int e = t + j * 256;
-        w[j] = e < nb * P ? wvis[(int64_t)(begin + b0) * P + e] : make_float2(0.f, 0.f);
-      }
-      if (t < nb) b_inf[t] = stage_info(r, d);
-#pragma unroll
-      for (int j = 0; j < P; ++j)
-        if (t + j * 256 < nb * P) b_vis[t + j * 256] = w[j];
-      if (nb & 1) {                                    // pad an odd batch (nb <= 255 here)
-        if (t == 0) b_inf[nb] = stage_info(rec[begin + b0 + nb - 1], d);
-        if (t < P) b_vis[nb * P + t] = make_float2(0.f, 0.f);
-      }
+      // wave w stages visibilities 64 w .. 64 w + 63 of the batch in pairing
+      // order within that quarter (pairs never straddle quarters); the quarter
+      // holding the last visibility of an odd batch (nb <= 255 here) pads slot nb
+      const int cb = wave * 64;
+      const int n = max(0, min(64, nb - cb));
+      const int pad = ((nb & 1) && nb - cb > 0 && nb - cb <= 64) ? nb - cb : -1;
+      stage_pairs<P>(rec, wvis, (int64_t)begin + b0 + cb, n, win_x0, win_y0, d, b_inf + cb, b_vis + cb * P, pad);
     }
     __syncthreads();
     mfma_batch<P, CPLX, WCG, NG, 4 * RG>(b_inf, b_vis, nb, lds, row0, win_x0, d, acc);
@@ -357,21 +412,8 @@ grid_mfma_waves(const Record* __restrict__ rec, const float2* __restrict__ wvis,
       // the wave's own slice: LDS operations of one wave execute in order, so
       // only the compiler must be kept from moving accesses across these points
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      const Record r = lane < nb ? rec[begin + b0 + lane] : Record{0, 0};
-      float2 w[P];
-#pragma unroll
-      for (int j = 0; j < P; ++j) {
-        const int e = lane + j * 64;
-        w[j] = e < nb * P ? wvis[(int64_t)(begin + b0) * P + e] : make_float2(0.f, 0.f);
-      }
-      if (lane < nb) b_inf[lane] = stage_info(r, d);
-#pragma unroll
-      for (int j = 0; j < P; ++j)
-        if (lane + j * 64 < nb * P) b_vis[lane + j * 64] = w[j];
-      if (nb & 1) {                                    // pad an odd batch (nb <= 63 here)
-        if (lane == 0) b_inf[nb] = stage_info(rec[begin + b0 + nb - 1], d);
-        if (lane < P) b_vis[nb * P + lane] = make_float2(0.f, 0.f);
-      }
+      // an odd batch (nb <= 63 here) is padded in slot nb
+      stage_pairs<P>(rec, wvis, (int64_t)begin + b0, nb, win_x0, win_y0, d, b_inf, b_vis, (nb & 1) ? nb : -1);
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       mfma_batch<P, CPLX, WCG, NG, PARTS * RG, CPLX>(b_inf, b_vis, nb, lds, row0, win_x0, d, acc);
     }
