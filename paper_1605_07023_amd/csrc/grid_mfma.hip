@@ -33,10 +33,12 @@
 //    16 waves then work without block barriers, each taking
 //    (segment, part) items from an atomic counter, where part p of a window is
 //    the row groups p, p + parts, p + 2 parts, ...  Each wave stages its own
-//    batches of 64 visibilities in its own LDS slice, each as its footprint
-//    origin and the offsets of its two tap rows (decoded once, not per use).
-//    With complex taps the staged table carries the negated imaginary parts
-//    as well, so that each lane reads its B value with one 4-byte load.
+//    batches of 64 visibilities in its own LDS slice, sorted into pairs of
+//    nearby footprints, each visibility as the LDS addresses of its two tap
+//    rows and each pair as the mask of D tiles it touches (decoded once, not
+//    per use).  Its table entries are (-Im, Re, Im) triples, so that every
+//    operand is one read at a lane-constant offset, clamped to the tap row by
+//    one v_med3 on its address.
 //  * grid_mfma_kernel: one 256-thread block per segment, its 4 waves sharing
 //    the segment's window rows (the form used when the table leaves too little
 //    LDS for 16 wave slices).
@@ -67,6 +69,11 @@ constexpr int kBatch = 256;        // visibilities staged per batch (block forms
 constexpr int kBatchWindow = 64;   // window of the batch gridder (batches bin for it)
 constexpr int kWaveBatch = 64;     // visibilities staged per batch (wave form)
 
+// LDS bytes of one wave's staging slice: staged rows, visibilities, pair masks
+__host__ __device__ constexpr size_t wave_slice_bytes(int n_pol) {
+  return (size_t)kWaveBatch * (sizeof(int4) + (size_t)n_pol * sizeof(float2)) + (kWaveBatch / 2) * sizeof(uint32_t);
+}
+
 template <bool CPLX>
 using TapT = typename std::conditional<CPLX, float2, float>::type;
 
@@ -93,11 +100,8 @@ __device__ __forceinline__ float b_value(const TapT<CPLX>* row, int tap, int S, 
 }
 
 // Stage the tap table as FP32 rows [plane * O + s] of S + 2 entries, with one
-// zero before and after the S taps.
-// With NEG (complex taps, wave form) the rows are followed by a second table of
-// the negated imaginary parts, [row][S + 2] floats, so that every B value is a
-// single 4-byte read (see mfma_batch).
-template <bool CPLX, bool NEG = false>
+// zero before and after the S taps (block forms).
+template <bool CPLX>
 __device__ __forceinline__ void stage_taps(TapT<CPLX>* __restrict__ lds, const void* __restrict__ taps,
                                            const MfmaDev& d) {
   const int S = d.S, SP = d.S + 2;
@@ -110,7 +114,6 @@ __device__ __forceinline__ void stage_taps(TapT<CPLX>* __restrict__ lds, const v
       const float re = in ? load_tap32(taps, 2 * src, d.tap_dtype) : 0.f;
       const float im = in ? load_tap32(taps, 2 * src + 1, d.tap_dtype) : 0.f;
       lds[e] = make_float2(re, im);
-      if constexpr (NEG) reinterpret_cast<float*>(lds + n_elem)[e] = -im;
     } else {
       lds[e] = in ? load_tap32(taps, src, d.tap_dtype) : 0.f;
     }
@@ -190,11 +193,192 @@ __device__ __forceinline__ void stage_pairs(const Record* __restrict__ rec, cons
   if (pad >= 0 && lane < P) b_vis[pad * P + lane] = make_float2(0.f, 0.f);
 }
 
+// ---- wave form --------------------------------------------------------------
+// The wave form keeps its tap table as entries of ES bytes: with complex taps
+// the triple (-Im g, Re g, Im g), so that every operand a lane needs is one
+// aligned read at a lane-constant offset (A of component 0 reads (-Im, Re) at
+// offset 0, component 1 reads (Re, Im) at offset 4; B reads Re at 4, Im at 8,
+// -Im at 0); with real taps the tap alone.  Rows are S + 2 entries with a zero
+// entry before and after the taps, and tap indices are clamped to that row as
+// LDS byte addresses (one v_med3 per operand).
+typedef __attribute__((address_space(3))) const float lds_float;
+struct __attribute__((aligned(4))) Pair4 {
+  float a, b;
+};
+typedef __attribute__((address_space(3))) const Pair4 lds_pair;
+
+__device__ __forceinline__ float lds_read(uint32_t addr) { return *(lds_float*)(uintptr_t)addr; }
+__device__ __forceinline__ Pair4 lds_read2(uint32_t addr) {
+  lds_pair* p = (lds_pair*)(uintptr_t)addr;
+  return Pair4{p->a, p->b};
+}
+
+__device__ __forceinline__ uint32_t clamp_addr(uint32_t a, uint32_t lo, uint32_t hi) {
+  int r;   // signed: an address below the row (negative tap index) clamps to its start
+  asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"((int)a), "v"((int)lo), "v"((int)hi));
+  return (uint32_t)r;
+}
+
+template <bool CPLX>
+__device__ __forceinline__ void stage_taps_wave(float* __restrict__ lds, const void* __restrict__ taps,
+                                                const MfmaDev& d) {
+  const int S = d.S, SP = d.S + 2;
+  const int n_elem = d.n_rows_tab * SP;
+  for (int e = threadIdx.x; e < n_elem; e += blockDim.x) {
+    const int row = e / SP, k = e - row * SP - 1;
+    const bool in = k >= 0 && k < S;
+    const int64_t src = (int64_t)row * S + (in ? k : 0);
+    if constexpr (CPLX) {
+      const float re = in ? load_tap32(taps, 2 * src, d.tap_dtype) : 0.f;
+      const float im = in ? load_tap32(taps, 2 * src + 1, d.tap_dtype) : 0.f;
+      lds[3 * e] = -im;
+      lds[3 * e + 1] = re;
+      lds[3 * e + 2] = im;
+    } else {
+      lds[e] = in ? load_tap32(taps, src, d.tap_dtype) : 0.f;
+    }
+  }
+}
+
+// Stage up to 64 visibilities of a segment batch (one per lane, lanes < n live)
+// for the wave form, in pairing order (pair_rank).  Per visibility: {B start,
+// B row, A start, A row}, LDS byte addresses of its G^u and G^v rows (row =
+// first entry, start = row - ES * its window-relative x0 or y0), and its
+// visibilities.  Per pair: the row groups (bits 0..15) and column groups (bits
+// 16..23) of the window that either footprint touches.  Slot `pad` (>= 0 for
+// an odd batch) takes a copy of the last visibility's rows with zero
+// visibility.  Called by all 64 lanes of a wave.
+template <int P, bool CPLX>
+__device__ __forceinline__ void stage_wave(const Record* __restrict__ rec, const float2* __restrict__ wvis,
+                                           int64_t first, int n, int win_x0, int win_y0, const MfmaDev& d,
+                                           uint32_t tab_base, int4* __restrict__ b_inf,
+                                           float2* __restrict__ b_vis, uint32_t* __restrict__ b_box, int pad) {
+  constexpr int ES = CPLX ? 12 : 4;
+  constexpr int RG = 16 / P;
+  const int lane = threadIdx.x & 63;
+  const bool live = lane < n;
+  const Record r = live ? rec[first + lane] : Record{0, 0};
+  float2 w[P];
+  if constexpr (P == 4) {
+    const float4* src = reinterpret_cast<const float4*>(wvis + (first + (live ? lane : 0)) * 4);
+    const float4 a = live ? src[0] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 b = live ? src[1] : make_float4(0.f, 0.f, 0.f, 0.f);
+    w[0] = make_float2(a.x, a.y); w[1] = make_float2(a.z, a.w);
+    w[2] = make_float2(b.x, b.y); w[3] = make_float2(b.z, b.w);
+  } else {
+    w[0] = live ? wvis[first + lane] : make_float2(0.f, 0.f);
+  }
+  const int xr = rec_x0(r) - win_x0, yr = rec_y0(r) - win_y0;
+  const uint32_t key = live ? (((spread6((uint32_t)xr) | (spread6((uint32_t)yr) << 1)) << 6) | (uint32_t)lane)
+                            : ((1u << 20) | (uint32_t)lane);
+  uint32_t sk = key;
+#pragma unroll
+  for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const uint32_t other = (uint32_t)__shfl_xor((int)sk, j);
+      const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
+      sk = keep_min ? min(sk, other) : max(sk, other);
+    }
+  }
+  // lane i holds the i-th key: its visibility's rank goes back to the owner, its
+  // footprint origin comes to lane i, and lane i^1 holds the pair partner's
+  const int src_lane = (int)(sk & 63u);
+  const int rank = __builtin_amdgcn_ds_permute(src_lane << 2, lane);
+  const int xy_own = xr | (yr << 8);
+  const int xy = __builtin_amdgcn_ds_bpermute(src_lane << 2, xy_own);
+  const int xy_partner = __shfl_xor(xy, 1);
+  if (live) {
+    const int rowlen = (d.S + 2) * ES;
+    const uint32_t bl = tab_base + (uint32_t)((rec_plane(r) * d.O + rec_sx(r)) * rowlen);
+    const uint32_t al = tab_base + (uint32_t)((rec_plane(r) * d.O + rec_sy(r)) * rowlen);
+    const int4 inf = make_int4((int)(bl - (uint32_t)(xr * ES)), (int)bl, (int)(al - (uint32_t)(yr * ES)), (int)al);
+    b_inf[rank] = inf;
+#pragma unroll
+    for (int p = 0; p < P; ++p) b_vis[rank * P + p] = w[p];
+    if (pad >= 0 && rank == n - 1) b_inf[pad] = inf;
+  }
+  if (pad >= 0 && lane < P) b_vis[pad * P + lane] = make_float2(0.f, 0.f);
+  if ((lane & 1) == 0 && lane < n) {
+    const int xb = (lane + 1 < n) ? xy_partner : xy;
+    const int xa_ = xy & 0xff, ya_ = xy >> 8, xb_ = xb & 0xff, yb_ = xb >> 8;
+    const int g_lo = min(ya_, yb_) / RG, g_hi = (max(ya_, yb_) + d.S - 1) / RG;
+    const int c_lo = min(xa_, xb_) >> 3, c_hi = (max(xa_, xb_) + d.S - 1) >> 3;
+    const uint32_t rbits = ((2u << g_hi) - 1u) & ~((1u << g_lo) - 1u);
+    const uint32_t cbits = ((2u << c_hi) - 1u) & ~((1u << c_lo) - 1u);
+    b_box[lane >> 1] = rbits | (cbits << 16);
+  }
+}
+
+// The work of one wave of the wave form on one staged batch: row groups
+// part + j * PARTS (j < NG) and all WCG column groups of the window.
+template <int P, bool CPLX, int WCG, int NG, int PARTS>
+__device__ __forceinline__ void wave_batch(const int4* __restrict__ b_inf, const float2* __restrict__ b_vis,
+                                           const uint32_t* __restrict__ b_box, int nb, int part, int S,
+                                           f4 (&acc)[NG][WCG]) {
+  constexpr int RG = 16 / P;
+  constexpr int ES = CPLX ? 12 : 4;
+  const int lane = threadIdx.x & 63;
+  const int kk = lane >> 4;                          // K index: (v, re|im)
+  const int v = kk >> 1, comp = kk & 1;
+  const int m = lane & 15;                           // A row / B column
+  const int ar = (P == 4) ? (m >> 2) : m;
+  const int ap = (P == 4) ? (m & 3) : 0;
+  const int bx = m >> 1, bcomp = m & 1;
+  // lane-constant parts of the operand addresses
+  const uint32_t sel_b = CPLX ? (comp == 1 && bcomp == 0 ? 0u : comp == 0 && bcomp == 1 ? 8u : 4u) : 0u;
+  const uint32_t span_b = (CPLX || comp == bcomp) ? (uint32_t)((S + 1) * ES) : 0u;   // 0: always the zero entry
+  const uint32_t off_b = (uint32_t)((bx + 1) * ES) + sel_b;
+  const uint32_t sel_a = CPLX ? (uint32_t)(comp * 4) : 0u;
+  const uint32_t span_a = (uint32_t)((S + 1) * ES);
+  const uint32_t off_a = (uint32_t)((part * RG + ar + 1) * ES) + sel_a;
+  for (int q = 0; q < nb; q += 2) {
+    const int4 inf = b_inf[q + v];
+    const float2 vv = b_vis[(q + v) * P + ap];
+    const uint32_t box = __builtin_amdgcn_readfirstlane(b_box[q >> 1]);
+    float bfr[WCG];
+    {
+      const uint32_t lo = (uint32_t)inf.y + sel_b, hi = lo + span_b;
+      const uint32_t b = (uint32_t)inf.x + off_b;
+#pragma unroll
+      for (int c = 0; c < WCG; ++c) bfr[c] = lds_read(clamp_addr(b + (uint32_t)(c * 8 * ES), lo, hi));
+    }
+    float afr[NG];
+    {
+      const uint32_t lo = (uint32_t)inf.w + sel_a, hi = lo + span_a;
+      const uint32_t a = (uint32_t)inf.z + off_a;
+      if constexpr (CPLX) {
+#pragma unroll
+        for (int j = 0; j < NG; ++j) {
+          const Pair4 t = lds_read2(clamp_addr(a + (uint32_t)(j * PARTS * RG * ES), lo, hi));
+          afr[j] = t.a * vv.y + t.b * vv.x;           // component comp of G^v V
+        }
+      } else {
+        const float vs = comp ? vv.y : vv.x;
+#pragma unroll
+        for (int j = 0; j < NG; ++j)
+          afr[j] = lds_read(clamp_addr(a + (uint32_t)(j * PARTS * RG * ES), lo, hi)) * vs;
+      }
+    }
+    const uint32_t rb = box >> part, cm = box >> 16;
+#pragma unroll
+    for (int j = 0; j < NG; ++j) {
+      if (__builtin_expect((rb >> (j * PARTS)) & 1u, 1)) {
+#pragma unroll
+        for (int c = 0; c < WCG; ++c) {
+          if (__builtin_expect((cm >> c) & 1u, 1))
+            acc[j][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[j], bfr[c], acc[j][c], 0, 0, 0);
+        }
+      }
+    }
+  }
+}
+
 // The work of one wave on one batch of a segment: the window rows of the NG
 // row groups whose first rows are row0 + j * GSTRIDE (j < NG), all WCG column
 // groups of the window at columns win_x0 + 8 c.  b_inf / b_vis hold nb
 // staged visibilities.
-template <int P, bool CPLX, int WCG, int NG, int GSTRIDE, bool NEG = false>
+template <int P, bool CPLX, int WCG, int NG, int GSTRIDE>
 __device__ __forceinline__ void mfma_batch(const int4* __restrict__ b_inf,
                                            const float2* __restrict__ b_vis, int nb,
                                            const TapT<CPLX>* __restrict__ lds, int row0, int win_x0,
@@ -212,11 +396,6 @@ __device__ __forceinline__ void mfma_batch(const int4* __restrict__ b_inf,
   const int bx = m >> 1, bcomp = m & 1;
   const bool sel_re = comp == bcomp;
   const float sgn = comp == 0 ? 1.f : -1.f;
-  // NEG layout: (comp, bcomp) = (0,0) Re from the (re, im) rows, (0,1) Im,
-  // (1,0) -Im from the negated-imaginary rows, (1,1) Re; byte base and stride
-  const bool use_neg = comp == 1 && bcomp == 0;
-  const int bstride = use_neg ? 4 : 8;
-  const int bbase = use_neg ? d.n_rows_tab * (S + 2) * 8 : (comp == 0 && bcomp == 1 ? 4 : 0);
   // an odd batch carries a zero visibility with the last one's footprint in
   // slot nb, so every pair is whole
   for (int q = 0; q < nb; q += 2) {
@@ -247,18 +426,9 @@ __device__ __forceinline__ void mfma_batch(const int4* __restrict__ b_inf,
       }
     }
     float bfr[WCG];
-    if constexpr (NEG && CPLX) {
-      const int rowbase = bbase + tabu * bstride;
 #pragma unroll
-      for (int c = 0; c < WCG; ++c) {
-        const int idx = clamp_tap(win_x0 + c * 8 + bx - x0v, S);
-        bfr[c] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(lds) + rowbase + idx * bstride);
-      }
-    } else {
-#pragma unroll
-      for (int c = 0; c < WCG; ++c)
-        bfr[c] = b_value<CPLX>(lds + tabu, win_x0 + c * 8 + bx - x0v, S, sel_re, sgn);
-    }
+    for (int c = 0; c < WCG; ++c)
+      bfr[c] = b_value<CPLX>(lds + tabu, win_x0 + c * 8 + bx - x0v, S, sel_re, sgn);
     // wave-uniform masks of the D tiles either footprint touches
     uint32_t rmask = 0;
 #pragma unroll
@@ -381,14 +551,14 @@ grid_mfma_waves(const Record* __restrict__ rec, const float2* __restrict__ wvis,
   constexpr int RG = 16 / P;
   constexpr int PARTS = WR / RG / NG;
   static_assert(PARTS * NG * RG == WR, "window rows must split into parts of NG row groups");
-  using Tap = TapT<CPLX>;
+  static_assert(WR / RG <= 16 && WCG <= 8, "pair masks hold 16 row groups and 8 column groups");
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  Tap* lds = reinterpret_cast<Tap*>(lds_raw);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  int4* b_inf = reinterpret_cast<int4*>(lds_raw + tap_bytes +
-                                        (size_t)wave * kWaveBatch * (sizeof(int4) + P * sizeof(float2)));
+  int4* b_inf = reinterpret_cast<int4*>(lds_raw + tap_bytes + (size_t)wave * wave_slice_bytes(P));
   float2* b_vis = reinterpret_cast<float2*>(b_inf + kWaveBatch);
-  stage_taps<CPLX, CPLX>(lds, taps, d);
+  uint32_t* b_box = reinterpret_cast<uint32_t*>(b_vis + kWaveBatch * P);
+  const uint32_t tab_base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned char*)lds_raw;
+  stage_taps_wave<CPLX>(reinterpret_cast<float*>(lds_raw), taps, d);
   __syncthreads();                                    // the only block barrier
   const int n_items = *n_segs_p * PARTS;
   for (;;) {
@@ -413,9 +583,10 @@ grid_mfma_waves(const Record* __restrict__ rec, const float2* __restrict__ wvis,
       // only the compiler must be kept from moving accesses across these points
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       // an odd batch (nb <= 63 here) is padded in slot nb
-      stage_pairs<P>(rec, wvis, (int64_t)begin + b0, nb, win_x0, win_y0, d, b_inf, b_vis, (nb & 1) ? nb : -1);
+      stage_wave<P, CPLX>(rec, wvis, (int64_t)begin + b0, nb, win_x0, win_y0, d, tab_base, b_inf, b_vis, b_box,
+                          (nb & 1) ? nb : -1);
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      mfma_batch<P, CPLX, WCG, NG, PARTS * RG, CPLX>(b_inf, b_vis, nb, lds, row0, win_x0, d, acc);
+      wave_batch<P, CPLX, WCG, NG, PARTS>(b_inf, b_vis, b_box, nb, part, d.S, acc);
     }
     flush_window<P, WCG, NG, PARTS * RG>(acc, row0, win_x0, grid, d);
   }
@@ -528,8 +699,9 @@ int wave_parts(int n_pol, int wr) {
   return wr / rg / ng;
 }
 
-size_t tap_lds_bytes(const gr_kernel& k, bool neg = false) {
-  const size_t per = k.taps_complex ? (neg ? 12 : 8) : 4;
+// wave = true: the wave form's (-Im, Re, Im) entries; false: the block forms' (Re, Im)
+size_t tap_lds_bytes(const gr_kernel& k, bool wave = false) {
+  const size_t per = k.taps_complex ? (wave ? 12 : 8) : 4;
   return align256((size_t)k.n_planes * k.oversample * (k.support + 2) * per);
 }
 
@@ -578,7 +750,7 @@ gr_status launch_mfma(const void* bins, const BinLayout& L, int n_pol, const gr_
   // wave form when the table leaves room for the wave slices
   const WaveShape ws = wave_shape(wr);
   const size_t wave_lds = tap_lds_bytes(k, true) +
-                          (size_t)(ws.threads / 64) * kWaveBatch * (sizeof(int4) + n_pol * sizeof(float2));
+                          (size_t)(ws.threads / 64) * wave_slice_bytes(n_pol);
   if (wave_lds <= 160 * 1024) {
     WaveFn fn;
     if (n_pol == 4) fn = k.taps_complex ? wave_fn<4, true>(wr) : wave_fn<4, false>(wr);
