@@ -653,7 +653,9 @@ using WaveFn = void (*)(const Record*, const float2*, const int4*, const int32_t
 struct WaveShape {
   int threads, blocks_per_cu;
 };
-WaveShape wave_shape(int) { return WaveShape{1024, 1}; }
+// P = 4 with the 32-cell window: one wave takes all 8 row groups (no parts), so
+// the accumulators allow three waves per SIMD (12 per CU)
+WaveShape wave_shape(int wr, int n_pol) { return WaveShape{wr == 32 && n_pol == 4 ? 768 : 1024, 1}; }
 using PersistFn = void (*)(const BatchInst*, const int32_t*, int, const int32_t*, int32_t*);
 
 // window edge (cells) for a support: footprints of a tile of edge WR - S fit it
@@ -678,12 +680,14 @@ PersistFn persist_fn(int wr) {
   return grid_mfma_persistent<P, CPLX, 64, 8>;
 }
 
-// Wave-form configurations: NG row groups per wave, chosen so that the
-// accumulators (NG x WCG x 4 registers) leave room for 4 waves per SIMD.
+// Wave-form configurations: NG row groups per wave and block size.  The
+// accumulators take NG x WCG x 4 registers; 4 waves per SIMD where they leave
+// room, 3 for P = 4 with the 32-cell window, where one wave taking the whole
+// window (8 row groups) measured faster than two parts at 4 waves per SIMD.
 template <int P, bool CPLX>
 WaveFn wave_fn(int wr) {
   if constexpr (P == 4) {
-    if (wr == 32) return grid_mfma_waves<4, CPLX, 32, 4, 4, 1024>;
+    if (wr == 32) return grid_mfma_waves<4, CPLX, 32, 4, 8, 768>;
     if (wr == 48) return grid_mfma_waves<4, CPLX, 48, 6, 3, 1024>;
     return grid_mfma_waves<4, CPLX, 64, 8, 2, 1024>;
   } else {
@@ -695,7 +699,7 @@ WaveFn wave_fn(int wr) {
 
 int wave_parts(int n_pol, int wr) {
   const int rg = 16 / n_pol;
-  const int ng = n_pol == 4 ? (wr == 48 ? 3 : wr == 32 ? 4 : 2) : 1;
+  const int ng = n_pol == 4 ? (wr == 48 ? 3 : wr == 32 ? 8 : 2) : 1;
   return wr / rg / ng;
 }
 
@@ -748,7 +752,7 @@ gr_status launch_mfma(const void* bins, const BinLayout& L, int n_pol, const gr_
   const int wr = window_of(k.support);
   if (L.tile + k.support > wr) return fail(GR_EINVAL, "binning tile does not fit the gridder window");
   // wave form when the table leaves room for the wave slices
-  const WaveShape ws = wave_shape(wr);
+  const WaveShape ws = wave_shape(wr, n_pol);
   const size_t wave_lds = tap_lds_bytes(k, true) +
                           (size_t)(ws.threads / 64) * wave_slice_bytes(n_pol);
   if (wave_lds <= 160 * 1024) {
