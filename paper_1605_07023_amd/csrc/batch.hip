@@ -66,7 +66,8 @@ struct Plan {
   size_t off_table, off_members, off_prefix, off_counters, bytes;
   std::vector<size_t> off_inst;      // per instance: preprocess buffers, then bins
   std::vector<BinLayout> bins;
-  std::vector<size_t> lds;           // MFMA LDS bytes per instance
+  std::vector<size_t> lds;           // MFMA LDS bytes per instance ((Re, Im) table entries)
+  std::vector<size_t> lds_tri;       // the same with triple entries
   int64_t total_blocks;
 };
 
@@ -116,11 +117,13 @@ gr_status make_plan(const gr_batch_item* items, int n, Plan* p) {
   p->off_inst.resize(n);
   p->bins.resize(n);
   p->lds.resize(n);
+  p->lds_tri.resize(n);
   p->total_blocks = 0;
   for (int i = 0; i < n; ++i) {
     const gr_batch_item& it = items[i];
     gr_status st = validate_item(it, i, &p->lds[i]);
     if (st != GR_OK) return st;
+    p->lds_tri[i] = block_lds_bytes(it.kernel, it.n_pol, true);
     p->off_inst[i] = off;
     // the persistent block-form gridder works on 64-cell windows: tiles of 64 - S
     // keep its segments dense even in sparse instances
@@ -179,8 +182,8 @@ extern "C" gr_status gr_grid_batch(const gr_batch_item* items, int32_t n_items, 
   int64_t blk = 0;
   int n_members[kGroups] = {0, 0, 0, 0};
   size_t lds_group[kGroups] = {0, 0, 0, 0};
+  size_t lds_tri_group[kGroups] = {0, 0, 0, 0};
   int64_t segs_group[kGroups] = {0, 0, 0, 0};
-  int max_support[kGroups] = {0, 0, 0, 0};
   for (int i = 0; i < n_items; ++i) {
     const gr_batch_item& it = items[i];
     const BinLayout& L = p.bins[i];
@@ -231,7 +234,7 @@ extern "C" gr_status gr_grid_batch(const gr_batch_item* items, int32_t n_items, 
     I.group = g;
     ++n_members[g];
     lds_group[g] = std::max(lds_group[g], p.lds[i]);
-    max_support[g] = std::max(max_support[g], (int)it.kernel.support);
+    lds_tri_group[g] = std::max(lds_tri_group[g], p.lds_tri[i]);
     segs_group[g] += L.max_segs;
   }
   for (int first = 0; first < n_items; first += kSetupChunk) {
@@ -250,9 +253,11 @@ extern "C" gr_status gr_grid_batch(const gr_batch_item* items, int32_t n_items, 
   for (int g = 0; g < kGroups; ++g) {
     if (n_members[g] == 0) continue;
     const int n_blocks = (int)std::min<int64_t>(resident, std::max<int64_t>(segs_group[g], 1));
+    // triple table entries when every member's table fits them
+    const bool tri = lds_tri_group[g] <= 160 * 1024;
     st = launch_mfma_persistent(table, members + g * n_items, n_members[g], prefix + g * (n_items + 1),
-                                counters + g, (g & 2) ? 4 : 1, (g & 1) != 0, lds_group[g], max_support[g],
-                                n_blocks, s);
+                                counters + g, (g & 2) ? 4 : 1, (g & 1) != 0, tri,
+                                tri ? lds_tri_group[g] : lds_group[g], n_blocks, s);
     if (st != GR_OK) return st;
   }
   return GR_OK;

@@ -521,24 +521,76 @@ __device__ __forceinline__ void mfma_segment(const Record* __restrict__ rec,
   flush_window<P, WCG, NG, 4 * RG>(acc, row0, win_x0, grid, d);
 }
 
+// Block form with the wave form's operands (triple table entries, staged row
+// addresses and pair masks): wave w stages quarter w of each 256-visibility
+// batch in pairing order and works on row groups w, w + 4, ... of every pair.
 template <int P, bool CPLX, int WR, int WCG>
+__device__ __forceinline__ void mfma_segment_tri(const Record* __restrict__ rec,
+                                                 const float2* __restrict__ wvis, const int4 sg,
+                                                 uint32_t tab_base, int4* __restrict__ b_inf,
+                                                 float2* __restrict__ b_vis, uint32_t* __restrict__ b_box,
+                                                 float2* __restrict__ grid, const MfmaDev& d) {
+  constexpr int RG = 16 / P;
+  constexpr int NG = WR / RG / 4;
+  static_assert(NG * RG * 4 == WR, "window rows must split into row groups over 4 waves");
+  static_assert(WR / RG <= 16 && WCG <= 8, "pair masks hold 16 row groups and 8 column groups");
+  const int wave = threadIdx.x >> 6;
+  const int begin = sg.x, len = sg.y, tile_id = sg.z;
+  const int win_x0 = (tile_id % d.n_tx) * d.tile;
+  const int win_y0 = (tile_id / d.n_tx) * d.tile;
+  const int row0 = win_y0 + wave * RG;
+  f4 acc[NG][WCG];
+#pragma unroll
+  for (int j = 0; j < NG; ++j)
+#pragma unroll
+    for (int c = 0; c < WCG; ++c) acc[j][c] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int b0 = 0; b0 < len; b0 += kBatch) {
+    const int nb = min(kBatch, len - b0);
+    __syncthreads();                                   // previous batch consumed (and taps staged)
+    {
+      // the quarter holding the last visibility of an odd batch (nb <= 255) pads slot nb
+      const int cb = wave * 64;
+      const int n = max(0, min(64, nb - cb));
+      const int pad = ((nb & 1) && nb - cb > 0 && nb - cb <= 64) ? nb - cb : -1;
+      stage_wave<P, CPLX>(rec, wvis, (int64_t)begin + b0 + cb, n, win_x0, win_y0, d, tab_base, b_inf + cb,
+                          b_vis + cb * P, b_box + cb / 2, pad);
+    }
+    __syncthreads();
+    wave_batch<P, CPLX, WCG, NG, 4>(b_inf, b_vis, b_box, nb, wave, d.S, acc);
+  }
+  flush_window<P, WCG, NG, 4 * RG>(acc, row0, win_x0, grid, d);
+}
+
+// LDS of the block forms: staging slices, then the tap table
+__host__ __device__ constexpr size_t block_slice_bytes(int n_pol, bool tri) {
+  return (size_t)kBatch * (sizeof(int4) + (size_t)n_pol * sizeof(float2)) + (tri ? (kBatch / 2) * sizeof(uint32_t) : 0);
+}
+
+template <int P, bool CPLX, int WR, int WCG, bool TRI>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 grid_mfma_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvis,
                  const int4* __restrict__ segs, const int32_t* __restrict__ n_segs_p,
                  const void* __restrict__ taps, float2* __restrict__ grid, MfmaDev d) {
-  using Tap = TapT<CPLX>;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   int4* b_inf = reinterpret_cast<int4*>(lds_raw);                               // [kBatch]
   float2* b_vis = reinterpret_cast<float2*>(lds_raw + kBatch * sizeof(int4));    // [kBatch][P]
-  Tap* lds = reinterpret_cast<Tap*>(lds_raw + kBatch * sizeof(int4) + kBatch * P * sizeof(float2));
+  unsigned char* tab = lds_raw + block_slice_bytes(P, TRI);
   // Segments are listed in tile order and their count is only known on the
   // device, so blocks take segments in dispatch order: consecutive segments
   // (neighbouring tiles) land on different XCDs, which spreads the dense
   // centre of the uv plane over the whole chip.
   const int seg = (int)blockIdx.x;
   if (seg >= *n_segs_p) return;                       // uniform for the block
-  stage_taps<CPLX>(lds, taps, d);
-  mfma_segment<P, CPLX, WR, WCG>(rec, wvis, segs[seg], lds, b_inf, b_vis, grid, d);
+  if constexpr (TRI) {
+    uint32_t* b_box = reinterpret_cast<uint32_t*>(b_vis + kBatch * P);
+    const uint32_t tab_base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned char*)tab;
+    stage_taps_wave<CPLX>(reinterpret_cast<float*>(tab), taps, d);
+    mfma_segment_tri<P, CPLX, WR, WCG>(rec, wvis, segs[seg], tab_base, b_inf, b_vis, b_box, grid, d);
+  } else {
+    stage_taps<CPLX>(reinterpret_cast<TapT<CPLX>*>(tab), taps, d);
+    mfma_segment<P, CPLX, WR, WCG>(rec, wvis, segs[seg], reinterpret_cast<const TapT<CPLX>*>(tab), b_inf, b_vis,
+                                   grid, d);
+  }
 }
 
 // Wave form (see the file header).  PARTS = (WR / RG) / NG items per segment.
@@ -597,16 +649,15 @@ grid_mfma_waves(const Record* __restrict__ rec, const float2* __restrict__ wvis,
 // the tap table is restaged only when the instance changes.  Every block exits
 // once the counter passes the item total, which the prefix kernel wrote before
 // this launch.
-template <int P, bool CPLX, int WR, int WCG>
+template <int P, bool CPLX, int WR, int WCG, bool TRI>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 grid_mfma_persistent(const BatchInst* __restrict__ inst, const int32_t* __restrict__ members,
                      int n_members, const int32_t* __restrict__ prefix,
                      int32_t* __restrict__ counter) {
-  using Tap = TapT<CPLX>;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   int4* b_inf = reinterpret_cast<int4*>(lds_raw);
   float2* b_vis = reinterpret_cast<float2*>(lds_raw + kBatch * sizeof(int4));
-  Tap* lds = reinterpret_cast<Tap*>(lds_raw + kBatch * sizeof(int4) + kBatch * P * sizeof(float2));
+  unsigned char* tab = lds_raw + block_slice_bytes(P, TRI);
   __shared__ int s_inst, s_seg;
   const int total = prefix[n_members];
   int staged = -1;
@@ -632,11 +683,22 @@ grid_mfma_persistent(const BatchInst* __restrict__ inst, const int32_t* __restri
     if (ii < 0) break;
     const BatchInst& I = inst[ii];
     const MfmaDev d = I.d;
-    if (ii != staged) {
-      stage_taps<CPLX>(lds, I.taps, d);
-      staged = ii;
+    if constexpr (TRI) {
+      if (ii != staged) {
+        stage_taps_wave<CPLX>(reinterpret_cast<float*>(tab), I.taps, d);
+        staged = ii;
+      }
+      uint32_t* b_box = reinterpret_cast<uint32_t*>(b_vis + kBatch * P);
+      const uint32_t tab_base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned char*)tab;
+      mfma_segment_tri<P, CPLX, WR, WCG>(I.brec, I.bwvis, I.segs[ls], tab_base, b_inf, b_vis, b_box, I.grid, d);
+    } else {
+      if (ii != staged) {
+        stage_taps<CPLX>(reinterpret_cast<TapT<CPLX>*>(tab), I.taps, d);
+        staged = ii;
+      }
+      mfma_segment<P, CPLX, WR, WCG>(I.brec, I.bwvis, I.segs[ls], reinterpret_cast<const TapT<CPLX>*>(tab), b_inf,
+                                     b_vis, I.grid, d);
     }
-    mfma_segment<P, CPLX, WR, WCG>(I.brec, I.bwvis, I.segs[ls], lds, b_inf, b_vis, I.grid, d);
   }
 }
 
@@ -662,22 +724,34 @@ using PersistFn = void (*)(const BatchInst*, const int32_t*, int, const int32_t*
 int window_of(int support) { return support <= 16 ? 32 : support <= 32 ? 48 : 64; }
 
 // Block forms: 4 waves share the window rows, so P = 1 (16-row groups) needs 64 rows.
-template <int P, bool CPLX>
+template <int P, bool CPLX, bool TRI>
 MfmaFn block_fn(int wr) {
   if constexpr (P == 4) {
-    if (wr == 32) return grid_mfma_kernel<4, CPLX, 32, 4>;
-    if (wr == 48) return grid_mfma_kernel<4, CPLX, 48, 6>;
+    if (wr == 32) return grid_mfma_kernel<4, CPLX, 32, 4, TRI>;
+    if (wr == 48) return grid_mfma_kernel<4, CPLX, 48, 6, TRI>;
   }
-  return grid_mfma_kernel<P, CPLX, 64, 8>;
+  return grid_mfma_kernel<P, CPLX, 64, 8, TRI>;
 }
 
-template <int P, bool CPLX>
+template <int P, bool CPLX, bool TRI>
 PersistFn persist_fn(int wr) {
   if constexpr (P == 4) {
-    if (wr == 32) return grid_mfma_persistent<4, CPLX, 32, 4>;
-    if (wr == 48) return grid_mfma_persistent<4, CPLX, 48, 6>;
+    if (wr == 32) return grid_mfma_persistent<4, CPLX, 32, 4, TRI>;
+    if (wr == 48) return grid_mfma_persistent<4, CPLX, 48, 6, TRI>;
   }
-  return grid_mfma_persistent<P, CPLX, 64, 8>;
+  return grid_mfma_persistent<P, CPLX, 64, 8, TRI>;
+}
+
+template <bool TRI>
+MfmaFn block_fn_for(int n_pol, bool cplx, int wr) {
+  if (n_pol == 4) return cplx ? block_fn<4, true, TRI>(wr) : block_fn<4, false, TRI>(wr);
+  return cplx ? block_fn<1, true, TRI>(wr) : block_fn<1, false, TRI>(wr);
+}
+
+template <bool TRI>
+PersistFn persist_fn_for(int n_pol, bool cplx, int wr) {
+  if (n_pol == 4) return cplx ? persist_fn<4, true, TRI>(wr) : persist_fn<4, false, TRI>(wr);
+  return cplx ? persist_fn<1, true, TRI>(wr) : persist_fn<1, false, TRI>(wr);
 }
 
 // Wave-form configurations: NG row groups per wave and block size.  The
@@ -724,9 +798,13 @@ int device_cus() {
 
 int binned_tile(int support, int window) { return (window > 0 ? window : window_of(support)) - support; }
 
+size_t block_lds_bytes(const gr_kernel& k, int n_pol, bool tri) {
+  return tap_lds_bytes(k, tri) + block_slice_bytes(n_pol, tri);
+}
+
 gr_status plan_mfma(const gr_kernel& k, int n_pol, size_t* lds_bytes) {
   if (k.support > 56) return fail(GR_EUNSUPPORTED, "MFMA gridder needs support <= 56");
-  const size_t lds = tap_lds_bytes(k) + (size_t)kBatch * (sizeof(int4) + (size_t)n_pol * sizeof(float2));
+  const size_t lds = block_lds_bytes(k, n_pol, false);
   if (lds > 160 * 1024) return fail(GR_EUNSUPPORTED, "tap table does not fit in LDS");
   *lds_bytes = lds;
   return GR_OK;
@@ -771,9 +849,11 @@ gr_status launch_mfma(const void* bins, const BinLayout& L, int n_pol, const gr_
                        nsegs, counter, k.taps, grid, d, (uint32_t)tap_lds_bytes(k, true));
     return check_launch("gr_grid_binned (mfma waves)");
   }
-  MfmaFn fn;
-  if (n_pol == 4) fn = k.taps_complex ? block_fn<4, true>(wr) : block_fn<4, false>(wr);
-  else fn = k.taps_complex ? block_fn<1, true>(wr) : block_fn<1, false>(wr);
+  // block form: triple entries when they fit, else (Re, Im) pairs
+  const size_t lds_tri = block_lds_bytes(k, n_pol, true);
+  const bool tri = lds_tri <= 160 * 1024;
+  if (tri) lds = lds_tri;
+  const MfmaFn fn = tri ? block_fn_for<true>(n_pol, k.taps_complex, wr) : block_fn_for<false>(n_pol, k.taps_complex, wr);
   if ((st = ensure_lds_limit(reinterpret_cast<const void*>(fn), lds, "gr_grid_binned")) != GR_OK) return st;
   hipLaunchKernelGGL(fn, dim3((unsigned)nb), dim3(256), lds, stream, rec, wv, segs, nsegs, k.taps,
                      grid, d);
@@ -782,14 +862,12 @@ gr_status launch_mfma(const void* bins, const BinLayout& L, int n_pol, const gr_
 
 gr_status launch_mfma_persistent(const BatchInst* inst, const int32_t* members, int n_members,
                                  const int32_t* group_prefix, int32_t* counter, int n_pol,
-                                 bool complex_taps, size_t lds_bytes, int max_support, int n_blocks,
+                                 bool complex_taps, bool tri, size_t lds_bytes, int n_blocks,
                                  hipStream_t stream) {
   if (n_members == 0 || n_blocks <= 0) return GR_OK;
-  (void)max_support;
   const int wr = kBatchWindow;
-  PersistFn fn;
-  if (n_pol == 4) fn = complex_taps ? persist_fn<4, true>(wr) : persist_fn<4, false>(wr);
-  else fn = complex_taps ? persist_fn<1, true>(wr) : persist_fn<1, false>(wr);
+  const PersistFn fn = tri ? persist_fn_for<true>(n_pol, complex_taps, wr)
+                           : persist_fn_for<false>(n_pol, complex_taps, wr);
   gr_status st = ensure_lds_limit(reinterpret_cast<const void*>(fn), lds_bytes, "gr_grid_batch");
   if (st != GR_OK) return st;
   hipLaunchKernelGGL(fn, dim3((unsigned)n_blocks), dim3(256), lds_bytes, stream, inst, members, n_members,

@@ -81,6 +81,9 @@ gr_status launch_bin(const Record* rec, const float2* wvis, int64_t n_vis, int n
 
 // MFMA gridder over the binned stream (grid_mfma.hip).
 gr_status plan_mfma(const gr_kernel& k, int n_pol, size_t* lds_bytes);
+// LDS bytes of the block-form MFMA gridder: tri = (-Im, Re, Im) table entries
+// (the form used where they fit), else (Re, Im) pairs (what plan_mfma checks)
+size_t block_lds_bytes(const gr_kernel& k, int n_pol, bool tri);
 gr_status launch_mfma(const void* bins, const BinLayout& L, int n_pol, const gr_kernel& k,
                       float2* grid, int height, int width, hipStream_t stream);
 
@@ -152,11 +155,12 @@ gr_status launch_batch_bin(const BatchInst* inst, int n_inst, int64_t total_bloc
                            hipStream_t stream);
 // Persistent MFMA gridder over the segments of the instances `members`
 // (group_prefix: [n_members + 1] exclusive prefix of their segment counts,
-// written on the device; counter: zeroed work counter).
-// max_support: the largest support among the members (it sets the window).
+// written on the device; counter: zeroed work counter).  The gridder works on
+// 64-cell windows; tri selects the triple-entry tap table (block_lds_bytes with
+// tri = true must fit every member), lds_bytes is the largest member's need.
 gr_status launch_mfma_persistent(const BatchInst* inst, const int32_t* members, int n_members,
                                  const int32_t* group_prefix, int32_t* counter, int n_pol,
-                                 bool complex_taps, size_t lds_bytes, int max_support, int n_blocks,
+                                 bool complex_taps, bool tri, size_t lds_bytes, int n_blocks,
                                  hipStream_t stream);
 
 }  // namespace gr

@@ -154,6 +154,25 @@ def test_grid_points_mfma(R, S, P, seg):
     assert stats.cpu().tolist() == [wl.n_vis - dropped, dropped] and dropped > 0
 
 
+# The single-problem MFMA gridder has three forms, chosen by the LDS its tap
+# table needs (complex W taps, S = 32, O = 8: 408 B per table row as (-Im, Re, Im)
+# triples, 272 B as (Re, Im) pairs; 160 KiB of LDS):
+#   wave form: table + 16 wave slices (P = 4: 3200 B, P = 1: 1664 B each);
+#   block form, triple entries: table + 12,800 B (P = 4) / 6,656 B (P = 1);
+#   block form, (Re, Im) pairs: pair table + 12,288 B (P = 4).
+# 40 planes (320 rows) at P = 4 take the triple block form, 60 planes (480 rows)
+# the pair block form, 48 planes (384 rows) at P = 1 the triple block form.
+@pytest.mark.parametrize("P,planes,seg", [(4, 40, 0), (4, 40, 77), (4, 60, 0), (1, 48, 9)])
+def test_grid_points_mfma_block_forms(R, P, planes, seg):
+    _say(f"grid random points MFMA block forms P={P} planes={planes} seg_len={seg}")
+    wl = random_point_workload(3001, P, 160, 144, 32, 8, seed=planes + P, n_planes=planes, margin=6,
+                               weights=True, kernel="wsep")
+    dw = R.upload(wl, DEV)
+    g = R.grid(dw, tune=R.tuning(vis_per_wg=seg, variant=2)).cpu().numpy()
+    ref, _ = _oracle_grid(wl, _oracle_taps(wl))
+    assert _rel_l2(g, ref) <= 1e-5
+
+
 def test_bin_is_a_grouping_of_the_valid_stream(R):
     """gr_bin output: every valid record exactly once, each segment inside its
     tile, segment lengths <= seg_len, input order kept within runs."""
