@@ -243,7 +243,7 @@ def main() -> int:
     rec = torch.empty((N, 2), dtype=torch.int32, device=dev)
     wvis = torch.empty((N, P), dtype=torch.complex64, device=dev)
     stats = torch.zeros(2, dtype=torch.int64, device=dev)
-    bins_bytes = max(B.gr_bin_bytes(N, P, S, wls[S].height, wls[S].width, seg_len[S]) for S in supports)
+    bins_bytes = max(B.gr_preprocess_bin_bytes(N, P, S, wls[S].height, wls[S].width, seg_len[S]) for S in supports)
     bins = torch.empty(bins_bytes, dtype=torch.uint8, device=dev) if variant == 2 else None
     stream = torch.cuda.current_stream(dev)
     ev = {S: [] for S in supports}
@@ -251,10 +251,15 @@ def main() -> int:
     def step(record: bool):
         for S in supports:
             wl = wls[S]
-            B.gr_preprocess(uvw, vis, vis_dt, vis_scale, None, N, P, kern[S], wl.inv_cell_u,
-                            wl.inv_cell_v, wl.height, wl.width, rec, wvis, stats, stream)
             if variant == 2:
-                B.gr_bin(rec, wvis, N, P, S, wl.height, wl.width, seg_len[S], bins, bins_bytes, stream)
+                # preprocess and bin fused: records and tile counts from uvw, then the
+                # weighted visibilities straight to their binned positions
+                B.gr_preprocess_bin(uvw, vis, vis_dt, vis_scale, None, N, P, kern[S], wl.inv_cell_u,
+                                    wl.inv_cell_v, wl.height, wl.width, seg_len[S], bins, bins_bytes, stats,
+                                    stream)
+            else:
+                B.gr_preprocess(uvw, vis, vis_dt, vis_scale, None, N, P, kern[S], wl.inv_cell_u,
+                                wl.inv_cell_v, wl.height, wl.width, rec, wvis, stats, stream)
             if record:
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(stream)

@@ -138,17 +138,44 @@ gr_status gr_bin(const void* records, const void* wvis, int64_t n_vis, int32_t n
                  int32_t support, int32_t height, int32_t width, int32_t seg_len, void* bins,
                  size_t bins_bytes, void* stream);
 
+/* Size in bytes of the `bins` buffer of gr_preprocess_bin: gr_bin_bytes plus
+ * 8 bytes per visibility, 256-aligned (0 if the arguments are invalid). */
+size_t gr_preprocess_bin_bytes(int64_t n_vis, int32_t n_pol, int32_t support, int32_t height,
+                               int32_t width, int32_t seg_len);
+
+/* gr_preprocess followed by gr_bin without the intermediate weighted
+ * visibilities (Section 4's preprocessing, and the binning of gr_bin): a
+ * first pass reads only uvw and writes the records and the per-tile counts,
+ * a second pass reads each kept record with its visibilities and weights and
+ * writes both, weighted, to the binned position.  The first gr_bin_bytes
+ * bytes of bins then hold exactly what gr_bin would write (the input to
+ * gr_grid_binned with the same n_vis, n_pol, support, height, width and
+ * seg_len); the rest holds the unbinned records.  A visibility whose values
+ * or weights are not finite is dropped as by gr_preprocess: it is counted as
+ * dropped in dev_stats and contributes nothing, but keeps a slot of zero
+ * values in its tile list.  Arguments as gr_preprocess and gr_bin;
+ * bins_bytes >= gr_preprocess_bin_bytes; support <= 56; n_vis < 2^31.
+ * About 112 bytes of HBM traffic per quad-polarisation visibility against
+ * 184 for gr_preprocess + gr_bin. */
+gr_status gr_preprocess_bin(const double* uvw, const void* vis, int32_t vis_dtype,
+                            const float* vis_scale, const float* weights, int64_t n_vis,
+                            int32_t n_pol, const gr_kernel* kernel, double inv_cell_u,
+                            double inv_cell_v, int32_t height, int32_t width, int32_t seg_len,
+                            void* bins, size_t bins_bytes, int64_t* dev_stats, void* stream);
+
 /* Grid a binned stream (gr_bin output; the same n_vis, n_pol, support,
  * height, width and seg_len) onto grid (+=).  Per segment, the W x W-cell
  * window is accumulated in matrix-core registers: the separable tile update
  * of Section 4, in the factored form G^u_i (G^v_j V_p) of Section 6, is a
  * rank-2 product per pair of visibilities (v_mfma_f32_16x16x4_f32), and the
  * window is added to the grid once with FP32 atomic adds (Section 2.2).
- * The tap table is staged in LDS once per block: one 1024-thread block per
- * compute unit whose 16 waves take (segment, row part) work from a counter in
- * the bins workspace, or, when the table leaves too little LDS for that,
- * one 256-thread block per segment.
- * support <= 56; the FP32 tap table [planes][O][S] must fit in 160 KiB.
+ * The tap table is staged in LDS once per block: one block per compute unit
+ * (1024 threads; 768 for W = 32 with n_pol = 4) whose waves take (segment,
+ * row part) work from a counter in the bins workspace and stage their own
+ * visibility batches, or, when the table leaves too little LDS for that, one
+ * 256-thread block per segment.
+ * support <= 56; the FP32 tap table [planes][O][S + 2] as (Re, Im) pairs plus
+ * 12 KiB of staging must fit in 160 KiB.
  * With a GR_TABLE2D kernel the non-separable taps are read per visibility
  * from the [planes][O][O][S][S] table instead: each work-item keeps a 4 x 4
  * block of the window per polarisation in registers.  With a GR_MLP kernel
@@ -163,9 +190,10 @@ gr_status gr_grid_binned(const void* bins, int64_t n_vis, int32_t n_pol, const g
 size_t gr_grid_workspace_bytes(int64_t n_vis, int32_t n_pol, const gr_kernel* kernel,
                                int32_t height, int32_t width, const gr_tuning* tuning);
 
-/* The whole hot path: gr_preprocess into `workspace`, then either
- * gr_grid_records (variant 1) or gr_bin + gr_grid_binned (variant 2; chosen
- * by default when the kernel allows it).  Same semantics as those calls. */
+/* The whole hot path: either gr_preprocess into `workspace` then
+ * gr_grid_records (variant 1), or gr_preprocess_bin into `workspace` then
+ * gr_grid_binned (variant 2; chosen by default when the kernel allows it).
+ * Same semantics as those calls. */
 gr_status gr_grid(const double* uvw, const void* vis, int32_t vis_dtype, const float* vis_scale,
                   const float* weights, int64_t n_vis, int32_t n_pol, const gr_kernel* kernel,
                   double inv_cell_u, double inv_cell_v, void* grid, int32_t height,

@@ -126,32 +126,53 @@ extern "C" size_t gr_bin_bytes(int64_t n_vis, int32_t n_pol, int32_t support, in
   return bin_layout(n_vis, n_pol, support, height, width, seg_len > 0 ? seg_len : kDefaultSegLen).bytes;
 }
 
+extern "C" size_t gr_preprocess_bin_bytes(int64_t n_vis, int32_t n_pol, int32_t support, int32_t height,
+                                          int32_t width, int32_t seg_len) {
+  if (n_vis < 0 || n_pol < 1 || support < 2 || support > 56 || height < 1 || width < 1) return 0;
+  return bin_layout(n_vis, n_pol, support, height, width, seg_len > 0 ? seg_len : kDefaultSegLen).bytes +
+         align256(sizeof(Record) * (size_t)n_vis);
+}
+
 extern "C" size_t gr_grid_workspace_bytes(int64_t n_vis, int32_t n_pol, const gr_kernel* kernel,
                                           int32_t height, int32_t width, const gr_tuning* tuning) {
   if (n_vis < 0 || n_pol < 1 || kernel == nullptr || height < 1 || width < 1) return 0;
-  size_t b = pre_bytes(n_vis, n_pol);
-  if (pick_variant(*kernel, n_pol, tuning) == 2)
-    b += bin_layout(n_vis, n_pol, kernel->support, height, width, seg_len_of(tuning)).bytes;
-  return b;
+  if (pick_variant(*kernel, n_pol, tuning) == 2)     // fused preprocess and bin
+    return bin_layout(n_vis, n_pol, kernel->support, height, width, seg_len_of(tuning)).bytes +
+           align256(sizeof(Record) * (size_t)n_vis);
+  return pre_bytes(n_vis, n_pol);
 }
 
-extern "C" gr_status gr_preprocess(const double* uvw, const void* vis, int32_t vis_dtype,
-                                   const float* vis_scale, const float* weights, int64_t n_vis,
-                                   int32_t n_pol, const gr_kernel* kernel, double inv_cell_u,
-                                   double inv_cell_v, int32_t height, int32_t width,
-                                   void* records, void* wvis, int64_t* dev_stats, void* stream) {
+namespace {
+// arguments common to gr_preprocess and gr_preprocess_bin
+gr_status validate_raw_inputs(const char* who, const double* uvw, const void* vis, int32_t vis_dtype,
+                              const float* vis_scale, int64_t n_vis, int32_t n_pol, const gr_kernel* kernel,
+                              double inv_cell_u, double inv_cell_v, int32_t height, int32_t width) {
   gr_status st = validate_kernel(kernel, false);
   if (st != GR_OK) return st;
   if ((st = validate_grid(n_pol, height, width, kernel->support)) != GR_OK) return st;
   if (n_vis < 0) return fail(GR_EINVAL, "n_vis must be >= 0");
-  if (n_vis > 0 && (uvw == nullptr || vis == nullptr || records == nullptr || wvis == nullptr))
-    return fail(GR_EINVAL, "gr_preprocess: uvw, vis, records and wvis must be non-NULL");
+  if (n_vis > 0 && (uvw == nullptr || vis == nullptr))
+    return fail(GR_EINVAL, std::string(who) + ": uvw and vis must be non-NULL");
   if (vis_dtype != GR_F32 && vis_dtype != GR_F16)
     return fail(GR_EINVAL, "vis_dtype must be GR_F32 (complex64) or GR_F16 (scaled half pairs)");
   if (vis_dtype == GR_F16 && n_vis > 0 && vis_scale == nullptr)
     return fail(GR_EINVAL, "GR_F16 visibilities need vis_scale");
   if (!std::isfinite(inv_cell_u) || !std::isfinite(inv_cell_v) || inv_cell_u <= 0 || inv_cell_v <= 0)
     return fail(GR_EINVAL, "inv_cell_u / inv_cell_v must be finite and > 0");
+  return GR_OK;
+}
+}  // namespace
+
+extern "C" gr_status gr_preprocess(const double* uvw, const void* vis, int32_t vis_dtype,
+                                   const float* vis_scale, const float* weights, int64_t n_vis,
+                                   int32_t n_pol, const gr_kernel* kernel, double inv_cell_u,
+                                   double inv_cell_v, int32_t height, int32_t width,
+                                   void* records, void* wvis, int64_t* dev_stats, void* stream) {
+  gr_status st = validate_raw_inputs("gr_preprocess", uvw, vis, vis_dtype, vis_scale, n_vis, n_pol, kernel,
+                                     inv_cell_u, inv_cell_v, height, width);
+  if (st != GR_OK) return st;
+  if (n_vis > 0 && (records == nullptr || wvis == nullptr))
+    return fail(GR_EINVAL, "gr_preprocess: records and wvis must be non-NULL");
   return launch_preprocess(uvw, vis, vis_dtype, vis_scale, weights, n_vis, n_pol, *kernel, inv_cell_u,
                            inv_cell_v, height, width, reinterpret_cast<Record*>(records),
                            reinterpret_cast<float2*>(wvis), dev_stats, (hipStream_t)stream);
@@ -195,6 +216,26 @@ extern "C" gr_status gr_bin(const void* records, const void* wvis, int64_t n_vis
                     n_pol, L, bins, (hipStream_t)stream);
 }
 
+extern "C" gr_status gr_preprocess_bin(const double* uvw, const void* vis, int32_t vis_dtype,
+                                       const float* vis_scale, const float* weights, int64_t n_vis,
+                                       int32_t n_pol, const gr_kernel* kernel, double inv_cell_u,
+                                       double inv_cell_v, int32_t height, int32_t width, int32_t seg_len,
+                                       void* bins, size_t bins_bytes, int64_t* dev_stats, void* stream) {
+  gr_status st = validate_raw_inputs("gr_preprocess_bin", uvw, vis, vis_dtype, vis_scale, n_vis, n_pol, kernel,
+                                     inv_cell_u, inv_cell_v, height, width);
+  if (st != GR_OK) return st;
+  if (kernel->support > 56) return fail(GR_EINVAL, "gr_preprocess_bin: support must be <= 56");
+  if (n_vis > 0x7fffffffLL) return fail(GR_EINVAL, "gr_preprocess_bin: n_vis must be in [0, 2^31)");
+  if (bins == nullptr) return fail(GR_EINVAL, "bins is NULL");
+  const BinLayout L = bin_layout(n_vis, n_pol, kernel->support, height, width,
+                                 seg_len > 0 ? seg_len : kDefaultSegLen);
+  if (bins_bytes < L.bytes + align256(sizeof(Record) * (size_t)n_vis))
+    return fail(GR_ENOMEM, "bins buffer too small (see gr_preprocess_bin_bytes)");
+  auto* rec_tmp = reinterpret_cast<Record*>(reinterpret_cast<char*>(bins) + L.bytes);
+  return launch_preprocess_bin(uvw, vis, vis_dtype, vis_scale, weights, n_vis, n_pol, *kernel, inv_cell_u,
+                               inv_cell_v, height, width, L, bins, rec_tmp, dev_stats, (hipStream_t)stream);
+}
+
 extern "C" gr_status gr_grid_binned(const void* bins, int64_t n_vis, int32_t n_pol, const gr_kernel* kernel,
                                     int32_t seg_len, void* grid, int32_t height, int32_t width, void* stream) {
   gr_status st = validate_kernel(kernel, true);
@@ -233,18 +274,21 @@ extern "C" gr_status gr_grid(const double* uvw, const void* vis, int32_t vis_dty
     if (kernel->support > 56) return fail(GR_EUNSUPPORTED, "the binned gridders need support <= 56");
     if (n_vis > 0x7fffffffLL) return fail(GR_EINVAL, "n_vis must be < 2^31 for the binned gridders");
   }
-  auto* rec = reinterpret_cast<Record*>(workspace);
-  auto* wv = reinterpret_cast<float2*>(reinterpret_cast<char*>(workspace) +
-                                       align256(sizeof(Record) * (size_t)n_vis));
-  st = gr_preprocess(uvw, vis, vis_dtype, vis_scale, weights, n_vis, n_pol, kernel, inv_cell_u,
-                     inv_cell_v, height, width, rec, wv, dev_stats, stream);
-  if (st != GR_OK) return st;
-  if (variant == 1)
+  if (variant == 1) {
+    auto* rec = reinterpret_cast<Record*>(workspace);
+    auto* wv = reinterpret_cast<float2*>(reinterpret_cast<char*>(workspace) +
+                                         align256(sizeof(Record) * (size_t)n_vis));
+    st = gr_preprocess(uvw, vis, vis_dtype, vis_scale, weights, n_vis, n_pol, kernel, inv_cell_u,
+                       inv_cell_v, height, width, rec, wv, dev_stats, stream);
+    if (st != GR_OK) return st;
     return launch_romein(rec, wv, n_vis, n_pol, *kernel, reinterpret_cast<float2*>(grid), height, width,
                          plan, (hipStream_t)stream);
-  void* bins = reinterpret_cast<char*>(workspace) + pre_bytes(n_vis, n_pol);
+  }
+  // binned path: preprocess and bin fused, then the binned gridder
+  st = gr_preprocess_bin(uvw, vis, vis_dtype, vis_scale, weights, n_vis, n_pol, kernel, inv_cell_u, inv_cell_v,
+                         height, width, seg_len_of(tuning), workspace, workspace_bytes, dev_stats, stream);
+  if (st != GR_OK) return st;
   const BinLayout L = bin_layout(n_vis, n_pol, kernel->support, height, width, seg_len_of(tuning));
-  if ((st = launch_bin(rec, wv, n_vis, n_pol, L, bins, (hipStream_t)stream)) != GR_OK) return st;
-  return launch_binned(bins, L, n_pol, *kernel, reinterpret_cast<float2*>(grid), height, width,
+  return launch_binned(workspace, L, n_pol, *kernel, reinterpret_cast<float2*>(grid), height, width,
                        (hipStream_t)stream);
 }

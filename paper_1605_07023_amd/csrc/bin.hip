@@ -12,7 +12,10 @@
 // Kernels: count (wave-aggregated atomics per tile), scan (one block:
 // offsets, segment table), scatter (wave-aggregated reservation, stable
 // within each wave's 64 entries).
+#include <algorithm>
+
 #include "internal.h"
+#include "prep.h"
 
 namespace gr {
 
@@ -101,22 +104,13 @@ bin_scan_kernel(const int32_t* __restrict__ count, int n_tiles, int seg_len,
   bin_scan_block(count, n_tiles, seg_len, cursor, segs, n_segs_out);
 }
 
-__device__ __forceinline__ void bin_scatter_one(const Record* __restrict__ rec,
-                                                const float2* __restrict__ wvis, int64_t n,
-                                                int64_t i, int n_pol, int tile, int n_tx,
-                                                int32_t* __restrict__ cursor,
-                                                Record* __restrict__ out_rec,
-                                                float2* __restrict__ out_wvis) {
+// List position of each lane's entry (lanes with key >= 0): the wave's lanes
+// are grouped by tile, each lane learning its group's first lane, its rank in
+// the group and (for the first lane) the group size; then all groups reserve
+// their list space with one atomic instruction.  Keeps lane order within a
+// group.  Called by all 64 lanes.
+__device__ __forceinline__ int reserve_grouped(int key, int32_t* __restrict__ cursor) {
   const int lane = threadIdx.x & 63;
-  int key = -1;
-  Record r{0, 0};
-  if (i < n) {
-    r = rec[i];
-    if (rec_valid(r)) key = tile_of(r, tile, n_tx);
-  }
-  // group the wave's lanes by tile: each lane learns its group's first lane,
-  // its rank in the group and (for the first lane) the group size; then all
-  // groups reserve their list space with one atomic instruction
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   int leader = lane, rank = 0, count = 0;
   uint64_t todo = __ballot(key >= 0);
@@ -134,8 +128,23 @@ __device__ __forceinline__ void bin_scatter_one(const Record* __restrict__ rec,
   int base = 0;
   if (key >= 0 && lane == leader) base = atomicAdd(&cursor[key], count);
   base = __shfl(base, leader);
+  return base + rank;
+}
+
+__device__ __forceinline__ void bin_scatter_one(const Record* __restrict__ rec,
+                                                const float2* __restrict__ wvis, int64_t n,
+                                                int64_t i, int n_pol, int tile, int n_tx,
+                                                int32_t* __restrict__ cursor,
+                                                Record* __restrict__ out_rec,
+                                                float2* __restrict__ out_wvis) {
+  int key = -1;
+  Record r{0, 0};
+  if (i < n) {
+    r = rec[i];
+    if (rec_valid(r)) key = tile_of(r, tile, n_tx);
+  }
+  const int pos = reserve_grouped(key, cursor);
   if (key >= 0) {
-    const int pos = base + rank;
     out_rec[pos] = r;
     for (int p = 0; p < n_pol; ++p) out_wvis[(int64_t)pos * n_pol + p] = wvis[i * n_pol + p];
   }
@@ -147,6 +156,75 @@ bin_scatter_kernel(const Record* __restrict__ rec, const float2* __restrict__ wv
                    Record* __restrict__ out_rec, float2* __restrict__ out_wvis) {
   bin_scatter_one(rec, wvis, n, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, n_pol, tile, n_tx,
                   cursor, out_rec, out_wvis);
+}
+
+// ---- preprocess and bin in one pass over the visibilities -------------------
+// Pass 1 reads only uvw: the record from the coordinates (into an unbinned
+// record array) and the per-tile counts.  Pass 2, after the scan, reads the
+// record, the visibilities and the weights, applies the weights and writes
+// both to the binned position.  A visibility whose values are not finite
+// stays in its list with zero values and moves from the kept to the dropped
+// count, so the grid and the statistics are those of gr_preprocess + gr_bin.
+
+__global__ void __launch_bounds__(256)
+prebin_count_kernel(prep::PreArgs a, int tile, int n_tx, int32_t* __restrict__ count,
+                    unsigned long long* __restrict__ stats) {
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int n_ok = 0, n_drop = 0;
+  // grid-stride by whole waves, so the wave-wide votes below see every lane
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); i0 < a.n; i0 += stride) {
+    const int64_t i = i0 + lane;
+    int key = -1;
+    if (i < a.n) {
+      const Record r = prep::coord_record(i, a);
+      a.rec[i] = r;
+      if (rec_valid(r)) {
+        key = tile_of(r, tile, n_tx);
+        ++n_ok;
+      } else {
+        ++n_drop;
+      }
+    }
+    uint64_t todo = __ballot(key >= 0);
+    while (todo) {
+      const int leader = __ffsll((unsigned long long)todo) - 1;
+      const int k = __shfl(key, leader);
+      const uint64_t same = __ballot(key == k);
+      if (lane == leader) atomicAdd(&count[k], (int32_t)__popcll(same));
+      todo &= ~same;
+    }
+  }
+  prep::add_block_counts(n_ok, n_drop, stats);
+}
+
+template <int VDT, int P>
+__global__ void __launch_bounds__(256)
+prebin_scatter_kernel(prep::PreArgs a, int tile, int n_tx, int32_t* __restrict__ cursor,
+                      Record* __restrict__ out_rec, float2* __restrict__ out_wvis,
+                      unsigned long long* __restrict__ stats) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int key = -1;
+  Record r{0, 0};
+  if (i < a.n) {
+    r = a.rec[i];
+    if (rec_valid(r)) key = tile_of(r, tile, n_tx);
+  }
+  float2 vw[P];
+  bool bad = false;
+  if (key >= 0) bad = !prep::weighted_vis<VDT, P>(i, a, vw);
+  const int pos = reserve_grouped(key, cursor);
+  if (key >= 0) {
+    out_rec[pos] = r;
+#pragma unroll
+    for (int p = 0; p < P; ++p) out_wvis[(int64_t)pos * P + p] = vw[p];
+  }
+  const uint64_t n_bad = __ballot(bad);
+  if (n_bad != 0 && (threadIdx.x & 63) == 0 && stats != nullptr) {
+    const unsigned long long nb = (unsigned long long)__popcll(n_bad);
+    atomicAdd(&stats[0], 0ull - nb);                // modular: subtracts nb
+    atomicAdd(&stats[1], nb);
+  }
 }
 
 // ---- batched forms (one launch for all instances of a batch) ----------------
@@ -203,6 +281,40 @@ BinLayout bin_layout(int64_t n_vis, int n_pol, int support, int height, int widt
   L.off_nsegs = off;   off += 256;
   L.bytes = off;
   return L;
+}
+
+gr_status launch_preprocess_bin(const double* uvw, const void* vis, int vis_dtype, const float* vis_scale,
+                                const float* weights, int64_t n_vis, int n_pol, const gr_kernel& k,
+                                double inv_cell_u, double inv_cell_v, int height, int width, const BinLayout& L,
+                                void* bins, Record* rec_tmp, int64_t* dev_stats, hipStream_t stream) {
+  char* base = reinterpret_cast<char*>(bins);
+  auto* count = reinterpret_cast<int32_t*>(base + L.off_count);
+  auto* cursor = reinterpret_cast<int32_t*>(base + L.off_cursor);
+  auto* segs = reinterpret_cast<int4*>(base + L.off_segs);
+  auto* nsegs = reinterpret_cast<int32_t*>(base + L.off_nsegs);
+  auto* orec = reinterpret_cast<Record*>(base + L.off_rec);
+  auto* owv = reinterpret_cast<float2*>(base + L.off_wvis);
+  if (L.n_tiles > 0x7fffffff) return fail(GR_EINVAL, "gr_preprocess_bin: too many tiles");
+  const int64_t blocks = (n_vis + 255) / 256;
+  if (blocks > 0x7fffffff) return fail(GR_EINVAL, "gr_preprocess_bin: n_vis too large");
+  fill_i32<<<(unsigned)((L.n_tiles + 255) / 256), 256, 0, stream>>>(count, L.n_tiles, 0);
+  fill_i32<<<1, 256, 0, stream>>>(nsegs, 1, 0);
+  auto* st = reinterpret_cast<unsigned long long*>(dev_stats);
+  const prep::PreArgs a = prep::make_pre_args(uvw, vis, vis_scale, weights, n_vis, n_pol, k, inv_cell_u,
+                                              inv_cell_v, height, width, rec_tmp, nullptr);
+  if (n_vis > 0) {
+    const int64_t cblocks = std::min<int64_t>(blocks, (int64_t)prep::device_cu_count() * 16);
+    prebin_count_kernel<<<(unsigned)cblocks, 256, 0, stream>>>(a, L.tile, L.n_tx, count, st);
+  }
+  bin_scan_kernel<<<1, 1024, 0, stream>>>(count, (int)L.n_tiles, L.seg_len, cursor, segs, nsegs);
+  if (n_vis > 0) {
+    using Fn = void (*)(prep::PreArgs, int, int, int32_t*, Record*, float2*, unsigned long long*);
+    Fn fn;
+    if (n_pol == 4) fn = vis_dtype == GR_F32 ? prebin_scatter_kernel<GR_F32, 4> : prebin_scatter_kernel<GR_F16, 4>;
+    else fn = vis_dtype == GR_F32 ? prebin_scatter_kernel<GR_F32, 1> : prebin_scatter_kernel<GR_F16, 1>;
+    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(256), 0, stream, a, L.tile, L.n_tx, cursor, orec, owv, st);
+  }
+  return check_launch("gr_preprocess_bin");
 }
 
 gr_status launch_bin(const Record* rec, const float2* wvis, int64_t n_vis, int n_pol,

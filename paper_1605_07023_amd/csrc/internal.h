@@ -76,6 +76,12 @@ struct BinLayout {
 int binned_tile(int support, int window = 0);
 BinLayout bin_layout(int64_t n_vis, int n_pol, int support, int height, int width, int seg_len,
                      int window = 0);
+// Preprocess and bin in one pass pair straight from the raw inputs (the
+// binned stream of launch_bin in `bins`; rec_tmp: n_vis unbinned records).
+gr_status launch_preprocess_bin(const double* uvw, const void* vis, int vis_dtype, const float* vis_scale,
+                                const float* weights, int64_t n_vis, int n_pol, const gr_kernel& k,
+                                double inv_cell_u, double inv_cell_v, int height, int width, const BinLayout& L,
+                                void* bins, Record* rec_tmp, int64_t* dev_stats, hipStream_t stream);
 gr_status launch_bin(const Record* rec, const float2* wvis, int64_t n_vis, int n_pol,
                      const BinLayout& L, void* bins, hipStream_t stream);
 

@@ -42,10 +42,14 @@ def test_version_and_workspace(lib):
     k = _kernel()
     n1 = B.gr_grid_workspace_bytes(1000, 4, k, 64, 64, B.GrTuning(0, 0, 0, 0, 0, 1))
     assert n1 >= 1000 * 8 + 1000 * 4 * 8
+    # the binned path preprocesses and bins in one fused pass: the bins plus the unbinned records
     n2 = B.gr_grid_workspace_bytes(1000, 4, k, 64, 64)
-    assert n2 >= 2 * n1 and n2 >= n1 + B.gr_bin_bytes(1000, 4, 16, 64, 64)
+    assert n2 == B.gr_preprocess_bin_bytes(1000, 4, 16, 64, 64)
+    assert n2 >= B.gr_bin_bytes(1000, 4, 16, 64, 64) + 1000 * 8
     assert B.gr_grid_workspace_bytes(-1, 4, k, 64, 64) == 0
     assert B.gr_bin_bytes(10, 4, 58, 64, 64) == 0
+    assert B.gr_preprocess_bin_bytes(10, 4, 58, 64, 64) == 0
+    assert B.gr_preprocess_bin_bytes(-1, 4, 16, 64, 64) == 0
 
 
 def _kernel(**kw):
@@ -115,6 +119,29 @@ def test_preprocess_rejects(lib):
     st = lib.gr_preprocess(1 << 20, 1 << 20, B.GR_F32, None, None, 10, 4, ctypes.byref(k), 0.0, 1.0,
                            64, 64, 1 << 20, 1 << 20, None, None)
     assert st == B.GR_EINVAL and "inv_cell" in lib.gr_last_error().decode()
+
+
+def test_preprocess_bin_rejects(lib):
+    """Host-side validation of gr_preprocess_bin, before anything is enqueued."""
+    from paper_1605_07023_amd import binding as B
+    k = _kernel()
+    need = B.gr_preprocess_bin_bytes(10, 4, 16, 64, 64, 0)
+    call = lambda *a: lib.gr_preprocess_bin(*a)
+    st = call(1 << 20, 1 << 20, B.GR_F32, None, None, 10, 4, ctypes.byref(k), 1.0, 1.0, 64, 64, 0,
+              1 << 20, need - 1, None, None)
+    assert st == B.GR_ENOMEM and "gr_preprocess_bin_bytes" in lib.gr_last_error().decode()
+    st = call(1 << 20, 1 << 20, B.GR_F32, None, None, 10, 4, ctypes.byref(k), 1.0, 1.0, 64, 64, 0,
+              None, need, None, None)
+    assert st == B.GR_EINVAL and "bins" in lib.gr_last_error().decode()
+    st = call(1 << 20, 1 << 20, B.GR_F16, None, None, 10, 4, ctypes.byref(k), 1.0, 1.0, 64, 64, 0,
+              1 << 20, need, None, None)
+    assert st == B.GR_EINVAL and "vis_scale" in lib.gr_last_error().decode()
+    st = call(None, 1 << 20, B.GR_F32, None, None, 10, 4, ctypes.byref(k), 1.0, 1.0, 64, 64, 0,
+              1 << 20, need, None, None)
+    assert st == B.GR_EINVAL and "uvw" in lib.gr_last_error().decode()
+    st = call(1 << 20, 1 << 20, B.GR_F32, None, None, 10, 3, ctypes.byref(k), 1.0, 1.0, 64, 64, 0,
+              1 << 20, need, None, None)
+    assert st == B.GR_EINVAL and "n_pol" in lib.gr_last_error().decode()
 
 
 def test_table_generators_reject(lib):

@@ -173,6 +173,74 @@ def test_grid_points_mfma_block_forms(R, P, planes, seg):
     assert _rel_l2(g, ref) <= 1e-5
 
 
+@pytest.mark.parametrize("P,seg", [(4, 0), (1, 45)])
+def test_preprocess_bin_equals_separate_calls(R, P, seg):
+    """gr_preprocess_bin (fused) + gr_grid_binned against gr_preprocess + gr_bin +
+    gr_grid_binned and the FP64 oracle, with coordinate drops and non-finite
+    visibilities and weights: integer values and taps, so every grid is exact;
+    statistics equal; the fused binned stream holds the same kept entries plus
+    one zero-valued entry per visibility dropped for its values."""
+    from paper_1605_07023_amd import binding as B
+    _say(f"fused preprocess+bin vs separate calls P={P} seg_len={seg}")
+    rng = np.random.default_rng(40 + P)
+    wl = random_point_workload(3000, P, 80, 72, 16, 4, seed=41 + P, n_planes=3, margin=5, weights=True,
+                               kernel="wsep")
+    wl.vis = (rng.integers(-2, 3, (wl.n_vis, P)) + 1j * rng.integers(-2, 3, (wl.n_vis, P))).astype(np.complex64)
+    wl.weights = rng.integers(1, 3, (wl.n_vis, P)).astype(np.float32)
+    wl.uvw[3, 1] = np.nan
+    wl.uvw[4, 2] = np.inf
+    wl.vis[10, P - 1] = np.complex64(complex(0, np.inf))
+    wl.vis[11, 0] = np.complex64(complex(np.nan, 1))
+    wl.weights[12, 0] = np.nan
+    taps = rng.integers(-1, 2, (3, 4, 16)) + 1j * rng.integers(-1, 2, (3, 4, 16))
+    t = torch.from_numpy(np.ascontiguousarray(np.stack([taps.real, taps.imag], axis=-1), dtype=np.float32)).to(DEV)
+    dw = R.upload(wl, DEV, taps=t)
+    k = B.make_kernel(t, 16, 4, 3, taps_complex=True, w_min=wl.w_min, inv_dw=wl.inv_dw)
+    N, H, W = wl.n_vis, wl.height, wl.width
+    # separate calls
+    st_a = torch.zeros(2, dtype=torch.int64, device=DEV)
+    rec = torch.empty((N, 2), dtype=torch.int32, device=DEV)
+    wv = torch.empty((N, P), dtype=torch.complex64, device=DEV)
+    B.gr_preprocess(dw.uvw, dw.vis, B.GR_F32, None, dw.weights, N, P, k, 1.0, 1.0, H, W, rec, wv, st_a)
+    nb_a = B.gr_bin_bytes(N, P, 16, H, W, seg)
+    bins_a = torch.empty(nb_a, dtype=torch.uint8, device=DEV)
+    B.gr_bin(rec, wv, N, P, 16, H, W, seg, bins_a, nb_a)
+    g_a = torch.zeros((P, H, W), dtype=torch.complex64, device=DEV)
+    B.gr_grid_binned(bins_a, N, P, k, seg, g_a, H, W)
+    # fused
+    st_b = torch.zeros(2, dtype=torch.int64, device=DEV)
+    nb_b = B.gr_preprocess_bin_bytes(N, P, 16, H, W, seg)
+    assert nb_b >= nb_a + 8 * N
+    bins_b = torch.empty(nb_b, dtype=torch.uint8, device=DEV)
+    B.gr_preprocess_bin(dw.uvw, dw.vis, B.GR_F32, None, dw.weights, N, P, k, 1.0, 1.0, H, W, seg, bins_b, nb_b,
+                        st_b)
+    g_b = torch.zeros((P, H, W), dtype=torch.complex64, device=DEV)
+    B.gr_grid_binned(bins_b, N, P, k, seg, g_b, H, W)
+    torch.cuda.synchronize()
+    ref, dropped = _oracle_grid(wl, taps)
+    np.testing.assert_array_equal(g_a.cpu().numpy().astype(np.complex128), ref)
+    np.testing.assert_array_equal(g_b.cpu().numpy().astype(np.complex128), ref)
+    assert st_a.cpu().tolist() == st_b.cpu().tolist() == [N - dropped, dropped]
+    # binned streams: kept entries as a multiset of (record, values)
+    coord_ok = G.pixel_coords(wl.uvw, 1.0, 1.0, 4, 16, H, W, 3, wl.w_min, wl.inv_dw)["valid"]
+    value_drops = int((coord_ok & ~G.finite_values(wl.vis, wl.weights)).sum())
+    assert value_drops == 3
+
+    def entries(raw, n_kept):
+        b = raw.cpu().numpy()
+        recs = b[:8 * N].view(np.uint32).reshape(N, 2)[:n_kept]
+        off = (8 * N + 255) // 256 * 256
+        vals = b[off:off + 8 * P * N].view(np.float32).reshape(N, 2 * P)[:n_kept]
+        return sorted(zip(map(tuple, recs.tolist()), map(tuple, vals.tolist())))
+
+    ea, eb = entries(bins_a, N - dropped), entries(bins_b, N - dropped + value_drops)
+    zero = tuple([0.0] * (2 * P))
+    extra = list(eb)
+    for e in ea:
+        extra.remove(e)
+    assert len(extra) == value_drops and all(v == zero for _, v in extra)
+
+
 def test_bin_is_a_grouping_of_the_valid_stream(R):
     """gr_bin output: every valid record exactly once, each segment inside its
     tile, segment lengths <= seg_len, input order kept within runs."""
