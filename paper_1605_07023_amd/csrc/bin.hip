@@ -97,11 +97,110 @@ __device__ __forceinline__ void bin_scan_block(const int32_t* __restrict__ count
   if (t == T - 1) *n_segs_out = (int32_t)s_seg[T - 1];
 }
 
+// ---- parallel scan of the tile counts (single-problem paths) ----------------
+// Three launches: per-block sums of 256 tiles' counts and segment counts, one
+// block scanning those sums, then per block the tile offsets (cursor) and the
+// segment table entries.  Visibility and segment totals fit int32 (n_vis < 2^31).
+constexpr int kScanTiles = 256;
+
+// exclusive block-wide prefix of (a, b) over a 256-thread block; totals in ta, tb
+__device__ __forceinline__ void block_exclusive_scan2(int a, int b, int& pa, int& pb, int& ta, int& tb) {
+  __shared__ int s_a[4], s_b[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int ia = a, ib = b;                                // inclusive scan within the wave
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int xa = __shfl_up(ia, o), xb = __shfl_up(ib, o);
+    if (lane >= o) {
+      ia += xa;
+      ib += xb;
+    }
+  }
+  if (lane == 63) {
+    s_a[wave] = ia;
+    s_b[wave] = ib;
+  }
+  __syncthreads();
+  int oa = 0, ob = 0;
+  ta = 0;
+  tb = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    if (w < wave) {
+      oa += s_a[w];
+      ob += s_b[w];
+    }
+    ta += s_a[w];
+    tb += s_b[w];
+  }
+  pa = oa + ia - a;
+  pb = ob + ib - b;
+}
+
+__global__ void __launch_bounds__(kScanTiles)
+scan_sums_kernel(const int32_t* __restrict__ count, int n_tiles, int seg_len, int32_t* __restrict__ sums) {
+  const int i = blockIdx.x * kScanTiles + threadIdx.x;
+  const int v = i < n_tiles ? count[i] : 0;
+  const int g = (v + seg_len - 1) / seg_len;
+  int pa, pb, ta, tb;
+  block_exclusive_scan2(v, g, pa, pb, ta, tb);
+  if (threadIdx.x == 0) {
+    sums[2 * blockIdx.x] = ta;
+    sums[2 * blockIdx.x + 1] = tb;
+  }
+}
+
+// one 1024-thread block: exclusive prefix of the n_blocks (count, segments)
+// sums in place; the segment total to n_segs_out
 __global__ void __launch_bounds__(1024)
-bin_scan_kernel(const int32_t* __restrict__ count, int n_tiles, int seg_len,
-                int32_t* __restrict__ cursor, int4* __restrict__ segs,
-                int32_t* __restrict__ n_segs_out) {
-  bin_scan_block(count, n_tiles, seg_len, cursor, segs, n_segs_out);
+scan_blocks_kernel(int32_t* __restrict__ sums, int n_blocks, int32_t* __restrict__ n_segs_out) {
+  __shared__ int s_v[1024], s_g[1024];
+  const int t = threadIdx.x, T = blockDim.x;
+  const int per = (n_blocks + T - 1) / T;
+  const int a = min(n_blocks, t * per), b = min(n_blocks, a + per);
+  int v = 0, g = 0;
+  for (int i = a; i < b; ++i) {
+    v += sums[2 * i];
+    g += sums[2 * i + 1];
+  }
+  s_v[t] = v;
+  s_g[t] = g;
+  __syncthreads();
+  for (int off = 1; off < T; off <<= 1) {            // Hillis-Steele inclusive scan
+    int xv = 0, xg = 0;
+    if (t >= off) {
+      xv = s_v[t - off];
+      xg = s_g[t - off];
+    }
+    __syncthreads();
+    s_v[t] += xv;
+    s_g[t] += xg;
+    __syncthreads();
+  }
+  int bv = s_v[t] - v, bg = s_g[t] - g;
+  for (int i = a; i < b; ++i) {
+    const int cv = sums[2 * i], cg = sums[2 * i + 1];
+    sums[2 * i] = bv;
+    sums[2 * i + 1] = bg;
+    bv += cv;
+    bg += cg;
+  }
+  if (t == T - 1) *n_segs_out = s_g[T - 1];
+}
+
+__global__ void __launch_bounds__(kScanTiles)
+scan_write_kernel(const int32_t* __restrict__ count, int n_tiles, int seg_len,
+                  const int32_t* __restrict__ sums, int32_t* __restrict__ cursor, int4* __restrict__ segs) {
+  const int i = blockIdx.x * kScanTiles + threadIdx.x;
+  const int v = i < n_tiles ? count[i] : 0;
+  const int g = (v + seg_len - 1) / seg_len;
+  int pa, pb, ta, tb;
+  block_exclusive_scan2(v, g, pa, pb, ta, tb);
+  if (i >= n_tiles) return;
+  const int base = sums[2 * blockIdx.x] + pa;
+  int sbase = sums[2 * blockIdx.x + 1] + pb;
+  cursor[i] = base;
+  for (int s0 = 0; s0 < v; s0 += seg_len) segs[sbase++] = make_int4(base + s0, min(seg_len, v - s0), i, 0);
 }
 
 // List position of each lane's entry (lanes with key >= 0): the wave's lanes
@@ -279,8 +378,21 @@ BinLayout bin_layout(int64_t n_vis, int n_pol, int support, int height, int widt
   L.off_cursor = off;  off += align256(sizeof(int32_t) * (size_t)L.n_tiles);
   L.off_segs = off;    off += align256(sizeof(int4) * (size_t)L.max_segs);
   L.off_nsegs = off;   off += 256;
+  L.off_scan = off;    off += align256(2 * sizeof(int32_t) * (size_t)((L.n_tiles + kScanTiles - 1) / kScanTiles));
   L.bytes = off;
   return L;
+}
+
+// tile offsets, segment table and segment count from the tile counts
+void launch_scan(const int32_t* count, const BinLayout& L, char* base, hipStream_t stream) {
+  auto* cursor = reinterpret_cast<int32_t*>(base + L.off_cursor);
+  auto* segs = reinterpret_cast<int4*>(base + L.off_segs);
+  auto* nsegs = reinterpret_cast<int32_t*>(base + L.off_nsegs);
+  auto* sums = reinterpret_cast<int32_t*>(base + L.off_scan);
+  const int nb = (int)((L.n_tiles + kScanTiles - 1) / kScanTiles);
+  scan_sums_kernel<<<nb, kScanTiles, 0, stream>>>(count, (int)L.n_tiles, L.seg_len, sums);
+  scan_blocks_kernel<<<1, 1024, 0, stream>>>(sums, nb, nsegs);
+  scan_write_kernel<<<nb, kScanTiles, 0, stream>>>(count, (int)L.n_tiles, L.seg_len, sums, cursor, segs);
 }
 
 gr_status launch_preprocess_bin(const double* uvw, const void* vis, int vis_dtype, const float* vis_scale,
@@ -290,7 +402,6 @@ gr_status launch_preprocess_bin(const double* uvw, const void* vis, int vis_dtyp
   char* base = reinterpret_cast<char*>(bins);
   auto* count = reinterpret_cast<int32_t*>(base + L.off_count);
   auto* cursor = reinterpret_cast<int32_t*>(base + L.off_cursor);
-  auto* segs = reinterpret_cast<int4*>(base + L.off_segs);
   auto* nsegs = reinterpret_cast<int32_t*>(base + L.off_nsegs);
   auto* orec = reinterpret_cast<Record*>(base + L.off_rec);
   auto* owv = reinterpret_cast<float2*>(base + L.off_wvis);
@@ -306,7 +417,7 @@ gr_status launch_preprocess_bin(const double* uvw, const void* vis, int vis_dtyp
     const int64_t cblocks = std::min<int64_t>(blocks, (int64_t)prep::device_cu_count() * 16);
     prebin_count_kernel<<<(unsigned)cblocks, 256, 0, stream>>>(a, L.tile, L.n_tx, count, st);
   }
-  bin_scan_kernel<<<1, 1024, 0, stream>>>(count, (int)L.n_tiles, L.seg_len, cursor, segs, nsegs);
+  launch_scan(count, L, base, stream);
   if (n_vis > 0) {
     using Fn = void (*)(prep::PreArgs, int, int, int32_t*, Record*, float2*, unsigned long long*);
     Fn fn;
@@ -322,7 +433,6 @@ gr_status launch_bin(const Record* rec, const float2* wvis, int64_t n_vis, int n
   char* base = reinterpret_cast<char*>(bins);
   auto* count = reinterpret_cast<int32_t*>(base + L.off_count);
   auto* cursor = reinterpret_cast<int32_t*>(base + L.off_cursor);
-  auto* segs = reinterpret_cast<int4*>(base + L.off_segs);
   auto* nsegs = reinterpret_cast<int32_t*>(base + L.off_nsegs);
   auto* orec = reinterpret_cast<Record*>(base + L.off_rec);
   auto* owv = reinterpret_cast<float2*>(base + L.off_wvis);
@@ -333,7 +443,7 @@ gr_status launch_bin(const Record* rec, const float2* wvis, int64_t n_vis, int n
   if (blocks > 0x7fffffff) return fail(GR_EINVAL, "gr_bin: n_vis too large");
   if (n_vis > 0)
     bin_count_kernel<<<(unsigned)blocks, 256, 0, stream>>>(rec, n_vis, L.tile, L.n_tx, count);
-  bin_scan_kernel<<<1, 1024, 0, stream>>>(count, (int)L.n_tiles, L.seg_len, cursor, segs, nsegs);
+  launch_scan(count, L, base, stream);
   if (n_vis > 0)
     bin_scatter_kernel<<<(unsigned)blocks, 256, 0, stream>>>(rec, wvis, n_vis, n_pol, L.tile, L.n_tx,
                                                             cursor, orec, owv);
