@@ -185,6 +185,30 @@ gr_status gr_preprocess_bin(const double* uvw, const void* vis, int32_t vis_dtyp
 gr_status gr_grid_binned(const void* bins, int64_t n_vis, int32_t n_pol, const gr_kernel* kernel,
                          int32_t seg_len, void* grid, int32_t height, int32_t width, void* stream);
 
+/* Degridding, the adjoint of gridding (Section 6 names degridding with thread
+ * coarsening as the next step): predicts every visibility from the grid
+ * through the same separable GCF,
+ *   vis_out[n][p] = sum_{ky,kx} Tv[plane][sy][ky] Tu[plane][sx][kx] grid[p][y0+ky][x0+kx]
+ * with the indices of gr_preprocess.  With the complex-conjugated taps it is
+ * the exact adjoint of gr_grid for unit weights.  vis_out (device, complex64
+ * [n_vis][n_pol]) is OVERWRITTEN; visibilities dropped by the coordinate rule
+ * of gr_preprocess get 0, and dev_stats (or NULL) receives {kept, dropped}
+ * (added).  The visibilities are binned as for gr_grid_binned (seg_len as
+ * there); then one 1024-thread block per compute unit stages the tap table
+ * once and, per segment, the grid window of all polarisations in LDS; waves
+ * contract it with the G^u rows of 8 visibilities at a time on the matrix
+ * cores (v_mfma_f32_16x16x4_f32) and apply the G^v taps per row.  Each
+ * visibility is written once (deterministic; no atomics).  kernel: separable,
+ * support <= 56, (window x window x n_pol) complex64 plus the (Re, Im) tap
+ * table [planes][O][S + 2] must fit in 160 KiB of LDS (window 32 for S <= 16,
+ * 48 for S <= 32, else 64).  workspace: gr_degrid_workspace_bytes. */
+size_t gr_degrid_workspace_bytes(int64_t n_vis, int32_t n_pol, int32_t support, int32_t height,
+                                 int32_t width, int32_t seg_len);
+gr_status gr_degrid(const double* uvw, int64_t n_vis, int32_t n_pol, const gr_kernel* kernel,
+                    double inv_cell_u, double inv_cell_v, const void* grid, int32_t height,
+                    int32_t width, void* vis_out, int32_t seg_len, void* workspace,
+                    size_t workspace_bytes, int64_t* dev_stats, void* stream);
+
 /* Bytes of workspace gr_grid needs (depends on the variant gr_grid selects
  * for these arguments; 0 if they are invalid). */
 size_t gr_grid_workspace_bytes(int64_t n_vis, int32_t n_pol, const gr_kernel* kernel,

@@ -74,6 +74,7 @@ def load_library():
         "gr_make_wkernel_table": [I32, I32, I32, D, D, I32, D, I32, I32, P, P],
         "gr_bin": [P, P, I64, I32, I32, I32, I32, I32, P, SZ, P],
         "gr_preprocess_bin": [P, P, I32, P, P, I64, I32, KP, D, D, I32, I32, I32, P, SZ, P, P],
+        "gr_degrid": [P, I64, I32, KP, D, D, P, I32, I32, P, I32, P, SZ, P, P],
         "gr_grid_binned": [P, I64, I32, KP, I32, P, I32, I32, P],
         "gr_autotune": [P, P, I64, I32, KP, P, I32, I32, P, SZ, TP, I32, I32, P, P, P],
         "gr_make_wkernel2d_table": [I32, I32, I32, D, D, D, I32, D, I32, I32, P, P],
@@ -92,6 +93,8 @@ def load_library():
     lib.gr_bin_bytes.restype = SZ
     lib.gr_preprocess_bin_bytes.argtypes = [I64, I32, I32, I32, I32, I32]
     lib.gr_preprocess_bin_bytes.restype = SZ
+    lib.gr_degrid_workspace_bytes.argtypes = [I64, I32, I32, I32, I32, I32]
+    lib.gr_degrid_workspace_bytes.restype = SZ
     lib.gr_last_error.argtypes = []
     lib.gr_last_error.restype = ctypes.c_char_p
     lib.gr_grid_batch.argtypes = [ctypes.POINTER(GrBatchItem), I32, P, SZ, P]
@@ -168,6 +171,18 @@ def gr_preprocess_bin(uvw, vis, vis_dtype, vis_scale, weights, n_vis, n_pol, ker
                                             n_vis, n_pol, ctypes.byref(kernel), inv_cell_u, inv_cell_v, height,
                                             width, seg_len, _ptr(bins), bins_bytes, _ptr(dev_stats),
                                             _stream(stream, uvw, vis, bins)))
+
+
+def gr_degrid_workspace_bytes(n_vis: int, n_pol: int, support: int, height: int, width: int,
+                              seg_len: int = 0) -> int:
+    return int(load_library().gr_degrid_workspace_bytes(n_vis, n_pol, support, height, width, seg_len))
+
+
+def gr_degrid(uvw, n_vis, n_pol, kernel: GrKernel, inv_cell_u, inv_cell_v, grid, height, width, vis_out,
+              seg_len, workspace, workspace_bytes, dev_stats=None, stream=None):
+    _check(load_library().gr_degrid(_ptr(uvw), n_vis, n_pol, ctypes.byref(kernel), inv_cell_u, inv_cell_v,
+                                    _ptr(grid), height, width, _ptr(vis_out), seg_len, _ptr(workspace),
+                                    workspace_bytes, _ptr(dev_stats), _stream(stream, grid, vis_out)))
 
 
 def gr_grid_binned(bins, n_vis, n_pol, kernel: GrKernel, seg_len, grid, height, width, stream=None):

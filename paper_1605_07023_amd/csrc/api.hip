@@ -236,6 +236,40 @@ extern "C" gr_status gr_preprocess_bin(const double* uvw, const void* vis, int32
                                inv_cell_v, height, width, L, bins, rec_tmp, dev_stats, (hipStream_t)stream);
 }
 
+extern "C" size_t gr_degrid_workspace_bytes(int64_t n_vis, int32_t n_pol, int32_t support, int32_t height,
+                                            int32_t width, int32_t seg_len) {
+  return gr_preprocess_bin_bytes(n_vis, n_pol, support, height, width, seg_len);
+}
+
+extern "C" gr_status gr_degrid(const double* uvw, int64_t n_vis, int32_t n_pol, const gr_kernel* kernel,
+                               double inv_cell_u, double inv_cell_v, const void* grid, int32_t height,
+                               int32_t width, void* vis_out, int32_t seg_len, void* workspace,
+                               size_t workspace_bytes, int64_t* dev_stats, void* stream) {
+  gr_status st = validate_kernel(kernel, true);
+  if (st != GR_OK) return st;
+  if ((st = validate_grid(n_pol, height, width, kernel->support)) != GR_OK) return st;
+  if (n_vis < 0 || n_vis > 0x7fffffffLL) return fail(GR_EINVAL, "gr_degrid: n_vis must be in [0, 2^31)");
+  if (n_vis > 0 && (uvw == nullptr || vis_out == nullptr))
+    return fail(GR_EINVAL, "gr_degrid: uvw and vis_out must be non-NULL");
+  if (grid == nullptr) return fail(GR_EINVAL, "gr_degrid: grid is NULL");
+  if (!std::isfinite(inv_cell_u) || !std::isfinite(inv_cell_v) || inv_cell_u <= 0 || inv_cell_v <= 0)
+    return fail(GR_EINVAL, "inv_cell_u / inv_cell_v must be finite and > 0");
+  size_t lds = 0;
+  if ((st = plan_degrid(*kernel, n_pol, &lds)) != GR_OK) return st;
+  const BinLayout L = bin_layout(n_vis, n_pol, kernel->support, height, width,
+                                 seg_len > 0 ? seg_len : kDefaultSegLen);
+  const size_t need = L.bytes + align256(sizeof(Record) * (size_t)n_vis);
+  if (n_vis > 0 && workspace == nullptr) return fail(GR_EINVAL, "gr_degrid: workspace is NULL");
+  if (workspace_bytes < need) return fail(GR_ENOMEM, "gr_degrid: workspace too small (see gr_degrid_workspace_bytes)");
+  if (n_vis == 0) return GR_OK;
+  auto* rec_tmp = reinterpret_cast<Record*>(reinterpret_cast<char*>(workspace) + L.bytes);
+  if ((st = launch_degrid_bin(uvw, n_vis, *kernel, inv_cell_u, inv_cell_v, height, width, L, workspace, rec_tmp,
+                              dev_stats, (hipStream_t)stream)) != GR_OK)
+    return st;
+  return launch_degrid(workspace, L, n_pol, *kernel, reinterpret_cast<const float2*>(grid), height, width,
+                       reinterpret_cast<float2*>(vis_out), n_vis, (hipStream_t)stream);
+}
+
 extern "C" gr_status gr_grid_binned(const void* bins, int64_t n_vis, int32_t n_pol, const gr_kernel* kernel,
                                     int32_t seg_len, void* grid, int32_t height, int32_t width, void* stream) {
   gr_status st = validate_kernel(kernel, true);

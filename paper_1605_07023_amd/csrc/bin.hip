@@ -326,6 +326,25 @@ prebin_scatter_kernel(prep::PreArgs a, int tile, int n_tx, int32_t* __restrict__
   }
 }
 
+// Degridding's binning: records from uvw and tile counts as above, then each
+// kept record and its input index (int32) to the binned slot.
+__global__ void __launch_bounds__(256)
+index_scatter_kernel(const Record* __restrict__ rec, int64_t n, int tile, int n_tx, int32_t* __restrict__ cursor,
+                     Record* __restrict__ out_rec, int32_t* __restrict__ out_idx) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int key = -1;
+  Record r{0, 0};
+  if (i < n) {
+    r = rec[i];
+    if (rec_valid(r)) key = tile_of(r, tile, n_tx);
+  }
+  const int pos = reserve_grouped(key, cursor);
+  if (key >= 0) {
+    out_rec[pos] = r;
+    out_idx[pos] = (int32_t)i;
+  }
+}
+
 // ---- batched forms (one launch for all instances of a batch) ----------------
 
 // zero every instance's tile counts and segment count (block per instance)
@@ -426,6 +445,33 @@ gr_status launch_preprocess_bin(const double* uvw, const void* vis, int vis_dtyp
     hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(256), 0, stream, a, L.tile, L.n_tx, cursor, orec, owv, st);
   }
   return check_launch("gr_preprocess_bin");
+}
+
+gr_status launch_degrid_bin(const double* uvw, int64_t n_vis, const gr_kernel& k, double inv_cell_u,
+                            double inv_cell_v, int height, int width, const BinLayout& L, void* bins,
+                            Record* rec_tmp, int64_t* dev_stats, hipStream_t stream) {
+  char* base = reinterpret_cast<char*>(bins);
+  auto* count = reinterpret_cast<int32_t*>(base + L.off_count);
+  auto* cursor = reinterpret_cast<int32_t*>(base + L.off_cursor);
+  auto* nsegs = reinterpret_cast<int32_t*>(base + L.off_nsegs);
+  auto* orec = reinterpret_cast<Record*>(base + L.off_rec);
+  auto* oidx = reinterpret_cast<int32_t*>(base + L.off_wvis);
+  if (L.n_tiles > 0x7fffffff) return fail(GR_EINVAL, "gr_degrid: too many tiles");
+  const int64_t blocks = (n_vis + 255) / 256;
+  if (blocks > 0x7fffffff) return fail(GR_EINVAL, "gr_degrid: n_vis too large");
+  fill_i32<<<(unsigned)((L.n_tiles + 255) / 256), 256, 0, stream>>>(count, L.n_tiles, 0);
+  fill_i32<<<1, 256, 0, stream>>>(nsegs, 1, 0);
+  auto* st = reinterpret_cast<unsigned long long*>(dev_stats);
+  const prep::PreArgs a = prep::make_pre_args(uvw, nullptr, nullptr, nullptr, n_vis, 1, k, inv_cell_u, inv_cell_v,
+                                              height, width, rec_tmp, nullptr);
+  if (n_vis > 0) {
+    const int64_t cblocks = std::min<int64_t>(blocks, (int64_t)prep::device_cu_count() * 16);
+    prebin_count_kernel<<<(unsigned)cblocks, 256, 0, stream>>>(a, L.tile, L.n_tx, count, st);
+  }
+  launch_scan(count, L, base, stream);
+  if (n_vis > 0)
+    index_scatter_kernel<<<(unsigned)blocks, 256, 0, stream>>>(rec_tmp, n_vis, L.tile, L.n_tx, cursor, orec, oidx);
+  return check_launch("gr_degrid (bin)");
 }
 
 gr_status launch_bin(const Record* rec, const float2* wvis, int64_t n_vis, int n_pol,

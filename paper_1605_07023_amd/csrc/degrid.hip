@@ -1,0 +1,274 @@
+// Degridding: the adjoint of gridding.  Merry (2016) names degridding with
+// thread coarsening as the next step (Section 6); the operation predicts each
+// visibility from the grid through the same separable GCF:
+//     V[n, p] = sum_{ky, kx} Tv[plane][sy][ky] Tu[plane][sx][kx] G[p][y0 + ky][x0 + kx]
+// (complex products; with the conjugated taps it is the exact adjoint of the
+// gridding of unit-weight visibilities).
+//
+// gfx950 form, on the binned stream of gridding (one window of W x W cells
+// per segment, W = T + S):
+//  * One 1024-thread block per compute unit stages the tap table once, then
+//    takes segments from an atomic counter; per segment the block stages the
+//    grid window (all polarisations) in LDS, once, and its 16 waves share it.
+//  * A wave takes batches of 8 visibilities.  Stage 1 contracts the window
+//    with each visibility's G^u row on the matrix cores: for a row group (4
+//    rows x 4 polarisations, or 16 rows at P = 1) and a column group of 8
+//    cells, Z[(r, p), (v, re|im)] += sum_{(x, re|im)} G[(r, p), (x, re|im)]
+//    B[(x, re|im), (v, re|im)], four v_mfma_f32_16x16x4_f32 per column group
+//    (K = 2 cells x (re, im)), with B the sign pattern that makes the real
+//    product the complex G . G^u.  Only the row and column groups that the
+//    batch's footprints touch are issued.  The A operand is one LDS read at a
+//    lane-constant address plus an immediate offset; the window lines are
+//    padded so that those reads are free of bank conflicts.
+//  * Stage 2, per row group: each lane multiplies its Z values by its
+//    visibility's G^v tap of that row (the complex product needs the partner
+//    component, one lane swap) and accumulates; at the end the partial sums
+//    of the 4 row lanes are added across the wave and each visibility is
+//    written once to its input position (no atomics: the result is
+//    deterministic).
+#include <algorithm>
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include "internal.h"
+
+namespace gr {
+
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kVisPerBatch = 8;     // N = 8 visibilities x (re, im)
+constexpr int kDegridThreads = 1024;
+
+__device__ inline float tap_value(const void* __restrict__ t, int64_t idx, int dtype) {
+  switch (dtype) {
+    case GR_F32: return reinterpret_cast<const float*>(t)[idx];
+    case GR_F16: return __half2float(reinterpret_cast<const __half*>(t)[idx]);
+    default: return __bfloat162float(reinterpret_cast<const __hip_bfloat16*>(t)[idx]);
+  }
+}
+
+// window lines: 2 W + 4 floats per (row, polarisation), so that the 64 lanes'
+// A reads fall in 64 different banks
+__host__ __device__ constexpr int degrid_line(int wr) { return 2 * wr + 4; }
+
+// clamp a tap index to the padded row (-1 and S read the zero entries)
+__device__ __forceinline__ int tap_slot(int t, int S) {
+  int r;
+  asm("v_med3_i32 %0, %1, -1, %2" : "=v"(r) : "v"(t), "s"(S));
+  return r + 1;
+}
+
+template <int P, int WR>
+__global__ void __launch_bounds__(kDegridThreads)
+degrid_kernel(const Record* __restrict__ rec, const int32_t* __restrict__ idx, const int4* __restrict__ segs,
+              const int32_t* __restrict__ n_segs_p, int32_t* __restrict__ counter, const void* __restrict__ taps,
+              int taps_complex, const float2* __restrict__ grid, float2* __restrict__ vis_out, MfmaDev d) {
+  constexpr int RG = 16 / P;
+  constexpr int NRG = WR / RG;
+  constexpr int WCG = WR / 8;
+  constexpr int LS = degrid_line(WR);
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  float* win = reinterpret_cast<float*>(lds_raw);                                   // [WR][P][LS]
+  float2* tab = reinterpret_cast<float2*>(lds_raw + (size_t)WR * P * LS * sizeof(float));   // [rows][S + 2]
+  __shared__ int s_seg;
+
+  // tap table: rows [plane * O + s] of S + 2 (re, im) entries, zero at both ends
+  {
+    const int S = d.S, SP = d.S + 2;
+    const int n_elem = d.n_rows_tab * SP;
+    for (int e = threadIdx.x; e < n_elem; e += blockDim.x) {
+      const int row = e / SP, kk = e - row * SP - 1;
+      const bool in = kk >= 0 && kk < S;
+      const int64_t src = (int64_t)row * S + (in ? kk : 0);
+      float re = 0.f, im = 0.f;
+      if (in) {
+        if (taps_complex) {
+          re = tap_value(taps, 2 * src, d.tap_dtype);
+          im = tap_value(taps, 2 * src + 1, d.tap_dtype);
+        } else {
+          re = tap_value(taps, src, d.tap_dtype);
+        }
+      }
+      tab[e] = make_float2(re, im);
+    }
+  }
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
+  const int m = lane & 15, k = lane >> 4;
+  const int ar = (P == 4) ? (m >> 2) : m, ap = (P == 4) ? (m & 3) : 0;   // A row: (row, polarisation)
+  const int v = m >> 1, comp = m & 1;                                     // B and D column: (visibility, re|im)
+  const int xk = k >> 1, bcomp = k & 1;                                   // B row: (cell of the K slice, re|im)
+  const int a_lane = (ar * P + ap) * LS + 2 * xk + bcomp;
+  const int S = d.S;
+  const int n_items = *n_segs_p;
+
+  for (;;) {
+    __syncthreads();                                 // previous window consumed (and the table staged)
+    if (threadIdx.x == 0) s_seg = atomicAdd(counter, 1);
+    __syncthreads();
+    const int seg = s_seg;
+    if (seg >= n_items) break;                       // uniform for the block
+    const int4 sg = segs[seg];
+    const int begin = sg.x, len = sg.y, tile_id = sg.z;
+    const int win_x0 = (tile_id % d.n_tx) * d.tile;
+    const int win_y0 = (tile_id / d.n_tx) * d.tile;
+    // the window, all polarisations; cells past the grid edge read as zero
+    for (int e = threadIdx.x; e < WR * P * WR; e += blockDim.x) {
+      const int x = e % WR, t = e / WR, p = t % P, row = t / P;
+      const int gy = win_y0 + row, gx = win_x0 + x;
+      float2 g = make_float2(0.f, 0.f);
+      if (gy < d.H && gx < d.W) g = grid[((int64_t)p * d.H + gy) * d.W + gx];
+      *reinterpret_cast<float2*>(win + (row * P + p) * LS + 2 * x) = g;
+    }
+    __syncthreads();
+
+    for (int b0 = wave * kVisPerBatch; b0 < len; b0 += n_waves * kVisPerBatch) {
+      const int nb = min(kVisPerBatch, len - b0);
+      const bool live = v < nb;
+      const Record r = rec[begin + b0 + (live ? v : 0)];
+      const int xr = rec_x0(r) - win_x0, yr = rec_y0(r) - win_y0;
+      const int rowu = (rec_plane(r) * d.O + rec_sx(r)) * (S + 2);
+      const int rowv = (rec_plane(r) * d.O + rec_sy(r)) * (S + 2);
+      // row and column groups that the batch's footprints touch (lane 2q holds visibility q)
+      int xlo = 1 << 30, xhi = -(1 << 30), ylo = 1 << 30, yhi = -(1 << 30);
+      for (int q = 0; q < nb; ++q) {
+        const int xq = __builtin_amdgcn_readlane(xr, 2 * q), yq = __builtin_amdgcn_readlane(yr, 2 * q);
+        xlo = min(xlo, xq);
+        xhi = max(xhi, xq);
+        ylo = min(ylo, yq);
+        yhi = max(yhi, yq);
+      }
+      const int g_lo = __builtin_amdgcn_readfirstlane(ylo / RG);
+      const int g_hi = __builtin_amdgcn_readfirstlane((yhi + S - 1) / RG);
+      const int c_lo = __builtin_amdgcn_readfirstlane(xlo >> 3);
+      const int c_hi = __builtin_amdgcn_readfirstlane((xhi + S - 1) >> 3);
+      // B: visibility v's G^u tap at cell 8c + 2s + xk, as the (bcomp, comp) entry of the complex product
+      float bfr[WCG][4];
+#pragma unroll
+      for (int c = 0; c < WCG; ++c) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const float2 t = tab[rowu + tap_slot(8 * c + 2 * s + xk - xr, S)];
+          const float b = bcomp == comp ? t.x : (bcomp ? -t.y : t.y);
+          bfr[c][s] = live ? b : 0.f;
+        }
+      }
+      float vacc[P == 4 ? 4 : 1];
+#pragma unroll
+      for (int i = 0; i < (P == 4 ? 4 : 1); ++i) vacc[i] = 0.f;
+#pragma unroll
+      for (int j = 0; j < NRG; ++j) {
+        if (j < g_lo || j > g_hi) continue;          // uniform
+        f4 z0 = {0.f, 0.f, 0.f, 0.f}, z1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < WCG; ++c) {
+          if (c < c_lo || c > c_hi) continue;        // uniform
+          const float* a = win + a_lane + j * RG * P * LS + 16 * c;
+          z0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], bfr[c][0], z0, 0, 0, 0);
+          z1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4], bfr[c][1], z1, 0, 0, 0);
+          z0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[8], bfr[c][2], z0, 0, 0, 0);
+          z1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[12], bfr[c][3], z1, 0, 0, 0);
+        }
+        // stage 2: D row 4k + i of this lane is (row k, pol i) at P = 4, row 4k + i at P = 1
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float zown = z0[i] + z1[i];
+          const float zpart = __shfl_xor(zown, 1);   // the other component of Z
+          const int row = j * RG + ((P == 4) ? k : 4 * k + i);
+          const float2 tv = tab[rowv + tap_slot(row - yr, S)];
+          const float t_im = comp ? tv.y : -tv.y;
+          vacc[(P == 4) ? i : 0] += tv.x * zown + t_im * zpart;
+        }
+      }
+      // add the partial sums of the 4 row lanes; lanes 0..15 write (visibility, component)
+#pragma unroll
+      for (int i = 0; i < (P == 4 ? 4 : 1); ++i) {
+        vacc[i] += __shfl_xor(vacc[i], 16);
+        vacc[i] += __shfl_xor(vacc[i], 32);
+      }
+      if (k == 0 && live) {
+        const int64_t n = idx[begin + b0 + v];
+        float* out = reinterpret_cast<float*>(vis_out) + n * P * 2 + comp;
+#pragma unroll
+        for (int i = 0; i < (P == 4 ? 4 : 1); ++i) out[2 * i] = vacc[i];
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) fill_f32(float* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.f;
+}
+
+__global__ void __launch_bounds__(64) zero_i32(int32_t* c) {
+  if (threadIdx.x == 0) *c = 0;
+}
+
+int window_for(int support) { return support <= 16 ? 32 : support <= 32 ? 48 : 64; }
+
+size_t degrid_lds(const gr_kernel& k, int n_pol) {
+  const int wr = window_for(k.support);
+  return align256((size_t)wr * n_pol * degrid_line(wr) * sizeof(float)) +
+         (size_t)k.n_planes * k.oversample * (k.support + 2) * sizeof(float2);
+}
+
+using DegridFn = void (*)(const Record*, const int32_t*, const int4*, const int32_t*, int32_t*, const void*, int,
+                          const float2*, float2*, MfmaDev);
+
+DegridFn degrid_fn(int n_pol, int wr) {
+  if (n_pol == 4) return wr == 32 ? degrid_kernel<4, 32> : wr == 48 ? degrid_kernel<4, 48> : degrid_kernel<4, 64>;
+  return wr == 32 ? degrid_kernel<1, 32> : wr == 48 ? degrid_kernel<1, 48> : degrid_kernel<1, 64>;
+}
+
+}  // namespace
+
+gr_status plan_degrid(const gr_kernel& k, int n_pol, size_t* lds_bytes) {
+  if (k.kind != GR_SEPARABLE) return fail(GR_EUNSUPPORTED, "gr_degrid takes separable kernels");
+  if (k.support > 56) return fail(GR_EUNSUPPORTED, "gr_degrid needs support <= 56");
+  const size_t lds = degrid_lds(k, n_pol);
+  if (lds > 160 * 1024)
+    return fail(GR_EUNSUPPORTED, "gr_degrid: grid window and tap table do not fit in LDS (160 KiB)");
+  *lds_bytes = lds;
+  return GR_OK;
+}
+
+gr_status launch_degrid(const void* bins, const BinLayout& L, int n_pol, const gr_kernel& k,
+                        const float2* grid, int height, int width, float2* vis_out, int64_t n_vis,
+                        hipStream_t stream) {
+  size_t lds = 0;
+  gr_status st = plan_degrid(k, n_pol, &lds);
+  if (st != GR_OK) return st;
+  const int wr = window_for(k.support);
+  if (L.tile + k.support > wr) return fail(GR_EINVAL, "gr_degrid: binning tile does not fit the window");
+  if (n_vis > 0) {
+    const int64_t n = n_vis * n_pol * 2;
+    fill_f32<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(reinterpret_cast<float*>(vis_out), n);
+  }
+  if (L.max_segs == 0 || n_vis == 0) return check_launch("gr_degrid");
+  const char* base = reinterpret_cast<const char*>(bins);
+  const auto* rec = reinterpret_cast<const Record*>(base + L.off_rec);
+  const auto* idx = reinterpret_cast<const int32_t*>(base + L.off_wvis);
+  const auto* segs = reinterpret_cast<const int4*>(base + L.off_segs);
+  auto* nsegs = const_cast<int32_t*>(reinterpret_cast<const int32_t*>(base + L.off_nsegs));
+  int32_t* counter = nsegs + 16;                     // after the segment count, in the same 256 bytes
+  MfmaDev d{};
+  d.S = k.support; d.O = k.oversample; d.n_rows_tab = k.n_planes * k.oversample;
+  d.tap_dtype = k.tap_dtype; d.tile = L.tile; d.n_tx = L.n_tx; d.H = height; d.W = width;
+  const DegridFn fn = degrid_fn(n_pol, wr);
+  if ((st = ensure_lds_limit(reinterpret_cast<const void*>(fn), lds, "gr_degrid")) != GR_OK) return st;
+  zero_i32<<<1, 64, 0, stream>>>(counter);
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    cus = 256;
+  const int blocks = (int)std::min<int64_t>(cus, L.max_segs);
+  hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kDegridThreads), lds, stream, rec, idx, segs, nsegs, counter,
+                     k.taps, k.taps_complex ? 1 : 0, grid, vis_out, d);
+  return check_launch("gr_degrid");
+}
+
+}  // namespace gr

@@ -82,6 +82,18 @@ gr_status launch_preprocess_bin(const double* uvw, const void* vis, int vis_dtyp
                                 const float* weights, int64_t n_vis, int n_pol, const gr_kernel& k,
                                 double inv_cell_u, double inv_cell_v, int height, int width, const BinLayout& L,
                                 void* bins, Record* rec_tmp, int64_t* dev_stats, hipStream_t stream);
+// Degridding's binning: records (rec_tmp) and tile counts from uvw, scan,
+// then kept records and their input indices (int32, in the wvis slot of the
+// layout) to the binned positions.
+gr_status launch_degrid_bin(const double* uvw, int64_t n_vis, const gr_kernel& k, double inv_cell_u,
+                            double inv_cell_v, int height, int width, const BinLayout& L, void* bins,
+                            Record* rec_tmp, int64_t* dev_stats, hipStream_t stream);
+// The degridder on such a binned stream (degrid.hip); vis_out complex64
+// [n_vis][n_pol], valid entries written, the caller zeroes the rest.
+gr_status plan_degrid(const gr_kernel& k, int n_pol, size_t* lds_bytes);
+gr_status launch_degrid(const void* bins, const BinLayout& L, int n_pol, const gr_kernel& k,
+                        const float2* grid, int height, int width, float2* vis_out, int64_t n_vis,
+                        hipStream_t stream);
 gr_status launch_bin(const Record* rec, const float2* wvis, int64_t n_vis, int n_pol,
                      const BinLayout& L, void* bins, hipStream_t stream);
 

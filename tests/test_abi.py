@@ -144,6 +144,33 @@ def test_preprocess_bin_rejects(lib):
     assert st == B.GR_EINVAL and "n_pol" in lib.gr_last_error().decode()
 
 
+def test_degrid_rejects(lib):
+    """Host-side validation of gr_degrid, before anything is enqueued."""
+    from paper_1605_07023_amd import binding as B
+    k = _kernel()
+    need = B.gr_degrid_workspace_bytes(10, 4, 16, 64, 64, 0)
+    assert need >= B.gr_bin_bytes(10, 4, 16, 64, 64) + 80
+    st = lib.gr_degrid(1 << 20, 10, 4, ctypes.byref(k), 1.0, 1.0, 1 << 20, 64, 64, 1 << 20, 0, 1 << 20, need - 1,
+                       None, None)
+    assert st == B.GR_ENOMEM and "gr_degrid_workspace_bytes" in lib.gr_last_error().decode()
+    st = lib.gr_degrid(1 << 20, 10, 3, ctypes.byref(k), 1.0, 1.0, 1 << 20, 64, 64, 1 << 20, 0, 1 << 20, need,
+                       None, None)
+    assert st == B.GR_EINVAL and "n_pol" in lib.gr_last_error().decode()
+    st = lib.gr_degrid(1 << 20, 10, 4, ctypes.byref(k), 1.0, 1.0, None, 64, 64, 1 << 20, 0, 1 << 20, need,
+                       None, None)
+    assert st == B.GR_EINVAL and "grid" in lib.gr_last_error().decode()
+    big = _kernel()
+    big.n_planes = 400                 # (Re, Im) table of 400 x 8 x 18 entries: beyond LDS with the window
+    st = lib.gr_degrid(1 << 20, 10, 4, ctypes.byref(big), 1.0, 1.0, 1 << 20, 64, 64, 1 << 20, 0, 1 << 20, need,
+                       None, None)
+    assert st == B.GR_EUNSUPPORTED and "LDS" in lib.gr_last_error().decode()
+    t2 = _kernel()
+    t2.kind = B.GR_TABLE2D
+    st = lib.gr_degrid(1 << 20, 10, 4, ctypes.byref(t2), 1.0, 1.0, 1 << 20, 64, 64, 1 << 20, 0, 1 << 20, need,
+                       None, None)
+    assert st == B.GR_EUNSUPPORTED
+
+
 def test_table_generators_reject(lib):
     from paper_1605_07023_amd import binding as B
     assert lib.gr_make_kb_table(8.6, 7, 8, B.GR_F32, 1 << 20, None) == B.GR_EINVAL

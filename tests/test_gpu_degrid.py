@@ -1,0 +1,155 @@
+"""GPU tests of gr_degrid (the adjoint of gridding) through the C ABI.
+
+Bars: within 1e-5 relative L2 of the FP64 oracle's degridding (FP32 products
+and sums); integer-valued grids and taps bit-exact; the adjoint identity
+<grid(V), G> = <V, degrid(G)> with conjugated taps within FP32 rounding;
+dropped visibilities exactly zero.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import gridding as G  # noqa: E402
+from synth import full_shape_workload, random_point_workload  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1605_07023_amd import binding, runner
+    binding.load_library()
+    return runner
+
+
+def _rel(got, ref):
+    return float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+def _taps(wl):
+    if wl.kernel == "kb":
+        return G.kb_table(wl.support, wl.oversample, wl.beta)
+    return G.wkernel_table(wl.support, wl.oversample, wl.plane_w_hat(), wl.support_aa, wl.beta)
+
+
+def _degrid(R, dw, grid, seg=0, stats=None):
+    from paper_1605_07023_amd import binding as B
+    wl = dw.wl
+    need = B.gr_degrid_workspace_bytes(wl.n_vis, wl.n_pol, wl.support, wl.height, wl.width, seg)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=DEV)
+    out = torch.full((max(wl.n_vis, 1), wl.n_pol), complex(7.0, -3.0), dtype=torch.complex64, device=DEV)
+    B.gr_degrid(dw.uvw, wl.n_vis, wl.n_pol, dw.kernel, wl.inv_cell_u, wl.inv_cell_v, grid, wl.height,
+                wl.width, out, seg, ws, need, stats)
+    torch.cuda.synchronize()
+    return out[:wl.n_vis].cpu().numpy()
+
+
+def _random_grid(rng, P, H, W):
+    return (rng.standard_normal((P, H, W)) + 1j * rng.standard_normal((P, H, W))).astype(np.complex64)
+
+
+@pytest.mark.parametrize("P,S,kern,seg", [(4, 16, "wsep", 0), (4, 32, "wsep", 0), (4, 32, "wsep", 37),
+                                          (1, 8, "kb", 0), (4, 8, "kb", 5), (1, 32, "wsep", 64),
+                                          (1, 56, "wsep", 0), (4, 16, "wsep", 1)])
+def test_degrid_matches_oracle(R, P, S, kern, seg):
+    _say(f"degrid vs oracle P={P} S={S} {kern} seg_len={seg}")
+    rng = np.random.default_rng(S * 10 + P + seg)
+    wl = random_point_workload(2500, P, 120, 104, S, 8, seed=S + P + seg, n_planes=3 if kern == "wsep" else 1,
+                               margin=6, kernel=kern)
+    g = _random_grid(rng, P, wl.height, wl.width)
+    dw = R.upload(wl, DEV)
+    stats = torch.zeros(2, dtype=torch.int64, device=DEV)
+    got = _degrid(R, dw, torch.from_numpy(g).to(DEV), seg, stats)
+    ref = G.degrid_separable(g.astype(np.complex128), wl.uvw, _taps(wl), wl.inv_cell_u, wl.inv_cell_v,
+                             wl.oversample, wl.n_planes, wl.w_min, wl.inv_dw)
+    valid = G.pixel_coords(wl.uvw, wl.inv_cell_u, wl.inv_cell_v, wl.oversample, S, wl.height, wl.width,
+                           wl.n_planes, wl.w_min, wl.inv_dw)["valid"]
+    err = _rel(got.astype(np.complex128), ref)
+    _say(f"  rel L2 {err:.2e}, dropped {int((~valid).sum())}")
+    assert err <= 1e-5
+    assert not got[~valid].any() and (~valid).sum() > 0
+    assert stats.cpu().tolist() == [int(valid.sum()), int((~valid).sum())]
+
+
+@pytest.mark.parametrize("P", [1, 4])
+def test_degrid_integer_inputs_bit_exact(R, P):
+    """Integer grid values and taps: every product and partial sum is an exact
+    FP32 integer, so the result equals the FP64 oracle bit for bit."""
+    from paper_1605_07023_amd import binding as B
+    _say(f"degrid integer inputs bit-exact P={P}")
+    rng = np.random.default_rng(60 + P)
+    wl = random_point_workload(1500, P, 72, 80, 16, 4, seed=61 + P, n_planes=3, margin=3, kernel="wsep")
+    g = (rng.integers(-3, 4, (P, 72, 80)) + 1j * rng.integers(-3, 4, (P, 72, 80))).astype(np.complex64)
+    taps = rng.integers(-1, 2, (3, 4, 16)) + 1j * rng.integers(-1, 2, (3, 4, 16))
+    t = torch.from_numpy(np.ascontiguousarray(np.stack([taps.real, taps.imag], axis=-1), dtype=np.float32)).to(DEV)
+    dw = R.upload(wl, DEV, taps=t)
+    dw.kernel = B.make_kernel(t, 16, 4, 3, taps_complex=True, w_min=wl.w_min, inv_dw=wl.inv_dw)
+    got = _degrid(R, dw, torch.from_numpy(g).to(DEV), 50)
+    ref = G.degrid_separable(g.astype(np.complex128), wl.uvw, taps, 1.0, 1.0, 4, 3, wl.w_min, wl.inv_dw)
+    np.testing.assert_array_equal(got.astype(np.complex128), ref)
+
+
+@pytest.mark.parametrize("P,S", [(4, 32), (1, 16)])
+def test_degrid_is_adjoint_of_grid(R, P, S):
+    """<gr_grid(V), G> = <V, gr_degrid(G)> with conjugated taps (unit weights)."""
+    from paper_1605_07023_amd import binding as B
+    _say(f"adjoint identity P={P} S={S}")
+    rng = np.random.default_rng(70 + S)
+    wl = random_point_workload(3000, P, 96, 96, S, 8, seed=71 + S, n_planes=3, margin=4, kernel="wsep")
+    taps = _taps(wl)
+    dw = R.upload(wl, DEV)
+    gv = R.grid(dw).cpu().numpy().astype(np.complex128)
+    probe = _random_grid(rng, P, 96, 96)
+    conj = torch.from_numpy(np.ascontiguousarray(np.stack([taps.real, -taps.imag], axis=-1),
+                                                 dtype=np.float32)).to(DEV)
+    dwc = R.upload(wl, DEV, taps=conj)
+    dwc.kernel = B.make_kernel(conj, S, 8, 3, taps_complex=True, w_min=wl.w_min, inv_dw=wl.inv_dw)
+    dg = _degrid(R, dwc, torch.from_numpy(probe).to(DEV)).astype(np.complex128)
+    lhs = np.vdot(probe.astype(np.complex128), gv)
+    rhs = np.vdot(dg, wl.vis.astype(np.complex128))
+    _say(f"  <G, grid(V)> {lhs:.6e}  <degrid(G), V> {rhs:.6e}")
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+def test_degrid_full_shape_sampled(R):
+    """The 33M-visibility full shape at S = 32: 1500 sampled visibilities against
+    the oracle's degridding of those visibilities."""
+    _say("degrid full shape S=32, sampled visibilities")
+    wl = full_shape_workload(32)
+    rng = np.random.default_rng(80)
+    g = _random_grid(rng, 4, wl.height, wl.width)
+    dw = R.upload(wl, DEV)
+    got = _degrid(R, dw, torch.from_numpy(g).to(DEV))
+    pick = np.sort(rng.choice(wl.n_vis, 1500, replace=False))
+    ref = G.degrid_separable(g, wl.uvw[pick], _taps(wl), wl.inv_cell_u, wl.inv_cell_v, 8, wl.n_planes,
+                             wl.w_min, wl.inv_dw)
+    err = _rel(got[pick].astype(np.complex128), ref)
+    _say(f"  rel L2 on the sample {err:.2e}")
+    assert err <= 1e-5
+
+
+def test_degrid_empty_and_all_dropped(R):
+    _say("degrid: empty input, all dropped")
+    wl = random_point_workload(0, 4, 64, 64, 16, 8, seed=1, n_planes=2, kernel="wsep")
+    dw = R.upload(wl, DEV)
+    g = torch.zeros((4, 64, 64), dtype=torch.complex64, device=DEV)
+    assert _degrid(R, dw, g).shape == (0, 4)
+    wl = random_point_workload(300, 4, 64, 64, 16, 8, seed=2, n_planes=2, kernel="wsep")
+    wl.uvw = wl.uvw.copy()
+    wl.uvw[:, 0] += 1e4
+    dw = R.upload(wl, DEV)
+    g = torch.ones((4, 64, 64), dtype=torch.complex64, device=DEV)
+    stats = torch.zeros(2, dtype=torch.int64, device=DEV)
+    got = _degrid(R, dw, g, 0, stats)
+    assert not got.any()
+    assert stats.cpu().tolist() == [0, 300]
