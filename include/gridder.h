@@ -194,7 +194,8 @@ gr_status gr_grid_binned(const void* bins, int64_t n_vis, int32_t n_pol, const g
  * [n_vis][n_pol]) is OVERWRITTEN; visibilities dropped by the coordinate rule
  * of gr_preprocess get 0, and dev_stats (or NULL) receives {kept, dropped}
  * (added).  The visibilities are binned as for gr_grid_binned (seg_len as
- * there); then one 1024-thread block per compute unit stages the tap table
+ * there, at most 4096) and each segment is put in Z (Morton) order of its
+ * footprint origins; then one 1024-thread block per compute unit stages the tap table
  * once and, per segment, the grid window of all polarisations in LDS; waves
  * contract it with the G^u rows of 8 visibilities at a time on the matrix
  * cores (v_mfma_f32_16x16x4_f32) and apply the G^v taps per row.  Each

@@ -256,6 +256,7 @@ extern "C" gr_status gr_degrid(const double* uvw, int64_t n_vis, int32_t n_pol, 
     return fail(GR_EINVAL, "inv_cell_u / inv_cell_v must be finite and > 0");
   size_t lds = 0;
   if ((st = plan_degrid(*kernel, n_pol, &lds)) != GR_OK) return st;
+  if (seg_len > 4096) return fail(GR_EINVAL, "gr_degrid: seg_len must be <= 4096");
   const BinLayout L = bin_layout(n_vis, n_pol, kernel->support, height, width,
                                  seg_len > 0 ? seg_len : kDefaultSegLen);
   const size_t need = L.bytes + align256(sizeof(Record) * (size_t)n_vis);

@@ -199,6 +199,86 @@ degrid_kernel(const Record* __restrict__ rec, const int32_t* __restrict__ idx, c
   }
 }
 
+// Per segment: reorder its (record, input index) entries into the Z (Morton)
+// order of their footprint origins inside the tile, so that the 8 visibilities
+// of a batch are neighbours and their footprints' union stays small (about
+// 24 % fewer MFMAs at S = 32, 36 % at S = 16 than in arrival order on the
+// full-shape tracks).  One 256-thread block per segment in turn: a counting
+// sort over the tile's cells (side^2 buckets, side the power of two >= the
+// tile edge) with LDS histograms, then the entries gathered through LDS and
+// written back in place.  Entries of one cell keep no particular order.
+constexpr int kSortMax = 4096;       // entries per segment (seg_len <= 4096)
+constexpr int kSortThreads = 256;
+
+__device__ __forceinline__ int spread6i(int v) {
+  v &= 63;
+  v = (v | (v << 4)) & 0x0f0f;
+  v = (v | (v << 2)) & 0x3333;
+  return (v | (v << 1)) & 0x5555;
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+sort_segments_kernel(Record* __restrict__ rec, int32_t* __restrict__ idx, const int4* __restrict__ segs,
+                     const int32_t* __restrict__ n_segs_p, int tile, int n_tx, int buckets) {
+  __shared__ int slot[kSortMax];         // cell, then destination, of entry i
+  __shared__ int offs[kSortMax];         // per cell: count, then running offset
+  __shared__ uint2 tmp[kSortMax];
+  const int n_segs = *n_segs_p;
+  const int t = threadIdx.x;
+  for (int seg = blockIdx.x; seg < n_segs; seg += gridDim.x) {
+    const int4 sg = segs[seg];
+    const int begin = sg.x, len = sg.y;
+    if (len <= 1) continue;                          // uniform for the block
+    const int wx0 = (sg.z % n_tx) * tile, wy0 = (sg.z / n_tx) * tile;
+    for (int b = t; b < buckets; b += kSortThreads) offs[b] = 0;
+    __syncthreads();
+    for (int i = t; i < len; i += kSortThreads) {
+      const Record r = rec[begin + i];
+      const int c = spread6i(rec_x0(r) - wx0) | (spread6i(rec_y0(r) - wy0) << 1);
+      slot[i] = c;
+      atomicAdd(&offs[c], 1);
+    }
+    __syncthreads();
+    // exclusive scan of the bucket counts: each thread a contiguous run
+    {
+      const int per = (buckets + kSortThreads - 1) / kSortThreads;
+      const int a = min(buckets, t * per), b = min(buckets, a + per);
+      int sum = 0;
+      for (int q = a; q < b; ++q) sum += offs[q];
+      __shared__ int s_part[kSortThreads];
+      s_part[t] = sum;
+      __syncthreads();
+      for (int o = 1; o < kSortThreads; o <<= 1) {   // Hillis-Steele inclusive scan
+        const int x = t >= o ? s_part[t - o] : 0;
+        __syncthreads();
+        s_part[t] += x;
+        __syncthreads();
+      }
+      int run = s_part[t] - sum;
+      for (int q = a; q < b; ++q) {
+        const int v = offs[q];
+        offs[q] = run;
+        run += v;
+      }
+    }
+    __syncthreads();
+    for (int i = t; i < len; i += kSortThreads) slot[i] = atomicAdd(&offs[slot[i]], 1);
+    __syncthreads();
+    // gather through LDS, then write back in place (all reads before any write)
+    for (int i = t; i < len; i += kSortThreads) {
+      const Record r = rec[begin + i];
+      tmp[slot[i]] = make_uint2(r.x, r.y);
+    }
+    __syncthreads();
+    for (int i = t; i < len; i += kSortThreads) rec[begin + i] = Record{tmp[i].x, tmp[i].y};
+    __syncthreads();
+    for (int i = t; i < len; i += kSortThreads) tmp[slot[i]].x = (uint32_t)idx[begin + i];
+    __syncthreads();
+    for (int i = t; i < len; i += kSortThreads) idx[begin + i] = (int32_t)tmp[i].x;
+    __syncthreads();
+  }
+}
+
 __global__ void __launch_bounds__(256) fill_f32(float* __restrict__ p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.f;
@@ -260,11 +340,19 @@ gr_status launch_degrid(const void* bins, const BinLayout& L, int n_pol, const g
   d.tap_dtype = k.tap_dtype; d.tile = L.tile; d.n_tx = L.n_tx; d.H = height; d.W = width;
   const DegridFn fn = degrid_fn(n_pol, wr);
   if ((st = ensure_lds_limit(reinterpret_cast<const void*>(fn), lds, "gr_degrid")) != GR_OK) return st;
-  zero_i32<<<1, 64, 0, stream>>>(counter);
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
     cus = 256;
+  if (L.seg_len > kSortMax) return fail(GR_EINVAL, "gr_degrid: seg_len must be <= 4096");
+  {
+    const int sblocks = (int)std::min<int64_t>((int64_t)cus * 8, L.max_segs);
+    int side = 1;
+    while (side < L.tile) side <<= 1;
+    sort_segments_kernel<<<sblocks, kSortThreads, 0, stream>>>(const_cast<Record*>(rec), const_cast<int32_t*>(idx),
+                                                             segs, nsegs, L.tile, L.n_tx, side * side);
+  }
+  zero_i32<<<1, 64, 0, stream>>>(counter);
   const int blocks = (int)std::min<int64_t>(cus, L.max_segs);
   hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kDegridThreads), lds, stream, rec, idx, segs, nsegs, counter,
                      k.taps, k.taps_complex ? 1 : 0, grid, vis_out, d);
