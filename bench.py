@@ -158,6 +158,44 @@ def learned_leg(dev, uvw, vis, wl_plain, rec, wvis, bins, bins_bytes, seg_len, s
     return out
 
 
+def degrid_leg(dev, uvw, wl, kern, grid, stream, reps: int) -> dict:
+    """gr_degrid (the adjoint operation, predicting every visibility from the grid)
+    on the full-shape S=32 visibilities and the grid the timed steps produced:
+    whole calls (binning, per-segment ordering, MFMA degridder), HIP events on the
+    stream, after one untimed call."""
+    import torch
+    from paper_1605_07023_amd import binding as B
+    N, P, S = wl.n_vis, wl.n_pol, wl.support
+    need = B.gr_degrid_workspace_bytes(N, P, S, wl.height, wl.width, 0)
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    out = torch.empty((N, P), dtype=torch.complex64, device=dev)
+    st = torch.zeros(2, dtype=torch.int64, device=dev)
+
+    def call():
+        B.gr_degrid(uvw, N, P, kern, wl.inv_cell_u, wl.inv_cell_v, grid, wl.height, wl.width, out, 0, ws, need,
+                    st, stream)
+
+    call()
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        call()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+    kept = int(st.cpu()[0]) // (reps + 1)
+    med = sorted(ms)[len(ms) // 2]
+    upd = kept * P * S * S
+    log(f"degridding leg: {med:.2f} ms per call")
+    del ws, out
+    return {"workload": "the full-shape S=32 visibilities predicted from the S=32 grid of the timed steps",
+            "ms_per_call": med, "updates_per_call": upd, "updates_per_s": upd / (med * 1e-3),
+            "pct_fp32_matrix_peak": 100.0 * 8 * upd / (med * 1e-3) / FP32_MFMA_PEAK,
+            "call": "gr_degrid: binning, per-segment Z ordering, MFMA degridder (16x16x4 FP32)"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +216,8 @@ def main() -> int:
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-kernel leg (network vs 2-D table, after the timed region)")
     ap.add_argument("--learned-steps", type=int, default=12000)
+    ap.add_argument("--no-degrid", action="store_true",
+                    help="skip the degridding leg (gr_degrid of the S=32 grid, after the timed region)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this size before timing "
                          "(reference dispatch for HBM byte counters)")
@@ -336,6 +376,11 @@ def main() -> int:
         learned = learned_leg(dev, uvw, vis, wls[32], rec, wvis, bins, bins_bytes, seg_len[32], stream,
                               args.learned_steps, reps=2)
 
+    degrid = None
+    if not args.no_degrid and variant == 2 and args.precision == "f32" and 32 in supports:
+        log("degridding leg")
+        degrid = degrid_leg(dev, uvw, wls[32], kern[32], grids[32], stream, reps=5)
+
     cpu = None
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
@@ -358,6 +403,7 @@ def main() -> int:
         "tuning": tuned or None,
         "roofline": roofline,
         "learned_kernel": learned,
+        "degrid": degrid,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

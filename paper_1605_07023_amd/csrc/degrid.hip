@@ -176,7 +176,8 @@ degrid_kernel(const Record* __restrict__ rec, const int32_t* __restrict__ idx, c
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const float zown = z0[i] + z1[i];
-          const float zpart = __shfl_xor(zown, 1);   // the other component of Z
+          // the other component of Z sits in the neighbouring lane: a DPP quad permutation (1, 0, 3, 2)
+          const float zpart = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(zown), 0xB1, 0xF, 0xF, false));
           const int row = j * RG + ((P == 4) ? k : 4 * k + i);
           const float2 tv = tab[rowv + tap_slot(row - yr, S)];
           const float t_im = comp ? tv.y : -tv.y;
