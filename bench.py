@@ -158,6 +158,64 @@ def learned_leg(dev, uvw, vis, wl_plain, rec, wvis, bins, bins_bytes, seg_len, s
     return out
 
 
+def compression_leg(dev, stream, reps: int) -> dict:
+    """Compression (adjacent visibilities on the same oversampled cell and w plane
+    summed, as the paper's preprocess does) on the stand-in for the paper's data
+    set: 2016 baselines x 3600 dumps of 2 s, one channel, quad pol, 2048^2 grid,
+    S=16 W kernel, 32 planes.  Times gr_compress and the binned gridding (gr_bin +
+    gr_grid_binned) of the stream before and after compression; the paper quotes
+    its rates on compressed visibilities."""
+    import torch
+    from paper_1605_07023_amd import binding as B, runner
+    from synth import compression_workload
+    wl = compression_workload()
+    N, P, S = wl.n_vis, wl.n_pol, wl.support
+    dw = runner.upload(wl, dev)
+    rec = torch.empty((N, 2), dtype=torch.int32, device=dev)
+    wv = torch.empty((N, P), dtype=torch.complex64, device=dev)
+    B.gr_preprocess(dw.uvw, dw.vis, B.GR_F32, None, None, N, P, dw.kernel, wl.inv_cell_u, wl.inv_cell_v,
+                    wl.height, wl.width, rec, wv, None, stream)
+    crec, cwv = torch.empty_like(rec), torch.empty_like(wv)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    nw = B.gr_compress_workspace_bytes(N)
+    cws = torch.empty(nw, dtype=torch.uint8, device=dev)
+    nb = B.gr_bin_bytes(N, P, S, wl.height, wl.width, 0)
+    bins = torch.empty(nb, dtype=torch.uint8, device=dev)
+    g = torch.zeros((P, wl.height, wl.width), dtype=torch.complex64, device=dev)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        return sorted(ms)[len(ms) // 2]
+
+    t_comp = timed(lambda: B.gr_compress(rec, wv, N, P, crec, cwv, cnt, cws, nw, stream))
+    m = int(cnt.item())
+
+    def grid_of(r, v):
+        B.gr_bin(r, v, N, P, S, wl.height, wl.width, 0, bins, nb, stream)
+        B.gr_grid_binned(bins, N, P, dw.kernel, 0, g, wl.height, wl.width, stream)
+
+    t_full = timed(lambda: grid_of(rec, wv))
+    t_comp_grid = timed(lambda: grid_of(crec, cwv))
+    log(f"compression leg: {N} -> {m} visibilities, bin+grid {t_full:.2f} -> {t_comp_grid:.2f} ms")
+    del bins, g, rec, wv, crec, cwv
+    return {"workload": "2016 baselines x 3600 dumps of 2 s over 2 h, 1 channel at 1.4 GHz, quad pol, 2048^2, "
+                        "separable W kernel S=16, 32 planes, oversampling 8 (stand-in for the paper's data set)",
+            "n_vis": N, "n_compressed": m, "ratio": N / m, "compress_ms": t_comp,
+            "bin_grid_ms_uncompressed": t_full, "bin_grid_ms_compressed": t_comp_grid,
+            "updates_per_s_uncompressed": N * P * S * S / (t_full * 1e-3),
+            "compressed_updates_per_s": m * P * S * S / (t_comp_grid * 1e-3),
+            "input_updates_per_s_via_compression": N * P * S * S / (t_comp_grid * 1e-3)}
+
+
 def degrid_leg(dev, uvw, wl, kern, grid, stream, reps: int) -> dict:
     """gr_degrid (the adjoint operation, predicting every visibility from the grid)
     on the full-shape S=32 visibilities and the grid the timed steps produced:
@@ -216,6 +274,8 @@ def main() -> int:
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-kernel leg (network vs 2-D table, after the timed region)")
     ap.add_argument("--learned-steps", type=int, default=12000)
+    ap.add_argument("--no-compression", action="store_true",
+                    help="skip the compression leg (2 s-dump tracks, after the timed region)")
     ap.add_argument("--no-degrid", action="store_true",
                     help="skip the degridding leg (gr_degrid of the S=32 grid, after the timed region)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -381,6 +441,11 @@ def main() -> int:
         log("degridding leg")
         degrid = degrid_leg(dev, uvw, wls[32], kern[32], grids[32], stream, reps=5)
 
+    compression = None
+    if not args.no_compression and variant == 2 and args.precision == "f32":
+        log("compression leg")
+        compression = compression_leg(dev, stream, reps=5)
+
     cpu = None
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
@@ -404,6 +469,7 @@ def main() -> int:
         "roofline": roofline,
         "learned_kernel": learned,
         "degrid": degrid,
+        "compression": compression,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -185,6 +185,24 @@ gr_status gr_preprocess_bin(const double* uvw, const void* vis, int32_t vis_dtyp
 gr_status gr_grid_binned(const void* bins, int64_t n_vis, int32_t n_pol, const gr_kernel* kernel,
                          int32_t seg_len, void* grid, int32_t height, int32_t width, void* stream);
 
+/* Compression (Section 2.2, after Muscat; Section 4 applies it once, in the
+ * preprocess): adjacent visibilities at the same position of the oversampled
+ * grid and in the same w plane meet the same GCF samples and are added into
+ * one.  Here "adjacent" is consecutive in the stream of gr_preprocess, and a
+ * dropped visibility separates runs.  records / wvis: gr_preprocess output
+ * (n_vis entries, input order).  out_records / out_wvis (same layouts and
+ * sizes, must not overlap the inputs) receive the compressed stream first, one
+ * entry per run in input order with the run's weighted visibilities summed in
+ * input order (deterministic), then invalid records up to n_vis, so that
+ * gr_bin and gr_grid_binned take them with the same n_vis and no host
+ * synchronisation; gridding them gives the grid of the input up to FP32
+ * rounding.  out_count (device int64, or NULL) receives the number of runs
+ * (overwritten).  workspace: gr_compress_workspace_bytes(n_vis). */
+size_t gr_compress_workspace_bytes(int64_t n_vis);
+gr_status gr_compress(const void* records, const void* wvis, int64_t n_vis, int32_t n_pol,
+                      void* out_records, void* out_wvis, int64_t* out_count, void* workspace,
+                      size_t workspace_bytes, void* stream);
+
 /* Degridding, the adjoint of gridding (Section 6 names degridding with thread
  * coarsening as the next step): predicts every visibility from the grid
  * through the same separable GCF,

@@ -307,23 +307,61 @@ def grid_separable(vis: np.ndarray, uvw: np.ndarray, weights: Optional[np.ndarra
     wv = weighted_vis(vis, weights)
     out = np.zeros((n_pol, height, width), np.complex128) if grid is None \
         else np.array(grid, dtype=np.complex128, copy=True)
-    idx = np.nonzero(pc["valid"])[0]
+    grid_coords(pc, wv, taps, out, taps_v=tv_all, chunk=chunk)
+    return out, int(np.count_nonzero(~pc["valid"]))
+
+
+def grid_coords(coords: dict, wv: np.ndarray, taps: np.ndarray, out: np.ndarray,
+                taps_v: Optional[np.ndarray] = None, chunk: int = 4096) -> np.ndarray:
+    """The definition of :func:`grid_separable` on precomputed coordinates:
+    out[p, y0+ky, x0+kx] += wv[n,p] Tv[plane][sy][ky] Tu[plane][sx][kx] for every n
+    with coords["valid"][n]; out is complex128 [P][H][W], updated in place."""
+    taps = np.asarray(taps)
+    tv_all = taps if taps_v is None else np.asarray(taps_v)
+    support = taps.shape[-1]
+    n_pol, height, width = out.shape
+    idx = np.nonzero(coords["valid"])[0]
     k = np.arange(support)
     flat = out.reshape(n_pol, -1)
     for c0 in range(0, idx.size, chunk):
         sel = idx[c0:c0 + chunk]
-        pl = pc["plane"][sel]
-        tu = taps[pl, pc["sx"][sel]].astype(np.complex128)            # [n][S]
-        tv = tv_all[pl, pc["sy"][sel]].astype(np.complex128)          # [n][S]
+        pl = coords["plane"][sel]
+        tu = taps[pl, coords["sx"][sel]].astype(np.complex128)        # [n][S]
+        tv = tv_all[pl, coords["sy"][sel]].astype(np.complex128)      # [n][S]
         kern = tv[:, :, None] * tu[:, None, :]                        # [n][S][S]
-        rows = pc["y0"][sel][:, None] + k[None, :]
-        cols = pc["x0"][sel][:, None] + k[None, :]
+        rows = coords["y0"][sel][:, None] + k[None, :]
+        cols = coords["x0"][sel][:, None] + k[None, :]
         cell = (rows[:, :, None] * width + cols[:, None, :]).ravel()
         for p in range(n_pol):
             contrib = (kern * wv[sel, p][:, None, None]).ravel()
             flat[p] += np.bincount(cell, weights=contrib.real, minlength=height * width) \
                 + 1j * np.bincount(cell, weights=contrib.imag, minlength=height * width)
-    return out, int(np.count_nonzero(~pc["valid"]))
+    return out
+
+
+def compress(coords: dict, wv: np.ndarray):
+    """Compression (Section 2.2, after Muscat; applied in the preprocess,
+    Section 4): adjacent visibilities that sit at the same position of the
+    oversampled grid and in the same w plane meet the same GCF samples, so they
+    are added into one visibility.  Reading: "adjacent" means consecutive in
+    the input stream, and a dropped visibility separates runs.
+
+    coords: :func:`pixel_coords` output whose "valid" already includes the value
+    rule; wv: weighted visibilities [N][P].  Returns (coords of the compressed
+    stream, keyed like the input, all valid; summed visibilities complex128
+    [M][P]; index of each run's first visibility in the input [M])."""
+    valid = np.asarray(coords["valid"], bool)
+    key = np.stack([np.asarray(coords[k]) for k in ("x0", "y0", "sx", "sy", "plane")], axis=1)
+    same_as_prev = np.zeros(valid.size, bool)
+    same_as_prev[1:] = valid[1:] & valid[:-1] & np.all(key[1:] == key[:-1], axis=1)
+    head = valid & ~same_as_prev
+    heads = np.nonzero(head)[0]
+    run = np.cumsum(head) - 1                   # the run each visibility belongs to
+    sums = np.zeros((heads.size, wv.shape[1]), np.complex128)
+    np.add.at(sums, run[valid], np.asarray(wv, np.complex128)[valid])
+    out = {k: np.asarray(coords[k])[heads] for k in ("x0", "y0", "sx", "sy", "plane")}
+    out["valid"] = np.ones(heads.size, bool)
+    return out, sums, heads
 
 
 def grid_table2d(vis: np.ndarray, uvw: np.ndarray, weights: Optional[np.ndarray],

@@ -75,6 +75,7 @@ def load_library():
         "gr_bin": [P, P, I64, I32, I32, I32, I32, I32, P, SZ, P],
         "gr_preprocess_bin": [P, P, I32, P, P, I64, I32, KP, D, D, I32, I32, I32, P, SZ, P, P],
         "gr_degrid": [P, I64, I32, KP, D, D, P, I32, I32, P, I32, P, SZ, P, P],
+        "gr_compress": [P, P, I64, I32, P, P, P, P, SZ, P],
         "gr_grid_binned": [P, I64, I32, KP, I32, P, I32, I32, P],
         "gr_autotune": [P, P, I64, I32, KP, P, I32, I32, P, SZ, TP, I32, I32, P, P, P],
         "gr_make_wkernel2d_table": [I32, I32, I32, D, D, D, I32, D, I32, I32, P, P],
@@ -95,6 +96,8 @@ def load_library():
     lib.gr_preprocess_bin_bytes.restype = SZ
     lib.gr_degrid_workspace_bytes.argtypes = [I64, I32, I32, I32, I32, I32]
     lib.gr_degrid_workspace_bytes.restype = SZ
+    lib.gr_compress_workspace_bytes.argtypes = [I64]
+    lib.gr_compress_workspace_bytes.restype = SZ
     lib.gr_last_error.argtypes = []
     lib.gr_last_error.restype = ctypes.c_char_p
     lib.gr_grid_batch.argtypes = [ctypes.POINTER(GrBatchItem), I32, P, SZ, P]
@@ -171,6 +174,17 @@ def gr_preprocess_bin(uvw, vis, vis_dtype, vis_scale, weights, n_vis, n_pol, ker
                                             n_vis, n_pol, ctypes.byref(kernel), inv_cell_u, inv_cell_v, height,
                                             width, seg_len, _ptr(bins), bins_bytes, _ptr(dev_stats),
                                             _stream(stream, uvw, vis, bins)))
+
+
+def gr_compress_workspace_bytes(n_vis: int) -> int:
+    return int(load_library().gr_compress_workspace_bytes(n_vis))
+
+
+def gr_compress(records, wvis, n_vis, n_pol, out_records, out_wvis, out_count, workspace, workspace_bytes,
+                stream=None):
+    _check(load_library().gr_compress(_ptr(records), _ptr(wvis), n_vis, n_pol, _ptr(out_records), _ptr(out_wvis),
+                                      _ptr(out_count), _ptr(workspace), workspace_bytes,
+                                      _stream(stream, records, out_records)))
 
 
 def gr_degrid_workspace_bytes(n_vis: int, n_pol: int, support: int, height: int, width: int,

@@ -236,6 +236,34 @@ extern "C" gr_status gr_preprocess_bin(const double* uvw, const void* vis, int32
                                inv_cell_v, height, width, L, bins, rec_tmp, dev_stats, (hipStream_t)stream);
 }
 
+extern "C" size_t gr_compress_workspace_bytes(int64_t n_vis) {
+  return n_vis < 0 ? 0 : compress_workspace_bytes(n_vis);
+}
+
+extern "C" gr_status gr_compress(const void* records, const void* wvis, int64_t n_vis, int32_t n_pol,
+                                 void* out_records, void* out_wvis, int64_t* out_count, void* workspace,
+                                 size_t workspace_bytes, void* stream) {
+  if (n_pol != 1 && n_pol != 4) return fail(GR_EINVAL, "n_pol must be 1 or 4");
+  if (n_vis < 0 || n_vis > 0x7fffffffLL) return fail(GR_EINVAL, "gr_compress: n_vis must be in [0, 2^31)");
+  if (n_vis > 0 && (records == nullptr || wvis == nullptr || out_records == nullptr || out_wvis == nullptr))
+    return fail(GR_EINVAL, "gr_compress: records, wvis, out_records and out_wvis must be non-NULL");
+  if (workspace == nullptr) return fail(GR_EINVAL, "gr_compress: workspace is NULL");
+  if (workspace_bytes < compress_workspace_bytes(n_vis))
+    return fail(GR_ENOMEM, "gr_compress: workspace too small (see gr_compress_workspace_bytes)");
+  // the outputs are written while the inputs are still read: they must not overlap
+  auto overlap = [](const void* a, size_t na, const void* b, size_t nb) {
+    const auto pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+    return pa < pb + nb && pb < pa + na;
+  };
+  const size_t rb = sizeof(Record) * (size_t)n_vis, wb = sizeof(float2) * (size_t)n_vis * n_pol;
+  if (n_vis > 0 && (overlap(out_records, rb, records, rb) || overlap(out_records, rb, wvis, wb) ||
+                    overlap(out_wvis, wb, records, rb) || overlap(out_wvis, wb, wvis, wb)))
+    return fail(GR_EINVAL, "gr_compress: outputs must not overlap the inputs");
+  return launch_compress(reinterpret_cast<const Record*>(records), reinterpret_cast<const float2*>(wvis), n_vis,
+                         n_pol, reinterpret_cast<Record*>(out_records), reinterpret_cast<float2*>(out_wvis),
+                         out_count, workspace, (hipStream_t)stream);
+}
+
 extern "C" size_t gr_degrid_workspace_bytes(int64_t n_vis, int32_t n_pol, int32_t support, int32_t height,
                                             int32_t width, int32_t seg_len) {
   return gr_preprocess_bin_bytes(n_vis, n_pol, support, height, width, seg_len);

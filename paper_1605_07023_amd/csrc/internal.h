@@ -82,6 +82,12 @@ gr_status launch_preprocess_bin(const double* uvw, const void* vis, int vis_dtyp
                                 const float* weights, int64_t n_vis, int n_pol, const gr_kernel& k,
                                 double inv_cell_u, double inv_cell_v, int height, int width, const BinLayout& L,
                                 void* bins, Record* rec_tmp, int64_t* dev_stats, hipStream_t stream);
+// Compression of a preprocessed stream (compress.hip): runs of consecutive kept
+// visibilities with equal records summed into one; out_rec padded with invalid
+// records to n_vis; the number of runs to *out_count (device, may be NULL).
+size_t compress_workspace_bytes(int64_t n_vis);
+gr_status launch_compress(const Record* rec, const float2* wvis, int64_t n_vis, int n_pol, Record* out_rec,
+                          float2* out_wvis, int64_t* out_count, void* workspace, hipStream_t stream);
 // Degridding's binning: records (rec_tmp) and tile counts from uvw, scan,
 // then kept records and their input indices (int32, in the wvis slot of the
 // layout) to the binned positions.

@@ -299,3 +299,44 @@ def learned_kernel_workload(seed: int = 0, n_baselines: Optional[int] = None,
     wl.kernel = "w2d"
     wl.fov = fov
     return wl
+
+
+@functools.lru_cache(maxsize=2)
+def _compression_extent(seed: int) -> np.ndarray:
+    """Two rows of uvw spanning the whole 2 h array's extent: (max|u|, max|v|,
+    max|w|) and its negation, enough for the scale and w-plane fits."""
+    rng = np.random.default_rng(seed)
+    enu = antenna_enu(rng, 64, 1000.0)
+    pairs = baseline_pairs(64)
+    b = enu[pairs[:, 1]] - enu[pairs[:, 0]]
+    full = enu_baselines_to_uvw(b, math.radians(-30.7), math.radians(-30.0), _hour_angles(2.0, 3600),
+                                np.array([1.4e9])).reshape(-1, 3)
+    m = np.abs(full).max(axis=0)
+    return np.stack([m, -m])
+
+
+def compression_workload(seed: int = 0, n_baselines: Optional[int] = None, n_pol: int = 4,
+                         grid: int = 2048, support: int = 16, n_planes: int = 32) -> Workload:
+    """Stand-in for the paper's simulated MeerKAT set (Section 5: 2 h at 2 s
+    dumps, one channel, 7,257,600 visibilities that compress about 3x): the
+    64-antenna array, 2016 baselines x 3600 dumps of 2 s over 2 h, one channel at
+    1.4 GHz, baselines then time, ``grid``^2 cells, separable W kernel
+    (``support`` taps, ``n_planes`` planes, oversampling 8).  Consecutive dumps
+    of short baselines fall on the same oversampled cell, which is what
+    compression merges.  ``n_baselines`` keeps only the first baselines."""
+    rng = np.random.default_rng(seed)
+    enu = antenna_enu(rng, 64, 1000.0)
+    pairs = baseline_pairs(64)
+    if n_baselines is not None:
+        pairs = pairs[:n_baselines]
+    b = enu[pairs[:, 1]] - enu[pairs[:, 0]]
+    uvw = enu_baselines_to_uvw(b, math.radians(-30.7), math.radians(-30.0), _hour_angles(2.0, 3600),
+                               np.array([1.4e9]))
+    flat = np.ascontiguousarray(uvw.reshape(-1, 3))
+    full = _compression_extent(seed)         # scales of the whole array, whatever n_baselines
+    s = _fit_scale(full, grid, grid, support)
+    w_min, inv_dw, whs = _w_planes(full, n_planes, float(max(support - 8, 0)))
+    vis = _draw_vis(rng, flat.shape[0], n_pol)
+    return Workload(f"compress-E1-{grid}", flat, vis, None, grid, grid, support, 8, s, s,
+                    n_planes=n_planes, w_min=w_min, inv_dw=inv_dw, w_hat_scale=whs, kernel="wsep",
+                    beta=8.6, support_aa=8)

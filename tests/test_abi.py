@@ -171,6 +171,22 @@ def test_degrid_rejects(lib):
     assert st == B.GR_EUNSUPPORTED
 
 
+def test_compress_rejects(lib):
+    """Host-side validation of gr_compress, before anything is enqueued."""
+    from paper_1605_07023_amd import binding as B
+    nw = B.gr_compress_workspace_bytes(1000)
+    assert nw >= 4 * 4 and B.gr_compress_workspace_bytes(-1) == 0
+    a, b, c, d = 1 << 20, 1 << 24, 1 << 28, 1 << 32
+    st = lib.gr_compress(a, b, 1000, 4, c, d, None, 1 << 36, nw - 1, None)
+    assert st == B.GR_ENOMEM and "gr_compress_workspace_bytes" in lib.gr_last_error().decode()
+    st = lib.gr_compress(a, b, 1000, 4, a + 800, d, None, 1 << 36, nw, None)    # out_records overlaps records
+    assert st == B.GR_EINVAL and "overlap" in lib.gr_last_error().decode()
+    st = lib.gr_compress(a, None, 1000, 4, c, d, None, 1 << 36, nw, None)
+    assert st == B.GR_EINVAL and "non-NULL" in lib.gr_last_error().decode()
+    st = lib.gr_compress(a, b, 1000, 2, c, d, None, 1 << 36, nw, None)
+    assert st == B.GR_EINVAL and "n_pol" in lib.gr_last_error().decode()
+
+
 def test_table_generators_reject(lib):
     from paper_1605_07023_amd import binding as B
     assert lib.gr_make_kb_table(8.6, 7, 8, B.GR_F32, 1 << 20, None) == B.GR_EINVAL

@@ -1,0 +1,133 @@
+"""GPU tests of gr_compress (Section 2.2 compression as a preprocess) through the C ABI.
+
+Bars: the runs (their records and order) equal the oracle's exactly; summed
+visibilities within FP32 rounding of the FP64 sums (integer values exact);
+records after the compressed stream invalid; gridding the compressed stream
+equals gridding the input within 1e-5 relative L2 (bit for bit with integer
+values and taps).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import gridding as G  # noqa: E402
+from synth import compression_workload  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1605_07023_amd import binding, runner
+    binding.load_library()
+    return runner
+
+
+def _compress(R, rec, wv, n, P):
+    from paper_1605_07023_amd import binding as B
+    orec = torch.full_like(rec, 7)
+    owv = torch.empty_like(wv)
+    cnt = torch.full((1,), -1, dtype=torch.int64, device=DEV)
+    nw = B.gr_compress_workspace_bytes(n)
+    ws = torch.empty(nw, dtype=torch.uint8, device=DEV)
+    B.gr_compress(rec, wv, n, P, orec, owv, cnt, ws, nw)
+    torch.cuda.synchronize()
+    return orec, owv, int(cnt.item())
+
+
+def _grid_binned(R, rec, wv, n, P, wl, kern, seg=0):
+    from paper_1605_07023_amd import binding as B
+    nb = B.gr_bin_bytes(n, P, wl.support, wl.height, wl.width, seg)
+    bins = torch.empty(nb, dtype=torch.uint8, device=DEV)
+    B.gr_bin(rec, wv, n, P, wl.support, wl.height, wl.width, seg, bins, nb)
+    g = torch.zeros((P, wl.height, wl.width), dtype=torch.complex64, device=DEV)
+    B.gr_grid_binned(bins, n, P, kern, seg, g, wl.height, wl.width)
+    torch.cuda.synchronize()
+    return g.cpu().numpy().astype(np.complex128)
+
+
+@pytest.mark.parametrize("P", [4, 1])
+def test_compress_matches_oracle_and_keeps_the_grid(R, P):
+    _say(f"compression on 2 s-dump tracks, P={P}")
+    wl = compression_workload(n_baselines=40, n_pol=P, grid=1024, support=16, n_planes=8)
+    wl.uvw = wl.uvw.copy()
+    wl.uvw[100, 0] = np.nan                      # a dropped visibility inside a run
+    dw = R.upload(wl, DEV)
+    rec, wv = R.preprocess(dw)
+    N = wl.n_vis
+    orec, owv, m = _compress(R, rec, wv, N, P)
+    pc = G.pixel_coords(wl.uvw, wl.inv_cell_u, wl.inv_cell_v, 8, 16, 1024, 1024, 8, wl.w_min, wl.inv_dw)
+    out, sums, heads = G.compress(pc, G.weighted_vis(wl.vis, None))
+    _say(f"  {N} visibilities -> {m} ({N / m:.2f}x)")
+    assert m == heads.size and N / m > 2.0
+    got = R.decode_records(orec.cpu().numpy())
+    for k in ("x0", "y0", "sx", "sy", "plane"):
+        np.testing.assert_array_equal(got[k][:m], out[k], err_msg=k)
+    assert got["valid"][:m].all() and not got["valid"][m:].any()
+    v = owv.cpu().numpy()[:m].astype(np.complex128)
+    err = float(np.linalg.norm(v - sums) / np.linalg.norm(sums))
+    _say(f"  summed visibilities rel L2 {err:.2e}")
+    assert err <= 1e-6
+    g_in = R.grid(dw).cpu().numpy().astype(np.complex128)
+    g_c = _grid_binned(R, orec, owv, N, P, wl, dw.kernel)
+    e = float(np.linalg.norm(g_c - g_in) / np.linalg.norm(g_in))
+    _say(f"  compressed grid vs input grid rel L2 {e:.2e}")
+    assert e <= 1e-5
+
+
+def test_compress_integer_values_exact(R):
+    """Integer visibilities and taps: the summed runs and the grids are exact."""
+    from paper_1605_07023_amd import binding as B
+    _say("compression, integer values, exact")
+    rng = np.random.default_rng(3)
+    wl = compression_workload(n_baselines=20, n_pol=4, grid=512, support=8, n_planes=4)
+    wl.vis = (rng.integers(-3, 4, (wl.n_vis, 4)) + 1j * rng.integers(-3, 4, (wl.n_vis, 4))).astype(np.complex64)
+    taps = rng.integers(-1, 2, (4, 8, 8)) + 1j * rng.integers(-1, 2, (4, 8, 8))
+    t = torch.from_numpy(np.ascontiguousarray(np.stack([taps.real, taps.imag], axis=-1), dtype=np.float32)).to(DEV)
+    dw = R.upload(wl, DEV, taps=t)
+    dw.kernel = B.make_kernel(t, 8, 8, 4, taps_complex=True, w_min=wl.w_min, inv_dw=wl.inv_dw)
+    rec, wv = R.preprocess(dw)
+    orec, owv, m = _compress(R, rec, wv, wl.n_vis, 4)
+    pc = G.pixel_coords(wl.uvw, wl.inv_cell_u, wl.inv_cell_v, 8, 8, 512, 512, 4, wl.w_min, wl.inv_dw)
+    out, sums, heads = G.compress(pc, G.weighted_vis(wl.vis, None))
+    np.testing.assert_array_equal(owv.cpu().numpy()[:m].astype(np.complex128), sums)
+    g_in, _ = G.grid_separable(wl.vis, wl.uvw, None, taps, wl.inv_cell_u, wl.inv_cell_v, 8, 512, 512, 4,
+                               wl.w_min, wl.inv_dw)
+    np.testing.assert_array_equal(_grid_binned(R, orec, owv, wl.n_vis, 4, wl, dw.kernel, 64), g_in)
+
+
+def test_compress_edge_cases(R):
+    """Empty stream; all dropped; one run over the whole stream."""
+    from paper_1605_07023_amd import binding as B
+    _say("compression edge cases")
+    rec = torch.zeros((1, 2), dtype=torch.int32, device=DEV)
+    wv = torch.zeros((1, 4), dtype=torch.complex64, device=DEV)
+    _, _, m = _compress(R, rec, wv, 0, 4)
+    assert m == 0
+    rec = torch.zeros((1000, 2), dtype=torch.int32, device=DEV)      # all invalid
+    wv = torch.ones((1000, 1), dtype=torch.complex64, device=DEV)
+    orec, _, m = _compress(R, rec, wv, 1000, 1)
+    assert m == 0 and not orec.any()
+    r = np.zeros((5000, 2), np.uint32)
+    r[:, 0] = 7 | (9 << 16)
+    r[:, 1] = 3 | (5 << 8) | (2 << 16) | (1 << 31)
+    rec = torch.from_numpy(r.view(np.int32)).to(DEV)
+    vals = np.arange(5000, dtype=np.float32)
+    wv = torch.from_numpy((vals + 1j * (2 * vals)).astype(np.complex64)[:, None]).to(DEV)
+    orec, owv, m = _compress(R, rec, wv, 5000, 1)
+    assert m == 1
+    assert orec.cpu().numpy()[0].view(np.uint32).tolist() == r[0].tolist()
+    s = float(np.sum(vals, dtype=np.float64))
+    assert owv.cpu().numpy()[0, 0] == np.complex64(complex(s, 2 * s))
+    assert not orec.cpu().numpy()[1:].any()
+    assert B.gr_compress_workspace_bytes(5000) > 0

@@ -379,3 +379,44 @@ def test_continuous_w2d_grid_equals_table_grid_on_table_points():
     got2, _ = G.grid_w2d_continuous(vis, uvw2, None, 1.0, 1.0, O, S, H, W, n_planes, w_min, inv_dw,
                                     whs, 0.5)
     assert np.linalg.norm(got2 - ref) > 1e-3 * np.linalg.norm(ref)
+
+
+def _coords_of(x0, y0, sx, sy, plane, valid):
+    return {"x0": np.array(x0), "y0": np.array(y0), "sx": np.array(sx), "sy": np.array(sy),
+            "plane": np.array(plane), "valid": np.array(valid, bool)}
+
+
+def test_compress_hand_case():
+    """Runs of equal (x0, y0, sx, sy, plane) among consecutive kept visibilities
+    merge; a changed key or a dropped visibility starts a new run."""
+    c = _coords_of([5, 5, 5, 6, 5, 5, 5, 5], [2, 2, 2, 2, 2, 2, 2, 2], [1, 1, 1, 1, 1, 1, 1, 2],
+                [0, 0, 0, 0, 0, 0, 0, 0], [0, 0, 0, 0, 0, 0, 0, 0], [1, 1, 1, 1, 0, 1, 1, 1])
+    wv = (np.arange(8) + 1j * np.arange(8)[::-1])[:, None] * np.array([[1.0, 10.0]])
+    out, sums, heads = G.compress(c, wv)
+    assert heads.tolist() == [0, 3, 5, 7]
+    np.testing.assert_array_equal(sums, np.array([wv[0] + wv[1] + wv[2], wv[3], wv[5] + wv[6], wv[7]]))
+    assert out["x0"].tolist() == [5, 6, 5, 5] and out["sx"].tolist() == [1, 1, 1, 2] and out["valid"].all()
+
+
+def test_compress_matches_brute_force_and_keeps_the_grid():
+    """On the 2 s-dump tracks (first 12 baselines): the run structure equals a
+    plain loop over the stream, and gridding the compressed stream gives the
+    grid of the full stream (FP64, 1e-12)."""
+    from synth import compression_workload
+    wl = compression_workload(n_baselines=12, n_pol=2, grid=512, support=8, n_planes=4)
+    pc = G.pixel_coords(wl.uvw, wl.inv_cell_u, wl.inv_cell_v, 8, 8, 512, 512, 4, wl.w_min, wl.inv_dw)
+    wv = G.weighted_vis(wl.vis, None)
+    out, sums, heads = G.compress(pc, wv)
+    keys = list(zip(*(pc[k].tolist() for k in ("x0", "y0", "sx", "sy", "plane"))))
+    bf_heads, prev = [], None
+    for i, (k, ok) in enumerate(zip(keys, pc["valid"].tolist())):
+        if ok and k != prev:
+            bf_heads.append(i)
+        prev = k if ok else None
+    assert heads.tolist() == bf_heads
+    assert wl.n_vis / heads.size > 2.0                  # short 2 s dumps do merge
+    taps = G.wkernel_table(8, 8, wl.plane_w_hat())
+    full, _ = G.grid_separable(wl.vis, wl.uvw, None, taps, wl.inv_cell_u, wl.inv_cell_v, 8, 512, 512, 4,
+                               wl.w_min, wl.inv_dw)
+    comp = G.grid_coords(out, sums, taps, np.zeros((2, 512, 512), np.complex128))
+    assert np.abs(comp - full).max() <= 1e-12 * np.abs(full).max()
