@@ -75,13 +75,14 @@ degrid_kernel(const Record* __restrict__ rec, const int32_t* __restrict__ idx, c
   float2* tab = reinterpret_cast<float2*>(lds_raw + (size_t)WR * P * LS * sizeof(float));   // [rows][S + 2]
   __shared__ int s_seg;
 
-  // tap table: rows [plane * O + s] of S + 2 (re, im) entries, zero at both ends
+  // tap table: rows [plane * O + s] of S + 2 (re, im) entries, zero at both ends,
+  // and one row of zeros after them for the lanes of a batch's missing visibilities
   {
     const int S = d.S, SP = d.S + 2;
-    const int n_elem = d.n_rows_tab * SP;
+    const int n_elem = (d.n_rows_tab + 1) * SP;
     for (int e = threadIdx.x; e < n_elem; e += blockDim.x) {
       const int row = e / SP, kk = e - row * SP - 1;
-      const bool in = kk >= 0 && kk < S;
+      const bool in = kk >= 0 && kk < S && row < d.n_rows_tab;
       const int64_t src = (int64_t)row * S + (in ? kk : 0);
       float re = 0.f, im = 0.f;
       if (in) {
@@ -130,8 +131,10 @@ degrid_kernel(const Record* __restrict__ rec, const int32_t* __restrict__ idx, c
       const bool live = v < nb;
       const Record r = rec[begin + b0 + (live ? v : 0)];
       const int xr = rec_x0(r) - win_x0, yr = rec_y0(r) - win_y0;
-      const int rowu = (rec_plane(r) * d.O + rec_sx(r)) * (S + 2);
-      const int rowv = (rec_plane(r) * d.O + rec_sy(r)) * (S + 2);
+      // a missing visibility reads the zero row: its B values and G^v taps are 0
+      const int zero_row = d.n_rows_tab * (S + 2);
+      const int rowu = live ? (rec_plane(r) * d.O + rec_sx(r)) * (S + 2) : zero_row;
+      const int rowv = live ? (rec_plane(r) * d.O + rec_sy(r)) * (S + 2) : zero_row;
       // row and column groups that the batch's footprints touch (lane 2q holds visibility q)
       int xlo = 1 << 30, xhi = -(1 << 30), ylo = 1 << 30, yhi = -(1 << 30);
       for (int q = 0; q < nb; ++q) {
@@ -152,8 +155,7 @@ degrid_kernel(const Record* __restrict__ rec, const int32_t* __restrict__ idx, c
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           const float2 t = tab[rowu + tap_slot(8 * c + 2 * s + xk - xr, S)];
-          const float b = bcomp == comp ? t.x : (bcomp ? -t.y : t.y);
-          bfr[c][s] = live ? b : 0.f;
+          bfr[c][s] = bcomp == comp ? t.x : (bcomp ? -t.y : t.y);
         }
       }
       float vacc[P == 4 ? 4 : 1];
@@ -294,7 +296,7 @@ int window_for(int support) { return support <= 16 ? 32 : support <= 32 ? 48 : 6
 size_t degrid_lds(const gr_kernel& k, int n_pol) {
   const int wr = window_for(k.support);
   return align256((size_t)wr * n_pol * degrid_line(wr) * sizeof(float)) +
-         (size_t)k.n_planes * k.oversample * (k.support + 2) * sizeof(float2);
+         ((size_t)k.n_planes * k.oversample + 1) * (k.support + 2) * sizeof(float2);
 }
 
 using DegridFn = void (*)(const Record*, const int32_t*, const int4*, const int32_t*, int32_t*, const void*, int,
