@@ -161,18 +161,28 @@ degrid_kernel(const Record* __restrict__ rec, const int32_t* __restrict__ idx, c
       float vacc[P == 4 ? 4 : 1];
 #pragma unroll
       for (int i = 0; i < (P == 4 ? 4 : 1); ++i) vacc[i] = 0.f;
+      // wave-uniform masks of the row and column groups in the batch's footprints
+      const uint32_t rmask = ((2u << g_hi) - 1u) & ~((1u << g_lo) - 1u);
+      const uint32_t cmask = ((2u << c_hi) - 1u) & ~((1u << c_lo) - 1u);
 #pragma unroll
       for (int j = 0; j < NRG; ++j) {
-        if (j < g_lo || j > g_hi) continue;          // uniform
+        if (!((rmask >> j) & 1u)) continue;          // uniform
+        // the row group's A operands first (every column group: reads stay in the
+        // window), so that the wave waits for LDS once per row group
+        float av[WCG][4];
+        const float* a = win + a_lane + j * RG * P * LS;
+#pragma unroll
+        for (int c = 0; c < WCG; ++c)
+#pragma unroll
+          for (int s = 0; s < 4; ++s) av[c][s] = a[16 * c + 4 * s];
         f4 z0 = {0.f, 0.f, 0.f, 0.f}, z1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int c = 0; c < WCG; ++c) {
-          if (c < c_lo || c > c_hi) continue;        // uniform
-          const float* a = win + a_lane + j * RG * P * LS + 16 * c;
-          z0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], bfr[c][0], z0, 0, 0, 0);
-          z1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4], bfr[c][1], z1, 0, 0, 0);
-          z0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[8], bfr[c][2], z0, 0, 0, 0);
-          z1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[12], bfr[c][3], z1, 0, 0, 0);
+          if (!((cmask >> c) & 1u)) continue;        // uniform
+          z0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c][0], bfr[c][0], z0, 0, 0, 0);
+          z1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c][1], bfr[c][1], z1, 0, 0, 0);
+          z0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c][2], bfr[c][2], z0, 0, 0, 0);
+          z1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c][3], bfr[c][3], z1, 0, 0, 0);
         }
         // stage 2: D row 4k + i of this lane is (row k, pol i) at P = 4, row 4k + i at P = 1
 #pragma unroll
