@@ -16,8 +16,8 @@
 //    cells, Z[(r, p), (v, re|im)] += sum_{(x, re|im)} G[(r, p), (x, re|im)]
 //    B[(x, re|im), (v, re|im)], four v_mfma_f32_16x16x4_f32 per column group
 //    (K = 2 cells x (re, im)), with B the sign pattern that makes the real
-//    product the complex G . G^u.  Only the row and column groups that the
-//    batch's footprints touch are issued.  The A operand is one LDS read at a
+//    product the complex G . G^u.  Only the row groups and the cell pairs
+//    (one MFMA each) that the batch's footprints touch are issued.  The A operand is one LDS read at a
 //    lane-constant address plus an immediate offset; the window lines are
 //    padded so that those reads are free of bank conflicts.
 //  * Stage 2, per row group: each lane multiplies its Z values by its
@@ -146,14 +146,17 @@ degrid_kernel(const Record* __restrict__ rec, const int32_t* __restrict__ idx, c
       }
       const int g_lo = __builtin_amdgcn_readfirstlane(ylo / RG);
       const int g_hi = __builtin_amdgcn_readfirstlane((yhi + S - 1) / RG);
-      const int c_lo = __builtin_amdgcn_readfirstlane(xlo >> 3);
-      const int c_hi = __builtin_amdgcn_readfirstlane((xhi + S - 1) >> 3);
+      // cell pairs (one MFMA's K slice) that the footprints touch
+      const int c_lo = __builtin_amdgcn_readfirstlane(xlo >> 1);
+      const int c_hi = __builtin_amdgcn_readfirstlane((xhi + S - 1) >> 1);
+      const uint64_t cmask = ((2ull << c_hi) - 1ull) & ~((1ull << c_lo) - 1ull);
       // B: visibility v's G^u tap at cell 8c + 2s + xk, as the (bcomp, comp) entry of the complex product
       float bfr[WCG][4];
 #pragma unroll
       for (int c = 0; c < WCG; ++c) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
+          if (!((cmask >> (4 * c + s)) & 1ull)) continue;   // uniform; the value is not used
           const float2 t = tab[rowu + tap_slot(8 * c + 2 * s + xk - xr, S)];
           bfr[c][s] = bcomp == comp ? t.x : (bcomp ? -t.y : t.y);
         }
@@ -161,9 +164,8 @@ degrid_kernel(const Record* __restrict__ rec, const int32_t* __restrict__ idx, c
       float vacc[P == 4 ? 4 : 1];
 #pragma unroll
       for (int i = 0; i < (P == 4 ? 4 : 1); ++i) vacc[i] = 0.f;
-      // wave-uniform masks of the row and column groups in the batch's footprints
+      // wave-uniform mask of the row groups in the batch's footprints
       const uint32_t rmask = ((2u << g_hi) - 1u) & ~((1u << g_lo) - 1u);
-      const uint32_t cmask = ((2u << c_hi) - 1u) & ~((1u << c_lo) - 1u);
 #pragma unroll
       for (int j = 0; j < NRG; ++j) {
         if (!((rmask >> j) & 1u)) continue;          // uniform
@@ -178,11 +180,13 @@ degrid_kernel(const Record* __restrict__ rec, const int32_t* __restrict__ idx, c
         f4 z0 = {0.f, 0.f, 0.f, 0.f}, z1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int c = 0; c < WCG; ++c) {
-          if (!((cmask >> c) & 1u)) continue;        // uniform
-          z0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c][0], bfr[c][0], z0, 0, 0, 0);
-          z1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c][1], bfr[c][1], z1, 0, 0, 0);
-          z0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c][2], bfr[c][2], z0, 0, 0, 0);
-          z1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c][3], bfr[c][3], z1, 0, 0, 0);
+#pragma unroll
+          for (int s = 0; s < 4; s += 2) {
+            if ((cmask >> (4 * c + s)) & 1ull)           // uniform
+              z0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c][s], bfr[c][s], z0, 0, 0, 0);
+            if ((cmask >> (4 * c + s + 1)) & 1ull)
+              z1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c][s + 1], bfr[c][s + 1], z1, 0, 0, 0);
+          }
         }
         // stage 2: D row 4k + i of this lane is (row k, pol i) at P = 4, row 4k + i at P = 1
 #pragma unroll
