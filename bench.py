@@ -216,6 +216,85 @@ def compression_leg(dev, stream, reps: int) -> dict:
             "input_updates_per_s_via_compression": N * P * S * S / (t_comp_grid * 1e-3)}
 
 
+def wstack_leg(dev, stream, reps: int) -> dict:
+    """W-stacking (Section 5: the stream split by w into 7 slices, each gridded as
+    its own problem with a GCF for the w offset from the slice's centre) on the
+    2 h, 2 s-dump tracks: gr_wslice_partition of the whole stream, then the 7
+    slices gridded by one gr_grid_batch (persistent work list over every slice)
+    and, as the paper launches them, by one gr_grid per slice; S=16 and S=32,
+    32 residual planes per slice, 2048^2 grids.  HIP events on the stream, median
+    of ``reps`` after one untimed call."""
+    import torch
+    from paper_1605_07023_amd import binding as B, runner
+    from synth import wstack_workload
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        return sorted(ms)[len(ms) // 2]
+
+    out = {"workload": "2016 baselines x 3600 dumps of 2 s over 2 h, 1 channel at 1.4 GHz, quad pol, "
+                       "7 equal w slices over [-max|w|, max|w|], 2048^2 grid per slice, separable W kernel "
+                       "of 32 planes over the slice width, oversampling 8", "per_support": {}}
+    for S in (16, 32):
+        wl = wstack_workload(n_pol=4, grid=2048, support=S)
+        m = wl.meta
+        N, P, n_sl = wl.n_vis, wl.n_pol, m["n_slices"]
+        dw = runner.upload(wl, dev)
+        uvw_p, vis_p = torch.empty_like(dw.uvw), torch.empty_like(dw.vis)
+        offs = torch.empty(n_sl + 1, dtype=torch.int64, device=dev)
+        nw = B.gr_wslice_partition_workspace_bytes(N, n_sl)
+        pws = torch.empty(nw, dtype=torch.uint8, device=dev)
+
+        def part():
+            B.gr_wslice_partition(dw.uvw, dw.vis, None, N, P, m["w_first"], m["inv_width"], n_sl, uvw_p, vis_p,
+                                  None, offs, pws, nw, stream)
+
+        t_part = timed(part)
+        off = offs.cpu().numpy()
+        sizes = [int(off[s + 1] - off[s]) for s in range(n_sl)]
+        grids = torch.zeros((n_sl, P, wl.height, wl.width), dtype=torch.complex64, device=dev)
+        kernels = [runner.slice_kernel(dw.kernel, runner.slice_w_min(m["w_first"], m["inv_width"], s, wl.w_min))
+                   for s in range(n_sl)]
+        items = [B.make_batch_item(uvw_p[int(off[s]):], vis_p[int(off[s]):], B.GR_F32, P, None, None, sizes[s],
+                                   kernels[s], wl.inv_cell_u, wl.inv_cell_v, grids[s], wl.height, wl.width)
+                 for s in range(n_sl)]
+        need = B.gr_grid_batch_workspace_bytes(items)
+        bws = torch.empty(need, dtype=torch.uint8, device=dev)
+        t_batch = timed(lambda: B.gr_grid_batch(items, bws, need, stream))
+        ws_need = max(B.gr_grid_workspace_bytes(sizes[s], P, kernels[s], wl.height, wl.width, None)
+                      for s in range(n_sl))
+        gws = torch.empty(ws_need, dtype=torch.uint8, device=dev)
+
+        def per_slice():
+            for s in range(n_sl):
+                if sizes[s]:
+                    a = int(off[s])
+                    B.gr_grid(uvw_p[a:], vis_p[a:], B.GR_F32, None, None, sizes[s], P, kernels[s], wl.inv_cell_u,
+                              wl.inv_cell_v, grids[s], wl.height, wl.width, None, gws, ws_need, None, stream)
+
+        t_per = timed(per_slice)
+        kept = int(off[n_sl])
+        upd = kept * P * S * S
+        log(f"w-stacking leg S={S}: partition {t_part:.3f} ms, batch {t_batch:.2f} ms, per slice {t_per:.2f} ms")
+        out["per_support"][str(S)] = {
+            "n_vis": N, "slice_sizes": sizes, "partition_ms": t_part,
+            "partition_GB_per_s": 2 * N * (24 + 8 * P) / (t_part * 1e-3) / 1e9,
+            "batch_ms": t_batch, "per_slice_ms": t_per,
+            "batch_updates_per_s": upd / (t_batch * 1e-3), "per_slice_updates_per_s": upd / (t_per * 1e-3)}
+        del grids, bws, gws, uvw_p, vis_p, dw
+        torch.cuda.empty_cache()
+    return out
+
+
 def degrid_leg(dev, uvw, wl, kern, grid, stream, reps: int) -> dict:
     """gr_degrid (the adjoint operation, predicting every visibility from the grid)
     on the full-shape S=32 visibilities and the grid the timed steps produced:
@@ -276,6 +355,8 @@ def main() -> int:
     ap.add_argument("--learned-steps", type=int, default=12000)
     ap.add_argument("--no-compression", action="store_true",
                     help="skip the compression leg (2 s-dump tracks, after the timed region)")
+    ap.add_argument("--no-wstack", action="store_true",
+                    help="skip the w-stacking leg (7 w slices of the 2 s-dump tracks, after the timed region)")
     ap.add_argument("--no-degrid", action="store_true",
                     help="skip the degridding leg (gr_degrid of the S=32 grid, after the timed region)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -446,6 +527,11 @@ def main() -> int:
         log("compression leg")
         compression = compression_leg(dev, stream, reps=5)
 
+    wstack = None
+    if not args.no_wstack and variant == 2 and args.precision == "f32":
+        log("w-stacking leg")
+        wstack = wstack_leg(dev, stream, reps=5)
+
     cpu = None
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
@@ -470,6 +556,7 @@ def main() -> int:
         "learned_kernel": learned,
         "degrid": degrid,
         "compression": compression,
+        "wstack": wstack,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

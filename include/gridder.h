@@ -203,6 +203,29 @@ gr_status gr_compress(const void* records, const void* wvis, int64_t n_vis, int3
                       void* out_records, void* out_wvis, int64_t* out_count, void* workspace,
                       size_t workspace_bytes, void* stream);
 
+/* W-stacking's split (Section 5 grids the data as a stack of slices by w,
+ * one problem per slice, each with a GCF for the w offset from the slice's
+ * centre): a stable partition of the stream by
+ *   slice = floor((w - w_first) * inv_width)         (FP64)
+ * into 1 <= n_slices <= 255 slices.  uvw [n_vis][3] f64, vis complex64
+ * [n_vis][n_pol], weights f32 [n_vis][n_pol] or NULL (device, input order)
+ * are copied to uvw_out / vis_out / weights_out (same layouts and sizes;
+ * weights_out is needed exactly when weights is given; none may overlap an
+ * input): slice 0's visibilities first, in input order, then slice 1's, and
+ * so on, then those whose slice falls outside [0, n_slices) or whose w is not
+ * finite, in input order.  The output is a permutation of the input, moved
+ * bit for bit.  slice_offsets (device int64 [n_slices + 1], overwritten):
+ * slice s occupies [slice_offsets[s], slice_offsets[s + 1]) for s < n_slices
+ * (with slice_offsets[n_slices] the first visibility outside every slice),
+ * which lets each slice be gridded as its own problem (gr_grid_batch items
+ * pointing into the outputs) with the kernel's w_min moved to that slice.
+ * No host synchronisation.  workspace: gr_wslice_partition_workspace_bytes. */
+size_t gr_wslice_partition_workspace_bytes(int64_t n_vis, int32_t n_slices);
+gr_status gr_wslice_partition(const double* uvw, const void* vis, const float* weights, int64_t n_vis,
+                              int32_t n_pol, double w_first, double inv_width, int32_t n_slices,
+                              double* uvw_out, void* vis_out, float* weights_out, int64_t* slice_offsets,
+                              void* workspace, size_t workspace_bytes, void* stream);
+
 /* Degridding, the adjoint of gridding (Section 6 names degridding with thread
  * coarsening as the next step): predicts every visibility from the grid
  * through the same separable GCF,

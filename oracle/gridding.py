@@ -364,6 +364,70 @@ def compress(coords: dict, wv: np.ndarray):
     return out, sums, heads
 
 
+# ----------------------------------------------------------------------------
+# W-stacking slices (Section 5: the data is split into slices by w, and each
+# slice is gridded as its own problem)
+# ----------------------------------------------------------------------------
+
+def wslice_index(uvw: np.ndarray, w_first: float, inv_width: float, n_slices: int) -> np.ndarray:
+    """Slice of each visibility, int64 [N]; n_slices for none.
+
+    Reading (the paper fixes no rule): slices of equal width 1 / inv_width
+    starting at w_first, slice = floor((w - w_first) * inv_width) in FP64; a
+    visibility whose slice falls outside [0, n_slices), or whose w is not
+    finite, belongs to no slice."""
+    w = np.asarray(uvw, dtype=np.float64)[:, 2]
+    with np.errstate(invalid="ignore"):
+        t = (w - w_first) * inv_width
+        inside = (t >= 0.0) & (t < n_slices)          # NaN fails both
+    return np.where(inside, np.floor(np.where(inside, t, 0.0)), n_slices).astype(np.int64)
+
+
+def wslice_partition(uvw: np.ndarray, w_first: float, inv_width: float, n_slices: int):
+    """Stable partition of the stream by slice: (order, offsets) with
+    order[offsets[s]:offsets[s + 1]] the input indices of slice s in input
+    order (s < n_slices) and order[offsets[n_slices]:] those of no slice."""
+    s = wslice_index(uvw, w_first, inv_width, n_slices)
+    order = np.argsort(s, kind="stable")
+    counts = np.bincount(s, minlength=n_slices + 1)
+    offsets = np.concatenate([[0], np.cumsum(counts)[:-1]]).astype(np.int64)
+    return order, offsets
+
+
+def wslice_w_min(w_first: float, inv_width: float, s: int, w_min_rel: float) -> float:
+    """w_min of slice s's GCF table.  Reading: the table's planes are relative
+    to the slice's centre w_first + (s + 1/2) / inv_width (the stack corrects
+    that w; the GCF only the offset from it), so its w_min moves with the
+    centre."""
+    return w_first + (s + 0.5) / inv_width + w_min_rel
+
+
+def grid_wstack(vis: np.ndarray, uvw: np.ndarray, weights: Optional[np.ndarray], taps: np.ndarray,
+                inv_cell_u: float, inv_cell_v: float, oversample: int, height: int, width: int,
+                n_planes: int, w_min_rel: float, inv_dw: float, w_first: float, inv_width: float,
+                n_slices: int):
+    """Every slice gridded on its own into its own grid by the definition of
+    :func:`grid_separable`, with the table ``taps`` whose plane rule is
+    rint((w - wslice_w_min(s)) * inv_dw).  Returns (grids complex128
+    [n_slices][P][H][W], visibilities dropped inside the slices by the
+    coordinate and value rules, visibilities in no slice)."""
+    vis = np.asarray(vis)
+    n_pol = vis.shape[1]
+    order, offsets = wslice_partition(uvw, w_first, inv_width, n_slices)
+    grids = np.zeros((n_slices, n_pol, height, width), np.complex128)
+    dropped = 0
+    for s in range(n_slices):
+        sel = order[offsets[s]:offsets[s + 1]]
+        if sel.size == 0:
+            continue
+        g, d = grid_separable(vis[sel], np.asarray(uvw)[sel], None if weights is None else np.asarray(weights)[sel],
+                              taps, inv_cell_u, inv_cell_v, oversample, height, width, n_planes,
+                              wslice_w_min(w_first, inv_width, s, w_min_rel), inv_dw)
+        grids[s] = g
+        dropped += d
+    return grids, dropped, int(order.size - offsets[n_slices])
+
+
 def grid_table2d(vis: np.ndarray, uvw: np.ndarray, weights: Optional[np.ndarray],
                  taps2d: np.ndarray, inv_cell_u: float, inv_cell_v: float, oversample: int,
                  height: int, width: int, n_planes: int, w_min: float, inv_dw: float,

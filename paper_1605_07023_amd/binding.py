@@ -76,6 +76,7 @@ def load_library():
         "gr_preprocess_bin": [P, P, I32, P, P, I64, I32, KP, D, D, I32, I32, I32, P, SZ, P, P],
         "gr_degrid": [P, I64, I32, KP, D, D, P, I32, I32, P, I32, P, SZ, P, P],
         "gr_compress": [P, P, I64, I32, P, P, P, P, SZ, P],
+        "gr_wslice_partition": [P, P, P, I64, I32, D, D, I32, P, P, P, P, P, SZ, P],
         "gr_grid_binned": [P, I64, I32, KP, I32, P, I32, I32, P],
         "gr_autotune": [P, P, I64, I32, KP, P, I32, I32, P, SZ, TP, I32, I32, P, P, P],
         "gr_make_wkernel2d_table": [I32, I32, I32, D, D, D, I32, D, I32, I32, P, P],
@@ -98,6 +99,8 @@ def load_library():
     lib.gr_degrid_workspace_bytes.restype = SZ
     lib.gr_compress_workspace_bytes.argtypes = [I64]
     lib.gr_compress_workspace_bytes.restype = SZ
+    lib.gr_wslice_partition_workspace_bytes.argtypes = [I64, I32]
+    lib.gr_wslice_partition_workspace_bytes.restype = SZ
     lib.gr_last_error.argtypes = []
     lib.gr_last_error.restype = ctypes.c_char_p
     lib.gr_grid_batch.argtypes = [ctypes.POINTER(GrBatchItem), I32, P, SZ, P]
@@ -185,6 +188,18 @@ def gr_compress(records, wvis, n_vis, n_pol, out_records, out_wvis, out_count, w
     _check(load_library().gr_compress(_ptr(records), _ptr(wvis), n_vis, n_pol, _ptr(out_records), _ptr(out_wvis),
                                       _ptr(out_count), _ptr(workspace), workspace_bytes,
                                       _stream(stream, records, out_records)))
+
+
+def gr_wslice_partition_workspace_bytes(n_vis: int, n_slices: int) -> int:
+    return int(load_library().gr_wslice_partition_workspace_bytes(n_vis, n_slices))
+
+
+def gr_wslice_partition(uvw, vis, weights, n_vis, n_pol, w_first, inv_width, n_slices, uvw_out, vis_out,
+                        weights_out, slice_offsets, workspace, workspace_bytes, stream=None):
+    _check(load_library().gr_wslice_partition(_ptr(uvw), _ptr(vis), _ptr(weights), n_vis, n_pol, w_first,
+                                              inv_width, n_slices, _ptr(uvw_out), _ptr(vis_out),
+                                              _ptr(weights_out), _ptr(slice_offsets), _ptr(workspace),
+                                              workspace_bytes, _stream(stream, uvw, slice_offsets)))
 
 
 def gr_degrid_workspace_bytes(n_vis: int, n_pol: int, support: int, height: int, width: int,

@@ -264,6 +264,52 @@ extern "C" gr_status gr_compress(const void* records, const void* wvis, int64_t 
                          out_count, workspace, (hipStream_t)stream);
 }
 
+extern "C" size_t gr_wslice_partition_workspace_bytes(int64_t n_vis, int32_t n_slices) {
+  if (n_vis < 0 || n_slices < 1 || n_slices > 255) return 0;
+  return wslice_workspace_bytes(n_vis, n_slices);
+}
+
+extern "C" gr_status gr_wslice_partition(const double* uvw, const void* vis, const float* weights, int64_t n_vis,
+                                         int32_t n_pol, double w_first, double inv_width, int32_t n_slices,
+                                         double* uvw_out, void* vis_out, float* weights_out,
+                                         int64_t* slice_offsets, void* workspace, size_t workspace_bytes,
+                                         void* stream) {
+  if (n_pol != 1 && n_pol != 4) return fail(GR_EINVAL, "n_pol must be 1 or 4");
+  if (n_vis < 0 || n_vis > 0x7fffffffLL) return fail(GR_EINVAL, "gr_wslice_partition: n_vis must be in [0, 2^31)");
+  if (n_slices < 1 || n_slices > 255) return fail(GR_EINVAL, "gr_wslice_partition: n_slices must be in [1, 255]");
+  if (!std::isfinite(w_first) || !std::isfinite(inv_width) || inv_width <= 0)
+    return fail(GR_EINVAL, "gr_wslice_partition: w_first must be finite and inv_width finite and > 0");
+  if (slice_offsets == nullptr) return fail(GR_EINVAL, "gr_wslice_partition: slice_offsets is NULL");
+  if (n_vis > 0 && (uvw == nullptr || vis == nullptr || uvw_out == nullptr || vis_out == nullptr))
+    return fail(GR_EINVAL, "gr_wslice_partition: uvw, vis, uvw_out and vis_out must be non-NULL");
+  if (n_vis > 0 && ((weights == nullptr) != (weights_out == nullptr)))
+    return fail(GR_EINVAL, "gr_wslice_partition: weights_out must be given exactly when weights is");
+  if (workspace == nullptr) return fail(GR_EINVAL, "gr_wslice_partition: workspace is NULL");
+  if (workspace_bytes < wslice_workspace_bytes(n_vis, n_slices))
+    return fail(GR_ENOMEM, "gr_wslice_partition: workspace too small (see gr_wslice_partition_workspace_bytes)");
+  // the outputs are written while the inputs are still read: they must not overlap
+  auto overlap = [](const void* a, size_t na, const void* b, size_t nb) {
+    const auto pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+    return na > 0 && nb > 0 && pa < pb + nb && pb < pa + na;
+  };
+  const size_t ub = 3 * sizeof(double) * (size_t)n_vis, vb = sizeof(float2) * (size_t)n_vis * n_pol;
+  const size_t wb = weights ? sizeof(float) * (size_t)n_vis * n_pol : 0;
+  const void* ins[3] = {uvw, vis, weights};
+  const size_t in_b[3] = {ub, vb, wb};
+  const void* outs[3] = {uvw_out, vis_out, weights_out};
+  const size_t out_b[3] = {ub, vb, wb};
+  for (int a = 0; a < 3; ++a) {
+    for (int b = 0; b < 3; ++b)
+      if (n_vis > 0 && overlap(outs[a], out_b[a], ins[b], in_b[b]))
+        return fail(GR_EINVAL, "gr_wslice_partition: outputs must not overlap the inputs");
+    if (n_vis > 0 && overlap(slice_offsets, sizeof(int64_t) * (size_t)(n_slices + 1), ins[a], in_b[a]))
+      return fail(GR_EINVAL, "gr_wslice_partition: slice_offsets must not overlap the inputs");
+  }
+  return launch_wslice_partition(uvw, reinterpret_cast<const float2*>(vis), weights, n_vis, n_pol, w_first,
+                                 inv_width, n_slices, uvw_out, reinterpret_cast<float2*>(vis_out), weights_out,
+                                 slice_offsets, workspace, (hipStream_t)stream);
+}
+
 extern "C" size_t gr_degrid_workspace_bytes(int64_t n_vis, int32_t n_pol, int32_t support, int32_t height,
                                             int32_t width, int32_t seg_len) {
   return gr_preprocess_bin_bytes(n_vis, n_pol, support, height, width, seg_len);

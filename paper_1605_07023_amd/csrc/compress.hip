@@ -64,33 +64,6 @@ head_count_kernel(const Record* __restrict__ rec, int64_t n, int32_t* __restrict
   if (threadIdx.x == 0) block_heads[blockIdx.x] = total;
 }
 
-// one 1024-thread block: exclusive prefix of the block counts in place; the
-// number of runs to *out_count (int64) when it is non-NULL
-__global__ void __launch_bounds__(1024)
-head_scan_kernel(int32_t* __restrict__ block_heads, int n_blocks, int64_t* __restrict__ out_count) {
-  __shared__ int64_t s[1024];
-  const int t = threadIdx.x, T = blockDim.x;
-  const int per = (n_blocks + T - 1) / T;
-  const int a = min(n_blocks, t * per), b = min(n_blocks, a + per);
-  int64_t v = 0;
-  for (int i = a; i < b; ++i) v += block_heads[i];
-  s[t] = v;
-  __syncthreads();
-  for (int off = 1; off < T; off <<= 1) {            // Hillis-Steele inclusive scan
-    const int64_t x = t >= off ? s[t - off] : 0;
-    __syncthreads();
-    s[t] += x;
-    __syncthreads();
-  }
-  int64_t run = s[t] - v;
-  for (int i = a; i < b; ++i) {
-    const int c = block_heads[i];
-    block_heads[i] = (int32_t)run;
-    run += c;
-  }
-  if (t == T - 1 && out_count != nullptr) *out_count = s[T - 1];
-}
-
 template <int P>
 __global__ void __launch_bounds__(kCompressBlock)
 compress_write_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvis, int64_t n,
@@ -125,6 +98,41 @@ __global__ void __launch_bounds__(256) zero_records(Record* __restrict__ p, int6
 
 }  // namespace
 
+namespace {
+
+// one 1024-thread block: exclusive prefix of n int32 counts in place (their
+// total below 2^31); the total to *total (int64) when it is non-NULL
+__global__ void __launch_bounds__(1024)
+scan_i32_kernel(int32_t* __restrict__ data, int n, int64_t* __restrict__ total) {
+  __shared__ int64_t s[1024];
+  const int t = threadIdx.x, T = blockDim.x;
+  const int per = (n + T - 1) / T;
+  const int a = min(n, t * per), b = min(n, a + per);
+  int64_t v = 0;
+  for (int i = a; i < b; ++i) v += data[i];
+  s[t] = v;
+  __syncthreads();
+  for (int off = 1; off < T; off <<= 1) {            // Hillis-Steele inclusive scan
+    const int64_t x = t >= off ? s[t - off] : 0;
+    __syncthreads();
+    s[t] += x;
+    __syncthreads();
+  }
+  int64_t run = s[t] - v;
+  for (int i = a; i < b; ++i) {
+    const int c = data[i];
+    data[i] = (int32_t)run;
+    run += c;
+  }
+  if (t == T - 1 && total != nullptr) *total = s[T - 1];
+}
+
+}  // namespace
+
+void launch_scan_i32(int32_t* data, int n, int64_t* total, hipStream_t stream) {
+  scan_i32_kernel<<<1, 1024, 0, stream>>>(data, n, total);
+}
+
 size_t compress_workspace_bytes(int64_t n_vis) {
   return align256(sizeof(int32_t) * (size_t)((n_vis + kCompressBlock - 1) / kCompressBlock)) + 256;
 }
@@ -138,7 +146,7 @@ gr_status launch_compress(const Record* rec, const float2* wvis, int64_t n_vis, 
     zero_records<<<(unsigned)((n_vis + 255) / 256), 256, 0, stream>>>(out_rec, n_vis);
     head_count_kernel<<<(unsigned)blocks, kCompressBlock, 0, stream>>>(rec, n_vis, block_heads);
   }
-  head_scan_kernel<<<1, 1024, 0, stream>>>(block_heads, (int)blocks, out_count);
+  launch_scan_i32(block_heads, (int)blocks, out_count, stream);
   if (n_vis > 0) {
     using Fn = void (*)(const Record*, const float2*, int64_t, const int32_t*, Record*, float2*);
     const Fn fn = n_pol == 4 ? compress_write_kernel<4> : compress_write_kernel<1>;

@@ -88,6 +88,16 @@ gr_status launch_preprocess_bin(const double* uvw, const void* vis, int vis_dtyp
 size_t compress_workspace_bytes(int64_t n_vis);
 gr_status launch_compress(const Record* rec, const float2* wvis, int64_t n_vis, int n_pol, Record* out_rec,
                           float2* out_wvis, int64_t* out_count, void* workspace, hipStream_t stream);
+// One-block exclusive scan of n int32 counts in place (total < 2^31); the
+// total to *total (device int64) when it is non-NULL.
+void launch_scan_i32(int32_t* data, int n, int64_t* total, hipStream_t stream);
+// W-stacking's split (wstack.hip): stable partition of (uvw, vis, weights) by
+// w slice; slice_offsets [n_slices + 1] (device int64).
+size_t wslice_workspace_bytes(int64_t n_vis, int n_slices);
+gr_status launch_wslice_partition(const double* uvw, const float2* vis, const float* wts, int64_t n_vis, int n_pol,
+                                  double w_first, double inv_width, int n_slices, double* uvw_out,
+                                  float2* vis_out, float* wts_out, int64_t* slice_offsets, void* workspace,
+                                  hipStream_t stream);
 // Degridding's binning: records (rec_tmp) and tile counts from uvw, scan,
 // then kept records and their input indices (int32, in the wvis slot of the
 // layout) to the binned positions.

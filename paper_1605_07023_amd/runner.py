@@ -177,3 +177,79 @@ class BatchGraph:
             self.close()
         except Exception:
             pass
+
+
+def slice_w_min(w_first: float, inv_width: float, s: int, w_min_rel: float) -> float:
+    """w_min of slice s's kernel: the slice centre w_first + (s + 1/2) / inv_width
+    plus the w_min of the residual-w table (planes relative to the centre)."""
+    return w_first + (s + 0.5) / inv_width + w_min_rel
+
+
+def wslice_partition(dw: DeviceWorkload, w_first: float, inv_width: float, n_slices: int,
+                     workspace: Optional[torch.Tensor] = None, stream=None):
+    """gr_wslice_partition of a device workload into fresh buffers: returns
+    (uvw, vis, weights or None, slice_offsets device int64 [n_slices + 1])."""
+    if dw.vis_dtype != B.GR_F32:
+        raise ValueError("gr_wslice_partition takes complex64 visibilities")
+    wl = dw.wl
+    dev = dw.uvw.device
+    uvw_p = torch.empty_like(dw.uvw)
+    vis_p = torch.empty_like(dw.vis)
+    w_p = None if dw.weights is None else torch.empty_like(dw.weights)
+    offs = torch.empty(n_slices + 1, dtype=torch.int64, device=dev)
+    need = B.gr_wslice_partition_workspace_bytes(wl.n_vis, n_slices)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    B.gr_wslice_partition(dw.uvw, dw.vis, dw.weights, wl.n_vis, wl.n_pol, w_first, inv_width, n_slices,
+                          uvw_p, vis_p, w_p, offs, workspace, workspace.numel(), stream)
+    return uvw_p, vis_p, w_p, offs
+
+
+def slice_kernel(k: B.GrKernel, w_min: float) -> B.GrKernel:
+    """The same tap table with another w_min."""
+    return B.GrKernel(k.kind, k.tap_dtype, k.taps_complex, k.support, k.oversample, k.n_planes,
+                      w_min, k.inv_dw, k.taps)
+
+
+def grid_wstack(dw: DeviceWorkload, w_first: float, inv_width: float, n_slices: int,
+                grids: Optional[torch.Tensor] = None, mode: str = "batch", stream=None):
+    """W-stacking: partition by w slice (gr_wslice_partition), then grid each
+    slice into its own grid with dw.kernel's table, whose w_min is taken as
+    relative to the slice centre (slice_w_min).  mode "batch": one
+    gr_grid_batch over the slices; "per_slice": one gr_grid per slice.  The
+    slice offsets are copied to the host (one synchronisation) to form the
+    calls.  Returns (grids complex64 [n_slices][P][H][W], host offsets)."""
+    wl = dw.wl
+    dev = dw.uvw.device
+    if grids is None:
+        grids = torch.zeros((n_slices, wl.n_pol, wl.height, wl.width), dtype=torch.complex64, device=dev)
+    uvw_p, vis_p, w_p, offs = wslice_partition(dw, w_first, inv_width, n_slices, stream=stream)
+    off = offs.cpu().numpy()
+    k = dw.kernel
+    if mode == "batch":
+        items = []
+        for s in range(n_slices):
+            a, b = int(off[s]), int(off[s + 1])
+            items.append(B.make_batch_item(uvw_p[a:], vis_p[a:], B.GR_F32, wl.n_pol, None,
+                                           None if w_p is None else w_p[a:], b - a,
+                                           slice_kernel(k, slice_w_min(w_first, inv_width, s, k.w_min)),
+                                           wl.inv_cell_u, wl.inv_cell_v, grids[s], wl.height, wl.width))
+        need = B.gr_grid_batch_workspace_bytes(items)
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+        B.gr_grid_batch(items, ws, ws.numel(), stream)
+    elif mode == "per_slice":
+        ws = None
+        for s in range(n_slices):
+            a, b = int(off[s]), int(off[s + 1])
+            if b == a:
+                continue
+            ks = slice_kernel(k, slice_w_min(w_first, inv_width, s, k.w_min))
+            need = B.gr_grid_workspace_bytes(b - a, wl.n_pol, ks, wl.height, wl.width, None)
+            if ws is None or ws.numel() < need:
+                ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+            B.gr_grid(uvw_p[a:], vis_p[a:], B.GR_F32, None, None if w_p is None else w_p[a:], b - a, wl.n_pol,
+                      ks, wl.inv_cell_u, wl.inv_cell_v, grids[s], wl.height, wl.width, None, ws, ws.numel(),
+                      None, stream)
+    else:
+        raise ValueError(f"unknown mode {mode}")
+    return grids, off

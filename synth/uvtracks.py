@@ -340,3 +340,23 @@ def compression_workload(seed: int = 0, n_baselines: Optional[int] = None, n_pol
     return Workload(f"compress-E1-{grid}", flat, vis, None, grid, grid, support, 8, s, s,
                     n_planes=n_planes, w_min=w_min, inv_dw=inv_dw, w_hat_scale=whs, kernel="wsep",
                     beta=8.6, support_aa=8)
+
+
+def wstack_workload(seed: int = 0, n_baselines: Optional[int] = None, n_pol: int = 4, grid: int = 2048,
+                    support: int = 16, n_slices: int = 7, planes_per_slice: int = 32) -> Workload:
+    """Stand-in for the paper's W-stacked runs (Section 5: the 2 h, 2 s-dump
+    set split by w into 7 slices, each gridded on its own): the tracks and
+    visibilities of :func:`compression_workload`.  ``meta`` holds the slicing:
+    ``n_slices`` equal slices from ``w_first`` of width 1 / ``inv_width``
+    spanning [-max|w|, +max|w|] of the whole array (padded by 2^-20 so that the
+    extreme w falls inside).  ``n_planes`` / ``w_min`` / ``inv_dw`` describe
+    one table for every slice, its planes spread over
+    [-width/2, +width/2] about a slice's centre (``w_min`` relative to it)."""
+    wl = compression_workload(seed, n_baselines, n_pol, grid, support, planes_per_slice)
+    full = _compression_extent(seed)
+    half = float(np.max(np.abs(full[:, 2]))) * (1.0 + 2.0 ** -20)
+    width = 2.0 * half / n_slices
+    return dataclasses.replace(
+        wl, name=f"wstack{n_slices}-{grid}", n_planes=planes_per_slice, w_min=-0.5 * width,
+        inv_dw=(planes_per_slice - 1) / width,
+        meta=dict(n_slices=n_slices, w_first=-half, inv_width=n_slices / (2.0 * half)))

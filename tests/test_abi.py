@@ -187,6 +187,47 @@ def test_compress_rejects(lib):
     assert st == B.GR_EINVAL and "n_pol" in lib.gr_last_error().decode()
 
 
+def test_wslice_partition_rejects(lib):
+    """Host-side validation of gr_wslice_partition, before anything is enqueued."""
+    from paper_1605_07023_amd import binding as B
+    nw = B.gr_wslice_partition_workspace_bytes(1000, 7)
+    assert nw >= 4 * 8 * 4 and B.gr_wslice_partition_workspace_bytes(-1, 7) == 0
+    assert B.gr_wslice_partition_workspace_bytes(10, 0) == 0 and B.gr_wslice_partition_workspace_bytes(10, 256) == 0
+    u, v, w, uo, vo, wo, off, ws = (1 << k for k in (20, 24, 28, 32, 36, 40, 44, 46))
+
+    def call(**kw):
+        a = dict(uvw=u, vis=v, weights=w, n=1000, n_pol=4, w_first=-10.0, inv_width=0.1, n_slices=7,
+                 uvw_out=uo, vis_out=vo, weights_out=wo, offsets=off, ws=ws, ws_bytes=nw)
+        a.update(kw)
+        st = lib.gr_wslice_partition(a["uvw"], a["vis"], a["weights"], a["n"], a["n_pol"], a["w_first"],
+                                     a["inv_width"], a["n_slices"], a["uvw_out"], a["vis_out"],
+                                     a["weights_out"], a["offsets"], a["ws"], a["ws_bytes"], None)
+        return st, lib.gr_last_error().decode()
+
+    st, msg = call(ws_bytes=nw - 1)
+    assert st == B.GR_ENOMEM and "gr_wslice_partition_workspace_bytes" in msg
+    st, msg = call(n_slices=0)
+    assert st == B.GR_EINVAL and "n_slices" in msg
+    st, msg = call(n_slices=256)
+    assert st == B.GR_EINVAL and "n_slices" in msg
+    st, msg = call(inv_width=0.0)
+    assert st == B.GR_EINVAL and "inv_width" in msg
+    st, msg = call(w_first=float("nan"))
+    assert st == B.GR_EINVAL and "w_first" in msg
+    st, msg = call(weights_out=None)
+    assert st == B.GR_EINVAL and "weights_out" in msg
+    st, msg = call(vis_out=u + 8)                                     # vis_out overlaps uvw
+    assert st == B.GR_EINVAL and "overlap" in msg
+    st, msg = call(offsets=v + 16)                                    # slice_offsets inside vis
+    assert st == B.GR_EINVAL and "overlap" in msg
+    st, msg = call(offsets=None)
+    assert st == B.GR_EINVAL and "slice_offsets" in msg
+    st, msg = call(n_pol=2)
+    assert st == B.GR_EINVAL and "n_pol" in msg
+    st, msg = call(n=-1)
+    assert st == B.GR_EINVAL and "n_vis" in msg
+
+
 def test_table_generators_reject(lib):
     from paper_1605_07023_amd import binding as B
     assert lib.gr_make_kb_table(8.6, 7, 8, B.GR_F32, 1 << 20, None) == B.GR_EINVAL
