@@ -295,6 +295,61 @@ def wstack_leg(dev, stream, reps: int) -> dict:
     return out
 
 
+def aterm_leg(dev, stream, reps: int) -> dict:
+    """Gridding with non-separable GCFs that change per visibility and per
+    polarisation (Section 6, A-projection) on the full-shape tracks: 16 GCF ids
+    (8 time intervals x 2 channel groups), 4 w planes, oversampling 8, one
+    synthetic complex GCF per (id, plane, phase, polarisation), quad pol,
+    4096^2, S=16 and S=32.  Times whole gr_grid_aterm calls (fused preprocess
+    and binning, the register-window gridder); HIP events on the stream, median
+    of ``reps`` after one untimed call."""
+    import numpy as np
+    import torch
+    from paper_1605_07023_amd import binding as B, runner
+    from synth import aterm_taps, aterm_workload
+    out = {"workload": "full-shape tracks (33,030,144 vis, quad pol, 4096^2), 16 GCF ids (8 time intervals x "
+                       "2 channel groups), 4 w planes, oversampling 8, synthetic complex GCFs per polarisation, "
+                       "FP32 taps (67 MB table at S=16, 268 MB at S=32)", "per_support": {}}
+    for S in (16, 32):
+        wl = aterm_workload(S)
+        n_ids = wl.meta["n_ids"]
+        taps = aterm_taps(0, n_ids, wl.n_planes, wl.oversample, wl.n_pol, S)
+        t_dev = torch.from_numpy(np.ascontiguousarray(taps).view(np.float32)).to(dev)
+        del taps
+        dw = runner.upload(wl, dev, taps=t_dev)
+        dw.kernel = B.make_kernel(t_dev, S, wl.oversample, wl.n_planes, taps_complex=True, w_min=wl.w_min,
+                                  inv_dw=wl.inv_dw, kind=B.GR_TABLE2D)
+        ids = torch.from_numpy(wl.meta["kernel_id"]).to(dev)
+        g = torch.zeros((wl.n_pol, wl.height, wl.width), dtype=torch.complex64, device=dev)
+        need = B.gr_grid_aterm_workspace_bytes(wl.n_vis, wl.n_pol, S, wl.height, wl.width)
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        st = torch.zeros(2, dtype=torch.int64, device=dev)
+
+        def call():
+            B.gr_grid_aterm(dw.uvw, dw.vis, B.GR_F32, None, None, ids, n_ids, wl.n_vis, wl.n_pol, dw.kernel,
+                            wl.inv_cell_u, wl.inv_cell_v, g, wl.height, wl.width, ws, need, st, stream)
+
+        call()
+        torch.cuda.synchronize()
+        kept = int(st[0].item())
+        ms = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            call()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        t = sorted(ms)[len(ms) // 2]
+        upd = kept * wl.n_pol * S * S
+        log(f"A-term leg S={S}: {t:.2f} ms per call, {upd / (t * 1e-3):.3e} updates/s")
+        out["per_support"][str(S)] = {"n_vis": wl.n_vis, "kept": kept, "call_ms": t,
+                                      "updates_per_s": upd / (t * 1e-3), "tap_GB_per_s": upd * 8 / (t * 1e-3) / 1e9}
+        del g, ws, dw, t_dev, ids
+        torch.cuda.empty_cache()
+    return out
+
+
 def degrid_leg(dev, uvw, wl, kern, grid, stream, reps: int) -> dict:
     """gr_degrid (the adjoint operation, predicting every visibility from the grid)
     on the full-shape S=32 visibilities and the grid the timed steps produced:
@@ -357,6 +412,8 @@ def main() -> int:
                     help="skip the compression leg (2 s-dump tracks, after the timed region)")
     ap.add_argument("--no-wstack", action="store_true",
                     help="skip the w-stacking leg (7 w slices of the 2 s-dump tracks, after the timed region)")
+    ap.add_argument("--no-aterm", action="store_true",
+                    help="skip the A-term leg (per-visibility non-separable GCFs, after the timed region)")
     ap.add_argument("--no-degrid", action="store_true",
                     help="skip the degridding leg (gr_degrid of the S=32 grid, after the timed region)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -532,6 +589,11 @@ def main() -> int:
         log("w-stacking leg")
         wstack = wstack_leg(dev, stream, reps=5)
 
+    aterm = None
+    if not args.no_aterm and variant == 2 and args.precision == "f32":
+        log("A-term leg")
+        aterm = aterm_leg(dev, stream, reps=3)
+
     cpu = None
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
@@ -557,6 +619,7 @@ def main() -> int:
         "degrid": degrid,
         "compression": compression,
         "wstack": wstack,
+        "aterm": aterm,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

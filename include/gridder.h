@@ -226,6 +226,33 @@ gr_status gr_wslice_partition(const double* uvw, const void* vis, const float* w
                               double* uvw_out, void* vis_out, float* weights_out, int64_t* slice_offsets,
                               void* workspace, size_t workspace_bytes, void* stream);
 
+/* Gridding with non-separable GCFs that change per visibility and per
+ * polarisation, as A-projection's do (Section 6: they depend on time,
+ * frequency, polarisation and possibly baseline and are not separable; the
+ * paper expects their loads to dominate).  Each visibility n carries a GCF id
+ * kernel_id[n] (device int32 [n_vis]; for instance its time and frequency
+ * interval); with the indices of gr_preprocess,
+ *   grid[p][y0+ky][x0+kx] += w[n][p] V[n][p] T[kernel_id[n]][plane][sy][sx][p][ky][kx]
+ * where `kernel` is a GR_TABLE2D descriptor (complex taps, FP32/FP16/BF16,
+ * support <= 56) whose table holds n_ids x n_planes x O x O x n_pol x S x S
+ * complex values in that order (polarisation-dependent; each correlation
+ * has its own GCF, no mixing between them), n_ids x n_planes <= 32767.  A
+ * visibility whose id falls outside [0, n_ids) is dropped and counted like
+ * one off the grid.  uvw, vis, vis_dtype, vis_scale, weights, dev_stats, grid
+ * (accumulated, +=) as gr_grid.  The visibilities are preprocessed and binned
+ * in one pass pair for windows of 32, 48 or 64 cells (S <= 16, <= 32, else),
+ * then one 256-work-item block per segment keeps its window in registers
+ * (C x C cells x n_pol per work-item, C = window / 16) and adds it to the grid
+ * once with atomic adds.
+ * workspace: gr_grid_aterm_workspace_bytes. */
+size_t gr_grid_aterm_workspace_bytes(int64_t n_vis, int32_t n_pol, int32_t support, int32_t height,
+                                     int32_t width);
+gr_status gr_grid_aterm(const double* uvw, const void* vis, int32_t vis_dtype, const float* vis_scale,
+                        const float* weights, const int32_t* kernel_id, int32_t n_ids, int64_t n_vis,
+                        int32_t n_pol, const gr_kernel* kernel, double inv_cell_u, double inv_cell_v,
+                        void* grid, int32_t height, int32_t width, void* workspace, size_t workspace_bytes,
+                        int64_t* dev_stats, void* stream);
+
 /* Degridding, the adjoint of gridding (Section 6 names degridding with thread
  * coarsening as the next step): predicts every visibility from the grid
  * through the same separable GCF,

@@ -428,6 +428,45 @@ def grid_wstack(vis: np.ndarray, uvw: np.ndarray, weights: Optional[np.ndarray],
     return grids, dropped, int(order.size - offsets[n_slices])
 
 
+def grid_aterm(vis: np.ndarray, uvw: np.ndarray, weights: Optional[np.ndarray], kernel_id: np.ndarray,
+               taps: np.ndarray, inv_cell_u: float, inv_cell_v: float, oversample: int, height: int,
+               width: int, n_planes: int, w_min: float, inv_dw: float, chunk: int = 1024):
+    """Non-separable GCFs per visibility and per polarisation (Section 6: the
+    A-projection GCFs depend on time, frequency, polarisation and possibly
+    baseline, and are not separable):
+        grid[p, y0+ky, x0+kx] += w[n,p] V[n,p] T[id[n], plane, sy, sx, p, ky, kx]
+    with ``taps`` complex [n_ids][planes][O][O][P][S][S] and the indices of
+    :func:`pixel_coords`.
+
+    Readings (paper silent): each polarisation has its own GCF and none mixes
+    polarisations (the diagonal of the Mueller matrix); a visibility whose id
+    lies outside [0, n_ids) is dropped and counted like one off the grid.
+    Returns (grid complex128 [P][H][W], n_dropped)."""
+    taps = np.asarray(taps)
+    n_ids, support = taps.shape[0], taps.shape[-1]
+    vis = np.asarray(vis)
+    n_pol = vis.shape[1]
+    pc = pixel_coords(uvw, inv_cell_u, inv_cell_v, oversample, support, height, width, n_planes, w_min, inv_dw)
+    ids = np.asarray(kernel_id, dtype=np.int64)
+    valid = pc["valid"] & finite_values(vis, weights) & (ids >= 0) & (ids < n_ids)
+    wv = weighted_vis(vis, weights)
+    out = np.zeros((n_pol, height, width), np.complex128)
+    flat = out.reshape(n_pol, -1)
+    idx = np.nonzero(valid)[0]
+    k = np.arange(support)
+    for c0 in range(0, idx.size, chunk):
+        sel = idx[c0:c0 + chunk]
+        kern = taps[ids[sel], pc["plane"][sel], pc["sy"][sel], pc["sx"][sel]].astype(np.complex128)  # [n][P][S][S]
+        rows = pc["y0"][sel][:, None] + k[None, :]
+        cols = pc["x0"][sel][:, None] + k[None, :]
+        cell = (rows[:, :, None] * width + cols[:, None, :]).ravel()
+        for p in range(n_pol):
+            contrib = (kern[:, p] * wv[sel, p][:, None, None]).ravel()
+            flat[p] += np.bincount(cell, weights=contrib.real, minlength=height * width) \
+                + 1j * np.bincount(cell, weights=contrib.imag, minlength=height * width)
+    return out, int(np.count_nonzero(~valid))
+
+
 def grid_table2d(vis: np.ndarray, uvw: np.ndarray, weights: Optional[np.ndarray],
                  taps2d: np.ndarray, inv_cell_u: float, inv_cell_v: float, oversample: int,
                  height: int, width: int, n_planes: int, w_min: float, inv_dw: float,

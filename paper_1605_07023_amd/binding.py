@@ -77,6 +77,7 @@ def load_library():
         "gr_degrid": [P, I64, I32, KP, D, D, P, I32, I32, P, I32, P, SZ, P, P],
         "gr_compress": [P, P, I64, I32, P, P, P, P, SZ, P],
         "gr_wslice_partition": [P, P, P, I64, I32, D, D, I32, P, P, P, P, P, SZ, P],
+        "gr_grid_aterm": [P, P, I32, P, P, P, I32, I64, I32, KP, D, D, P, I32, I32, P, SZ, P, P],
         "gr_grid_binned": [P, I64, I32, KP, I32, P, I32, I32, P],
         "gr_autotune": [P, P, I64, I32, KP, P, I32, I32, P, SZ, TP, I32, I32, P, P, P],
         "gr_make_wkernel2d_table": [I32, I32, I32, D, D, D, I32, D, I32, I32, P, P],
@@ -101,6 +102,8 @@ def load_library():
     lib.gr_compress_workspace_bytes.restype = SZ
     lib.gr_wslice_partition_workspace_bytes.argtypes = [I64, I32]
     lib.gr_wslice_partition_workspace_bytes.restype = SZ
+    lib.gr_grid_aterm_workspace_bytes.argtypes = [I64, I32, I32, I32, I32]
+    lib.gr_grid_aterm_workspace_bytes.restype = SZ
     lib.gr_last_error.argtypes = []
     lib.gr_last_error.restype = ctypes.c_char_p
     lib.gr_grid_batch.argtypes = [ctypes.POINTER(GrBatchItem), I32, P, SZ, P]
@@ -200,6 +203,19 @@ def gr_wslice_partition(uvw, vis, weights, n_vis, n_pol, w_first, inv_width, n_s
                                               inv_width, n_slices, _ptr(uvw_out), _ptr(vis_out),
                                               _ptr(weights_out), _ptr(slice_offsets), _ptr(workspace),
                                               workspace_bytes, _stream(stream, uvw, slice_offsets)))
+
+
+def gr_grid_aterm_workspace_bytes(n_vis: int, n_pol: int, support: int, height: int, width: int) -> int:
+    return int(load_library().gr_grid_aterm_workspace_bytes(n_vis, n_pol, support, height, width))
+
+
+def gr_grid_aterm(uvw, vis, vis_dtype, vis_scale, weights, kernel_id, n_ids, n_vis, n_pol, kernel: GrKernel,
+                  inv_cell_u, inv_cell_v, grid, height, width, workspace, workspace_bytes, dev_stats=None,
+                  stream=None):
+    _check(load_library().gr_grid_aterm(_ptr(uvw), _ptr(vis), vis_dtype, _ptr(vis_scale), _ptr(weights),
+                                        _ptr(kernel_id), n_ids, n_vis, n_pol, ctypes.byref(kernel), inv_cell_u,
+                                        inv_cell_v, _ptr(grid), height, width, _ptr(workspace), workspace_bytes,
+                                        _ptr(dev_stats), _stream(stream, grid, uvw)))
 
 
 def gr_degrid_workspace_bytes(n_vis: int, n_pol: int, support: int, height: int, width: int,

@@ -310,6 +310,45 @@ extern "C" gr_status gr_wslice_partition(const double* uvw, const void* vis, con
                                  slice_offsets, workspace, (hipStream_t)stream);
 }
 
+extern "C" size_t gr_grid_aterm_workspace_bytes(int64_t n_vis, int32_t n_pol, int32_t support, int32_t height,
+                                                int32_t width) {
+  if (n_vis < 0 || n_pol < 1 || support < 2 || support > 56 || height < 1 || width < 1) return 0;
+  return bin_layout(n_vis, n_pol, support, height, width, kDefaultSegLen, aterm_window(support)).bytes +
+         align256(sizeof(Record) * (size_t)n_vis);
+}
+
+extern "C" gr_status gr_grid_aterm(const double* uvw, const void* vis, int32_t vis_dtype, const float* vis_scale,
+                                   const float* weights, const int32_t* kernel_id, int32_t n_ids, int64_t n_vis,
+                                   int32_t n_pol, const gr_kernel* kernel, double inv_cell_u, double inv_cell_v,
+                                   void* grid, int32_t height, int32_t width, void* workspace,
+                                   size_t workspace_bytes, int64_t* dev_stats, void* stream) {
+  gr_status st = validate_raw_inputs("gr_grid_aterm", uvw, vis, vis_dtype, vis_scale, n_vis, n_pol, kernel,
+                                     inv_cell_u, inv_cell_v, height, width);
+  if (st != GR_OK) return st;
+  if ((st = validate_kernel(kernel, true)) != GR_OK) return st;
+  if (kernel->kind != GR_TABLE2D)
+    return fail(GR_EUNSUPPORTED, "gr_grid_aterm takes a GR_TABLE2D kernel (taps [n_ids][planes][O][O][n_pol][S][S])");
+  if (kernel->support > 56) return fail(GR_EUNSUPPORTED, "gr_grid_aterm: support must be <= 56");
+  if (n_ids < 1 || (int64_t)n_ids * kernel->n_planes > kMaxPlanes)
+    return fail(GR_EINVAL, "gr_grid_aterm: n_ids must be >= 1 with n_ids x n_planes <= 32767");
+  if (n_vis > 0x7fffffffLL) return fail(GR_EINVAL, "gr_grid_aterm: n_vis must be in [0, 2^31)");
+  if (n_vis > 0 && kernel_id == nullptr) return fail(GR_EINVAL, "gr_grid_aterm: kernel_id is NULL");
+  if (grid == nullptr) return fail(GR_EINVAL, "grid is NULL");
+  const BinLayout L = bin_layout(n_vis, n_pol, kernel->support, height, width, kDefaultSegLen,
+                                 aterm_window(kernel->support));
+  const size_t need = L.bytes + align256(sizeof(Record) * (size_t)n_vis);
+  if (workspace == nullptr) return fail(GR_EINVAL, "gr_grid_aterm: workspace is NULL");
+  if (workspace_bytes < need)
+    return fail(GR_ENOMEM, "gr_grid_aterm: workspace too small (see gr_grid_aterm_workspace_bytes)");
+  auto* rec_tmp = reinterpret_cast<Record*>(reinterpret_cast<char*>(workspace) + L.bytes);
+  if ((st = launch_preprocess_bin(uvw, vis, vis_dtype, vis_scale, weights, n_vis, n_pol, *kernel, inv_cell_u,
+                                  inv_cell_v, height, width, L, workspace, rec_tmp, dev_stats, (hipStream_t)stream,
+                                  kernel_id, n_ids)) != GR_OK)
+    return st;
+  return launch_aterm(workspace, L, n_pol, *kernel, reinterpret_cast<float2*>(grid), height, width,
+                      (hipStream_t)stream);
+}
+
 extern "C" size_t gr_degrid_workspace_bytes(int64_t n_vis, int32_t n_pol, int32_t support, int32_t height,
                                             int32_t width, int32_t seg_len) {
   return gr_preprocess_bin_bytes(n_vis, n_pol, support, height, width, seg_len);

@@ -417,7 +417,8 @@ void launch_scan(const int32_t* count, const BinLayout& L, char* base, hipStream
 gr_status launch_preprocess_bin(const double* uvw, const void* vis, int vis_dtype, const float* vis_scale,
                                 const float* weights, int64_t n_vis, int n_pol, const gr_kernel& k,
                                 double inv_cell_u, double inv_cell_v, int height, int width, const BinLayout& L,
-                                void* bins, Record* rec_tmp, int64_t* dev_stats, hipStream_t stream) {
+                                void* bins, Record* rec_tmp, int64_t* dev_stats, hipStream_t stream,
+                                const int32_t* ids, int n_ids) {
   char* base = reinterpret_cast<char*>(bins);
   auto* count = reinterpret_cast<int32_t*>(base + L.off_count);
   auto* cursor = reinterpret_cast<int32_t*>(base + L.off_cursor);
@@ -430,8 +431,10 @@ gr_status launch_preprocess_bin(const double* uvw, const void* vis, int vis_dtyp
   fill_i32<<<(unsigned)((L.n_tiles + 255) / 256), 256, 0, stream>>>(count, L.n_tiles, 0);
   fill_i32<<<1, 256, 0, stream>>>(nsegs, 1, 0);
   auto* st = reinterpret_cast<unsigned long long*>(dev_stats);
-  const prep::PreArgs a = prep::make_pre_args(uvw, vis, vis_scale, weights, n_vis, n_pol, k, inv_cell_u,
-                                              inv_cell_v, height, width, rec_tmp, nullptr);
+  prep::PreArgs a = prep::make_pre_args(uvw, vis, vis_scale, weights, n_vis, n_pol, k, inv_cell_u, inv_cell_v,
+                                        height, width, rec_tmp, nullptr);
+  a.ids = ids;
+  a.n_ids = n_ids;
   if (n_vis > 0) {
     const int64_t cblocks = std::min<int64_t>(blocks, (int64_t)prep::device_cu_count() * 16);
     prebin_count_kernel<<<(unsigned)cblocks, 256, 0, stream>>>(a, L.tile, L.n_tx, count, st);

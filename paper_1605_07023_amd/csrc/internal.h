@@ -81,7 +81,14 @@ BinLayout bin_layout(int64_t n_vis, int n_pol, int support, int height, int widt
 gr_status launch_preprocess_bin(const double* uvw, const void* vis, int vis_dtype, const float* vis_scale,
                                 const float* weights, int64_t n_vis, int n_pol, const gr_kernel& k,
                                 double inv_cell_u, double inv_cell_v, int height, int width, const BinLayout& L,
-                                void* bins, Record* rec_tmp, int64_t* dev_stats, hipStream_t stream);
+                                void* bins, Record* rec_tmp, int64_t* dev_stats, hipStream_t stream,
+                                const int32_t* ids = nullptr, int n_ids = 0);
+// Gridding with per-visibility, per-polarisation non-separable GCFs over a
+// binned stream whose records carry id * n_planes + plane (aterm.hip).
+gr_status launch_aterm(const void* bins, const BinLayout& L, int n_pol, const gr_kernel& k, float2* grid,
+                       int height, int width, hipStream_t stream);
+// the window (cells) that gr_grid_aterm bins for: 32, 48 or 64
+int aterm_window(int support);
 // Compression of a preprocessed stream (compress.hip): runs of consecutive kept
 // visibilities with equal records summed into one; out_rec padded with invalid
 // records to n_vis; the number of runs to *out_count (device, may be NULL).

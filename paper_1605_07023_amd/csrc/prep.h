@@ -41,6 +41,10 @@ struct PreArgs {
   double w_min, inv_dw;
   Record* rec;
   float2* wvis;
+  // per-visibility GCF ids (NULL: none): the record's plane field then holds
+  // id * n_planes + plane, and an id outside [0, n_ids) drops the visibility
+  const int32_t* ids = nullptr;
+  int n_ids = 0;
 };
 
 // Record of visibility i (< a.n) from its coordinates alone: the drop rule's
@@ -67,6 +71,11 @@ __device__ __forceinline__ Record coord_record(int64_t i, const PreArgs& a) {
   }
   ok = ok && plane >= 0 && plane < a.n_planes && x0 >= 0 && x0 + a.S <= a.W && y0 >= 0 &&
        y0 + a.S <= a.H;
+  if (a.ids != nullptr) {
+    const int id = a.ids[i];
+    ok = ok && id >= 0 && id < a.n_ids;
+    plane += (int64_t)(ok ? id : 0) * a.n_planes;
+  }
   Record r{0, 0};
   if (ok) {
     r.x = (uint32_t)x0 | ((uint32_t)y0 << 16);

@@ -253,3 +253,20 @@ def grid_wstack(dw: DeviceWorkload, w_first: float, inv_width: float, n_slices: 
     else:
         raise ValueError(f"unknown mode {mode}")
     return grids, off
+
+
+def grid_aterm(dw: DeviceWorkload, kernel_id: torch.Tensor, n_ids: int, grid_out: Optional[torch.Tensor] = None,
+               workspace: Optional[torch.Tensor] = None, stats: Optional[torch.Tensor] = None, stream=None):
+    """gr_grid_aterm of a device workload whose kernel is a GR_TABLE2D descriptor of the
+    per-id, per-polarisation table; kernel_id: device int32 [N].  Returns the grid."""
+    wl = dw.wl
+    dev = dw.uvw.device
+    if grid_out is None:
+        grid_out = torch.zeros((wl.n_pol, wl.height, wl.width), dtype=torch.complex64, device=dev)
+    need = B.gr_grid_aterm_workspace_bytes(wl.n_vis, wl.n_pol, wl.support, wl.height, wl.width)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    B.gr_grid_aterm(dw.uvw, dw.vis, dw.vis_dtype, dw.vis_scale, dw.weights, kernel_id, n_ids, wl.n_vis, wl.n_pol,
+                    dw.kernel, wl.inv_cell_u, wl.inv_cell_v, grid_out, wl.height, wl.width, workspace,
+                    workspace.numel(), stats, stream)
+    return grid_out

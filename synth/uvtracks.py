@@ -360,3 +360,32 @@ def wstack_workload(seed: int = 0, n_baselines: Optional[int] = None, n_pol: int
         wl, name=f"wstack{n_slices}-{grid}", n_planes=planes_per_slice, w_min=-0.5 * width,
         inv_dw=(planes_per_slice - 1) / width,
         meta=dict(n_slices=n_slices, w_first=-half, inv_width=n_slices / (2.0 * half)))
+
+
+def aterm_workload(support: int, seed: int = 0, n_baselines: Optional[int] = None, n_times: int = 1024,
+                   n_chan: int = 16, grid: int = 4096, n_planes: int = 4, n_pol: int = 4, time_slots: int = 8,
+                   freq_groups: int = 2) -> Workload:
+    """The tracks of :func:`full_shape_workload` (baseline, time, channel
+    order) with a GCF id per visibility, as A-projection assigns GCFs by time
+    and frequency (Section 6): ``time_slots`` equal intervals of the dumps
+    times ``freq_groups`` equal groups of the channels.  ``meta`` holds
+    ``kernel_id`` (int32 [N]) and ``n_ids``; the GCF values come from
+    :func:`aterm_taps`."""
+    wl = full_shape_workload(support, seed, n_baselines, n_times, n_chan, grid, n_planes, n_pol)
+    n = np.arange(wl.n_vis, dtype=np.int64)
+    t = (n // n_chan) % n_times
+    c = n % n_chan
+    ids = ((t * time_slots) // n_times) * freq_groups + (c * freq_groups) // n_chan
+    return dataclasses.replace(wl, name=f"aterm-S{support}", kernel="aterm",
+                               meta=dict(kernel_id=ids.astype(np.int32), n_ids=time_slots * freq_groups))
+
+
+def aterm_taps(seed: int, n_ids: int, n_planes: int, oversample: int, n_pol: int, support: int) -> np.ndarray:
+    """Synthetic GCF table complex64 [n_ids][planes][O][O][P][S][S] (there are
+    no beam models here): real and imaginary parts i.i.d. N(0, 1/S^2)."""
+    rng = np.random.default_rng(seed)
+    shape = (n_ids, n_planes, oversample, oversample, n_pol, support, support)
+    out = np.empty(shape, dtype=np.complex64)
+    rng.standard_normal(out=out.view(np.float32), dtype=np.float32)
+    out *= np.float32(1.0 / support)
+    return out

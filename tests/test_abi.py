@@ -228,6 +228,35 @@ def test_wslice_partition_rejects(lib):
     assert st == B.GR_EINVAL and "n_vis" in msg
 
 
+def test_grid_aterm_rejects(lib):
+    """Host-side validation of gr_grid_aterm, before anything is enqueued."""
+    import ctypes
+    from paper_1605_07023_amd import binding as B
+    nw = B.gr_grid_aterm_workspace_bytes(1000, 4, 16, 512, 512)
+    assert nw > 0 and B.gr_grid_aterm_workspace_bytes(-1, 4, 16, 512, 512) == 0
+    assert B.gr_grid_aterm_workspace_bytes(10, 4, 64, 512, 512) == 0
+    k = B.make_kernel(1 << 40, 16, 8, 4, taps_complex=True, w_min=-1.0, inv_dw=1.5, kind=B.GR_TABLE2D)
+
+    def call(kern=k, ids=1 << 30, n_ids=16, n=1000, ws_bytes=nw, grid=1 << 34):
+        st = lib.gr_grid_aterm(1 << 20, 1 << 24, B.GR_F32, None, None, ids, n_ids, n, 4, ctypes.byref(kern), 1.0,
+                               1.0, grid, 512, 512, 1 << 36, ws_bytes, None, None)
+        return st, lib.gr_last_error().decode()
+
+    st, msg = call(ws_bytes=nw - 1)
+    assert st == B.GR_ENOMEM and "gr_grid_aterm_workspace_bytes" in msg
+    st, msg = call(ids=None)
+    assert st == B.GR_EINVAL and "kernel_id" in msg
+    st, msg = call(n_ids=0)
+    assert st == B.GR_EINVAL and "n_ids" in msg
+    st, msg = call(n_ids=8192)                                   # 8192 x 4 planes > 32767
+    assert st == B.GR_EINVAL and "n_ids" in msg
+    sep = B.make_kernel(1 << 40, 16, 8, 4, taps_complex=True, w_min=-1.0, inv_dw=1.5)
+    st, msg = call(kern=sep)
+    assert st == B.GR_EUNSUPPORTED and "GR_TABLE2D" in msg
+    st, msg = call(grid=None)
+    assert st == B.GR_EINVAL and "grid" in msg
+
+
 def test_table_generators_reject(lib):
     from paper_1605_07023_amd import binding as B
     assert lib.gr_make_kb_table(8.6, 7, 8, B.GR_F32, 1 << 20, None) == B.GR_EINVAL
