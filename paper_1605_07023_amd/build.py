@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgridder.so")
-SOURCES = ["api.hip", "preprocess.hip", "tables.hip", "grid_romein.hip", "bin.hip", "grid_mfma.hip", "tune.hip", "grid_table2d.hip", "mlp.hip", "batch.hip", "degrid.hip", "compress.hip", "wstack.hip", "aterm.hip"]
+SOURCES = ["api.hip", "preprocess.hip", "tables.hip", "grid_romein.hip", "bin.hip", "grid_mfma.hip", "tune.hip", "mlp.hip", "batch.hip", "degrid.hip", "compress.hip", "wstack.hip", "aterm.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

@@ -1,7 +1,14 @@
-// Gridding with non-separable GCFs that change per visibility and per
-// polarisation, as A-projection's do (Merry 2016, Section 6: such GCFs depend
-// on time, frequency, polarisation and possibly baseline, are not separable,
-// and their loads, not the arithmetic, are expected to set the speed).
+// Gridding with non-separable GCF tables over the binned stream.  The
+// paper's speed-ups rely on a separable GCF (Section 4); without separability
+// the S x S taps of every visibility must be read, so these paths are bound by
+// tap loads from L2 / Infinity Cache rather than by arithmetic.  Two tables:
+//  * GR_TABLE2D through gr_grid / gr_grid_binned: [planes][O][O][S][S], one
+//    tap per cell shared by the polarisations (the exact 2-D W kernel, the
+//    judge of the learned kernel);
+//  * gr_grid_aterm: GCFs that change per visibility and per polarisation, as
+//    A-projection's do (Merry 2016, Section 6: such GCFs depend on time,
+//    frequency, polarisation and possibly baseline, are not separable, and
+//    their loads, not the arithmetic, are expected to set the speed).
 //
 // The caller gives every visibility a GCF id (for instance its time and
 // frequency interval); the fused preprocess stores id * n_planes + plane in
@@ -26,6 +33,8 @@
 // register window at S = 16.)
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
+
+#include <string>
 
 #include "internal.h"
 
@@ -53,9 +62,9 @@ struct AtermDev {
 
 constexpr int kAtermBatch = 256;
 
-template <int P, int C>
+template <int P, int C, bool POL>
 __global__ void __launch_bounds__(256)
-grid_aterm_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvis, const int4* __restrict__ segs,
+grid_nonsep_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvis, const int4* __restrict__ segs,
                   const int32_t* __restrict__ n_segs_p, const void* __restrict__ taps, float2* __restrict__ grid,
                   AtermDev d) {
   __shared__ Record b_rec[kAtermBatch];
@@ -98,7 +107,7 @@ grid_aterm_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvi
       float2 v[P];
 #pragma unroll
       for (int p = 0; p < P; ++p) v[p] = b_vis[q * P + p];
-      const int64_t base = (((int64_t)rec_plane(r) * O + rec_sy(r)) * O + rec_sx(r)) * P * SS;
+      const int64_t base = (((int64_t)rec_plane(r) * O + rec_sy(r)) * O + rec_sx(r)) * (POL ? P : 1) * SS;
 #pragma unroll
       for (int i = 0; i < C; ++i) {
         const int ky = cy + i - oy;
@@ -107,9 +116,10 @@ grid_aterm_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvi
         for (int j = 0; j < C; ++j) {
           const int kx = cx + j - ox;
           if ((unsigned)kx >= (unsigned)S) continue;
+          float2 g = load_tap2(taps, base + ky * S + kx, d.tap_dtype);
 #pragma unroll
           for (int p = 0; p < P; ++p) {
-            const float2 g = load_tap2(taps, base + p * SS + ky * S + kx, d.tap_dtype);
+            if (POL && p > 0) g = load_tap2(taps, base + p * SS + ky * S + kx, d.tap_dtype);
             float2& a = acc[i][j][p];
             a.x = fmaf(g.x, v[p].x, a.x);
             a.x = fmaf(-g.y, v[p].y, a.x);
@@ -140,9 +150,32 @@ grid_aterm_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvi
 
 using AtermFn = void (*)(const Record*, const float2*, const int4*, const int32_t*, const void*, float2*, AtermDev);
 
-template <int P>
-AtermFn aterm_fn(int window) {
-  return window == 32 ? grid_aterm_kernel<P, 2> : window == 48 ? grid_aterm_kernel<P, 3> : grid_aterm_kernel<P, 4>;
+template <int P, bool POL>
+AtermFn nonsep_fn(int window) {
+  return window == 32 ? grid_nonsep_kernel<P, 2, POL>
+                      : window == 48 ? grid_nonsep_kernel<P, 3, POL> : grid_nonsep_kernel<P, 4, POL>;
+}
+
+gr_status launch_nonsep(const void* bins, const BinLayout& L, int n_pol, const gr_kernel& k, float2* grid,
+                        int height, int width, bool pol, const char* who, hipStream_t stream) {
+  if (!k.taps_complex) return fail(GR_EUNSUPPORTED, std::string(who) + ": the GCF table must be complex");
+  if (k.support > 56) return fail(GR_EUNSUPPORTED, std::string(who) + ": support must be <= 56");
+  const int window = aterm_window(k.support);
+  if (L.tile + k.support > window)
+    return fail(GR_EINVAL, std::string(who) + ": binning tile does not fit the window");
+  const char* base = reinterpret_cast<const char*>(bins);
+  const auto* rec = reinterpret_cast<const Record*>(base + L.off_rec);
+  const auto* wv = reinterpret_cast<const float2*>(base + L.off_wvis);
+  const auto* segs = reinterpret_cast<const int4*>(base + L.off_segs);
+  const auto* nsegs = reinterpret_cast<const int32_t*>(base + L.off_nsegs);
+  AtermDev d{k.support, k.oversample, k.tap_dtype, L.tile, L.n_tx, height, width};
+  if (L.max_segs > 0x7fffffff) return fail(GR_EINVAL, std::string(who) + ": too many segments");
+  if (L.max_segs == 0) return check_launch(who);
+  AtermFn fn;
+  if (pol) fn = n_pol == 4 ? nonsep_fn<4, true>(window) : nonsep_fn<1, true>(window);
+  else fn = n_pol == 4 ? nonsep_fn<4, false>(window) : nonsep_fn<1, false>(window);
+  hipLaunchKernelGGL(fn, dim3((unsigned)L.max_segs), dim3(256), 0, stream, rec, wv, segs, nsegs, k.taps, grid, d);
+  return check_launch(who);
 }
 
 }  // namespace
@@ -151,21 +184,12 @@ int aterm_window(int support) { return support <= 16 ? 32 : support <= 32 ? 48 :
 
 gr_status launch_aterm(const void* bins, const BinLayout& L, int n_pol, const gr_kernel& k, float2* grid,
                        int height, int width, hipStream_t stream) {
-  if (!k.taps_complex) return fail(GR_EUNSUPPORTED, "gr_grid_aterm: the GCF table must be complex");
-  if (k.support > 56) return fail(GR_EUNSUPPORTED, "gr_grid_aterm: support must be <= 56");
-  const int window = aterm_window(k.support);
-  if (L.tile + k.support > window) return fail(GR_EINVAL, "gr_grid_aterm: binning tile does not fit the window");
-  const char* base = reinterpret_cast<const char*>(bins);
-  const auto* rec = reinterpret_cast<const Record*>(base + L.off_rec);
-  const auto* wv = reinterpret_cast<const float2*>(base + L.off_wvis);
-  const auto* segs = reinterpret_cast<const int4*>(base + L.off_segs);
-  const auto* nsegs = reinterpret_cast<const int32_t*>(base + L.off_nsegs);
-  AtermDev d{k.support, k.oversample, k.tap_dtype, L.tile, L.n_tx, height, width};
-  if (L.max_segs > 0x7fffffff) return fail(GR_EINVAL, "gr_grid_aterm: too many segments");
-  if (L.max_segs == 0) return check_launch("gr_grid_aterm");
-  const AtermFn fn = n_pol == 4 ? aterm_fn<4>(window) : aterm_fn<1>(window);
-  hipLaunchKernelGGL(fn, dim3((unsigned)L.max_segs), dim3(256), 0, stream, rec, wv, segs, nsegs, k.taps, grid, d);
-  return check_launch("gr_grid_aterm");
+  return launch_nonsep(bins, L, n_pol, k, grid, height, width, true, "gr_grid_aterm", stream);
+}
+
+gr_status launch_table2d(const void* bins, const BinLayout& L, int n_pol, const gr_kernel& k, float2* grid,
+                         int height, int width, hipStream_t stream) {
+  return launch_nonsep(bins, L, n_pol, k, grid, height, width, false, "gr_grid_binned (table2d)", stream);
 }
 
 }  // namespace gr

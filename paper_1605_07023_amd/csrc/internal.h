@@ -128,7 +128,7 @@ size_t block_lds_bytes(const gr_kernel& k, int n_pol, bool tri);
 gr_status launch_mfma(const void* bins, const BinLayout& L, int n_pol, const gr_kernel& k,
                       float2* grid, int height, int width, hipStream_t stream);
 
-// Non-separable table gridder over the binned stream (grid_table2d.hip).
+// Non-separable table gridder over the binned stream (aterm.hip).
 gr_status launch_table2d(const void* bins, const BinLayout& L, int n_pol, const gr_kernel& k,
                          float2* grid, int height, int width, hipStream_t stream);
 
