@@ -177,21 +177,19 @@ degrid_kernel(const Record* __restrict__ rec, const int32_t* __restrict__ idx, c
         for (int c = 0; c < WCG; ++c)
 #pragma unroll
           for (int s = 0; s < 4; ++s) av[c][s] = a[16 * c + 4 * s];
-        f4 z0 = {0.f, 0.f, 0.f, 0.f}, z1 = {0.f, 0.f, 0.f, 0.f};
+        f4 z = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int c = 0; c < WCG; ++c) {
 #pragma unroll
-          for (int s = 0; s < 4; s += 2) {
+          for (int s = 0; s < 4; ++s) {
             if ((cmask >> (4 * c + s)) & 1ull)           // uniform
-              z0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c][s], bfr[c][s], z0, 0, 0, 0);
-            if ((cmask >> (4 * c + s + 1)) & 1ull)
-              z1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c][s + 1], bfr[c][s + 1], z1, 0, 0, 0);
+              z = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c][s], bfr[c][s], z, 0, 0, 0);
           }
         }
         // stage 2: D row 4k + i of this lane is (row k, pol i) at P = 4, row 4k + i at P = 1
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const float zown = z0[i] + z1[i];
+          const float zown = z[i];
           // the other component of Z sits in the neighbouring lane: a DPP quad permutation (1, 0, 3, 2)
           const float zpart = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(zown), 0xB1, 0xF, 0xF, false));
           const int row = j * RG + ((P == 4) ? k : 4 * k + i);
