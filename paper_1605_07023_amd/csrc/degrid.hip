@@ -191,11 +191,14 @@ degrid_kernel(const Record* __restrict__ rec, const int32_t* __restrict__ idx, c
         for (int i = 0; i < 4; ++i) {
           const float zown = z[i];
           // the other component of Z sits in the neighbouring lane: a DPP quad permutation (1, 0, 3, 2)
-          const float zpart = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(zown), 0xB1, 0xF, 0xF, false));
+          const float zpart =
+              __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(zown), 0xB1, 0xF, 0xF, true));
           const int row = j * RG + ((P == 4) ? k : 4 * k + i);
           const float2 tv = tab[rowv + tap_slot(row - yr, S)];
           const float t_im = comp ? tv.y : -tv.y;
-          vacc[(P == 4) ? i : 0] += tv.x * zown + t_im * zpart;
+          float& va = vacc[(P == 4) ? i : 0];
+          va = fmaf(tv.x, zown, va);
+          va = fmaf(t_im, zpart, va);
         }
       }
       // add the partial sums of the 4 row lanes; lanes 0..15 write (visibility, component)
