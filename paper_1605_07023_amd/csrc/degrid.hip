@@ -50,9 +50,12 @@ __device__ inline float tap_value(const void* __restrict__ t, int64_t idx, int d
   }
 }
 
-// window lines: 2 W + 4 floats per (row, polarisation), so that the 64 lanes'
-// A reads fall in 64 different banks
-__host__ __device__ constexpr int degrid_line(int wr) { return 2 * wr + 4; }
+// window lines: 2 W + 2 floats per (row, polarisation).  A wave's LDS read is
+// served 32 lanes at a time over 32 banks; the A reads of lanes 0..31 (16
+// (row, polarisation) lines x K values 0, 1) then fall in 32 different banks,
+// as do lanes 32..63 (measured: 2 W + 4, conflict-free for 64 banks, spent 6x
+// more cycles in bank conflicts)
+__host__ __device__ constexpr int degrid_line(int wr) { return 2 * wr + 2; }
 
 // clamp a tap index to the padded row (-1 and S read the zero entries)
 __device__ __forceinline__ int tap_slot(int t, int S) {
