@@ -350,6 +350,49 @@ def aterm_leg(dev, stream, reps: int) -> dict:
     return out
 
 
+def romein_tracks_leg(dev, stream, reps: int) -> dict:
+    """The paper's own method (variant 1: Romein work distribution with thread
+    coarsening on the vector units, FP32 atomic flushes) beside the MFMA path on
+    the paper-like single-channel tracks (2016 baselines x 3600 dumps of 2 s,
+    quad pol, 2048^2, separable W kernel, 32 planes), where consecutive
+    visibilities of a baseline stay on nearby cells; whole gr_grid calls, HIP
+    events on the stream, median of ``reps`` after one untimed call."""
+    import torch
+    from paper_1605_07023_amd import binding as B, runner
+    from synth import compression_workload
+    out = {"workload": "2016 baselines x 3600 dumps of 2 s over 2 h, 1 channel at 1.4 GHz, quad pol, 2048^2, "
+                       "separable W kernel, 32 planes, oversampling 8 (uncompressed)", "per_support": {}}
+    for S in (16, 32):
+        wl = compression_workload(support=S)
+        dw = runner.upload(wl, dev)
+        g = torch.zeros((wl.n_pol, wl.height, wl.width), dtype=torch.complex64, device=dev)
+        res = {}
+        for name, variant in (("romein_valu", 1), ("mfma", 2)):
+            tune = runner.tuning(variant=variant)
+            need = B.gr_grid_workspace_bytes(wl.n_vis, wl.n_pol, dw.kernel, wl.height, wl.width, tune)
+            ws = torch.empty(need, dtype=torch.uint8, device=dev)
+            runner.grid(dw, g, tune, ws, stream=stream)
+            torch.cuda.synchronize()
+            ms = []
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                runner.grid(dw, g, tune, ws, stream=stream)
+                b.record(stream)
+                torch.cuda.synchronize()
+                ms.append(a.elapsed_time(b))
+            t = sorted(ms)[len(ms) // 2]
+            res[name] = {"call_ms": t, "updates_per_s": wl.n_vis * wl.n_pol * S * S / (t * 1e-3)}
+            del ws
+        res["romein_pct_fp32_valu_peak"] = 100.0 * 8 * res["romein_valu"]["updates_per_s"] / FP32_VALU_PEAK
+        log(f"paper's method on 2 s-dump tracks S={S}: {res['romein_valu']['call_ms']:.2f} ms "
+            f"(MFMA path {res['mfma']['call_ms']:.2f} ms)")
+        out["per_support"][str(S)] = res
+        del g, dw
+        torch.cuda.empty_cache()
+    return out
+
+
 def degrid_leg(dev, uvw, wl, kern, grid, stream, reps: int) -> dict:
     """gr_degrid (the adjoint operation, predicting every visibility from the grid)
     on the full-shape S=32 visibilities and the grid the timed steps produced:
@@ -414,6 +457,8 @@ def main() -> int:
                     help="skip the w-stacking leg (7 w slices of the 2 s-dump tracks, after the timed region)")
     ap.add_argument("--no-aterm", action="store_true",
                     help="skip the A-term leg (per-visibility non-separable GCFs, after the timed region)")
+    ap.add_argument("--no-romein-tracks", action="store_true",
+                    help="skip the leg timing the paper's VALU method on the single-channel tracks")
     ap.add_argument("--no-degrid", action="store_true",
                     help="skip the degridding leg (gr_degrid of the S=32 grid, after the timed region)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -594,6 +639,11 @@ def main() -> int:
         log("A-term leg")
         aterm = aterm_leg(dev, stream, reps=3)
 
+    romein_tracks = None
+    if not args.no_romein_tracks and variant == 2 and args.precision == "f32":
+        log("paper's method on the 2 s-dump tracks")
+        romein_tracks = romein_tracks_leg(dev, stream, reps=3)
+
     cpu = None
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
@@ -620,6 +670,7 @@ def main() -> int:
         "compression": compression,
         "wstack": wstack,
         "aterm": aterm,
+        "romein_tracks": romein_tracks,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
