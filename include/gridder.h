@@ -428,7 +428,8 @@ size_t gr_grid_batch_workspace_bytes(const gr_batch_item* items, int32_t n_items
  * through one fixed launch sequence: per-visibility preprocess and binning
  * kernels spanning every item, then one persistent gridder per (n_pol, real or
  * complex taps) group whose work-groups take (item, segment) work from an
- * atomic counter.  The sequence issues no memset and never synchronises with
+ * atomic counter, and one launch of the single-problem MFMA gridder for each
+ * item of at least 2^19 visibilities (binned for its support's window).  The sequence issues no memset and never synchronises with
  * the host, so it can be captured into a HIP graph and replayed (the items'
  * buffers and the workspace must then stay allocated).  Items are validated
  * on the host before anything is launched; the first invalid item's index is

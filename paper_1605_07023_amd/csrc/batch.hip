@@ -27,6 +27,10 @@ namespace {
 constexpr int kSetupChunk = 4;      // descriptors per setup launch (passed by value)
 constexpr int kGroups = 4;          // (n_pol == 4) * 2 + complex taps
 constexpr int kMaxBatch = 4096;
+// items with at least this many visibilities are binned for their support's
+// window and gridded by the single-problem wave form (one launch each); the
+// persistent work list keeps the smaller ones
+constexpr int64_t kWideMin = int64_t(1) << 19;
 
 struct SetupChunk {
   int first, count;
@@ -68,6 +72,7 @@ struct Plan {
   std::vector<BinLayout> bins;
   std::vector<size_t> lds;           // MFMA LDS bytes per instance ((Re, Im) table entries)
   std::vector<size_t> lds_tri;       // the same with triple entries
+  std::vector<char> wide;            // gridded on its own by the wave form
   int64_t total_blocks;
 };
 
@@ -118,6 +123,7 @@ gr_status make_plan(const gr_batch_item* items, int n, Plan* p) {
   p->bins.resize(n);
   p->lds.resize(n);
   p->lds_tri.resize(n);
+  p->wide.resize(n);
   p->total_blocks = 0;
   for (int i = 0; i < n; ++i) {
     const gr_batch_item& it = items[i];
@@ -126,9 +132,11 @@ gr_status make_plan(const gr_batch_item* items, int n, Plan* p) {
     p->lds_tri[i] = block_lds_bytes(it.kernel, it.n_pol, true);
     p->off_inst[i] = off;
     // the persistent block-form gridder works on 64-cell windows: tiles of 64 - S
-    // keep its segments dense even in sparse instances
+    // keep its segments dense even in sparse instances; a wide item is binned
+    // for the window of its support, as a single problem is
+    p->wide[i] = it.n_vis >= kWideMin;
     p->bins[i] = bin_layout(it.n_vis, it.n_pol, it.kernel.support, it.height, it.width,
-                            it.seg_len > 0 ? it.seg_len : kDefaultSegLen, 64);
+                            it.seg_len > 0 ? it.seg_len : kDefaultSegLen, p->wide[i] ? 0 : 64);
     if (p->bins[i].n_tiles > 0x7fffffff || p->bins[i].max_segs > 0x7fffffff)
       return fail(GR_EINVAL, "gr_grid_batch item " + std::to_string(i) + ": too many tiles");
     off += pre_size(it.n_vis, it.n_pol) + p->bins[i].bytes;
@@ -230,6 +238,10 @@ extern "C" gr_status gr_grid_batch(const gr_batch_item* items, int32_t n_items, 
     I.d.H = it.height;
     I.d.W = it.width;
     I.d.n_blocks = (uint32_t)L.max_segs;
+    if (p.wide[i]) {
+      I.group = -1;                                   // not in any persistent work list
+      continue;
+    }
     const int g = group_of(it);
     I.group = g;
     ++n_members[g];
@@ -258,6 +270,14 @@ extern "C" gr_status gr_grid_batch(const gr_batch_item* items, int32_t n_items, 
     st = launch_mfma_persistent(table, members + g * n_items, n_members[g], prefix + g * (n_items + 1),
                                 counters + g, (g & 2) ? 4 : 1, (g & 1) != 0, tri,
                                 tri ? lds_tri_group[g] : lds_group[g], n_blocks, s);
+    if (st != GR_OK) return st;
+  }
+  for (int i = 0; i < n_items; ++i) {
+    if (!p.wide[i]) continue;
+    const gr_batch_item& it = items[i];
+    char* bins = ws + p.off_inst[i] + pre_size(it.n_vis, it.n_pol);
+    st = launch_mfma(bins, p.bins[i], it.n_pol, it.kernel, reinterpret_cast<float2*>(it.grid), it.height,
+                     it.width, s);
     if (st != GR_OK) return st;
   }
   return GR_OK;
