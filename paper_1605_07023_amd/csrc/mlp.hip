@@ -367,17 +367,35 @@ mlp_dataset_kernel(const float2* __restrict__ table, int S, int O, int64_t n, do
 //      64-vector, computed in FP32 into LDS;
 //  (2) the block's 4 waves evaluate h1 = relu(c + U + V) and the remaining
 //      layers for all S x S taps on matrix cores, taps into LDS;
-//  (3) every work-item updates its 4 x 4 cells of the 64 x 64 window from
-//      LDS; the window is added to the grid once at the end of the segment.
+//  (3) every work-item updates its C x C cells of the window (C = window / 16,
+//      the support's window of 32, 48 or 64 cells) from LDS; the window is
+//      added to the grid once at the end of the segment.
+// The layer weights stay in registers as A operands and the hidden biases are
+// read from LDS when used, so that two waves fit per SIMD.
 struct MlpGridDev {
   int S, O, tile, n_tx, H, W;
 };
 
-template <int P>
-__global__ void __launch_bounds__(256)
-grid_mlp_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvis,
-                const int4* __restrict__ segs, const int32_t* __restrict__ n_segs_p,
-                const float* __restrict__ blob, float2* __restrict__ grid, MlpGridDev d) {
+// One hidden layer of the gridder on a 16-sample tile, its biases read from
+// LDS (bias[m], m = 16 mt + 4 (lane / 16) + i, the D rows the lane holds) into
+// the accumulator: relu(b + W^T h).
+__device__ __forceinline__ void layer_lds_bias(const h8 (&w)[4][2], const float* __restrict__ bias,
+                                               const h8 (&h)[2], h8 (&out)[2], int lane) {
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    f4 d = *reinterpret_cast<const f4*>(bias + 16 * mt + 4 * (lane >> 4));
+    d = __builtin_amdgcn_mfma_f32_16x16x32_f16(w[mt][0], h[0], d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_16x16x32_f16(w[mt][1], h[1], d, 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) out[mt >> 1][4 * (mt & 1) + i] = (_Float16)fmaxf(d[i], 0.f);
+  }
+}
+
+template <int P, int C>
+__device__ __forceinline__ void grid_mlp_body(const Record* __restrict__ rec, const float2* __restrict__ wvis,
+                                              const int4* __restrict__ segs, const int32_t* __restrict__ n_segs_p,
+                                              const float* __restrict__ blob, float2* __restrict__ grid,
+                                              const MlpGridDev& d) {
   extern __shared__ __align__(16) float smg[];
   const int S = d.S, O = d.O;
   float* W1t = smg;                        // [24][64]  rows 12..35 of W1
@@ -386,24 +404,30 @@ grid_mlp_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvis,
   float* cvis = UV + 2 * S * 64;           // [64]
   float* zero = cvis + 64;                 // [2][S] 1 where the offset is outside the support
   float2* taps = reinterpret_cast<float2*>(zero + 2 * S);   // [S * S] (2 S is even: 8-byte aligned)
+  float* bias = reinterpret_cast<float*>(taps + S * S);    // [2][64] b2, b3 (S * S * 8 bytes: 16-byte aligned)
   const int seg = (int)blockIdx.x;
   if (seg >= *n_segs_p) return;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   for (int e = t; e < 24 * 64; e += 256) W1t[e] = blob[kW1 + 12 * 64 + e];
-  Net net;
-  load_net(blob, net, lane);
+  if (t < 2 * kHid) bias[t] = t < kHid ? blob[kB2 + t] : blob[kB3 + t - kHid];
+  h8 w2[4][2], w3[4][2], w4[1][2];
+  float b4[1][4];
+  load_wfrag<4>(blob + kW2, kHid, w2, lane);
+  load_wfrag<4>(blob + kW3, kHid, w3, lane);
+  load_wfrag<1>(blob + kW4, 2, w4, lane);
+  load_bias<1>(blob + kB4, 2, b4, lane);
   const float x0_off = blob[0], x0_step = blob[1], out_scale = blob[2];
   const float half = 0.5f * (float)S;
   const int4 sg = segs[seg];
   const int begin = sg.x, len = sg.y, tile_id = sg.z;
   const int win_x0 = (tile_id % d.n_tx) * d.tile;
   const int win_y0 = (tile_id / d.n_tx) * d.tile;
-  const int cy = 4 * (t >> 4), cx = 4 * (t & 15);
-  float2 acc[4][4][P];
+  const int cy = C * (t >> 4), cx = C * (t & 15);
+  float2 acc[C][C][P];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < C; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < C; ++j)
 #pragma unroll
       for (int p = 0; p < P; ++p) acc[i][j][p] = make_float2(0.f, 0.f);
   const int n_taps = S * S;
@@ -449,9 +473,12 @@ grid_mlp_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvis,
           const int f = kidx(kk, lane >> 4, qq);
           h1[kk][qq] = (_Float16)fmaxf(cvis[f] + U[f] + V[f], 0.f);
         }
-      layer(net.w2, net.b2, h1, h2, nullptr);
-      layer(net.w3, net.b3, h2, h3, nullptr);
-      const float2 y = out_layer(net, h3);
+      layer_lds_bias(w2, bias, h1, h2, lane);
+      layer_lds_bias(w3, bias + kHid, h2, h3, lane);
+      f4 dy = {0.f, 0.f, 0.f, 0.f};
+      dy = __builtin_amdgcn_mfma_f32_16x16x32_f16(w4[0][0], h3[0], dy, 0, 0, 0);
+      dy = __builtin_amdgcn_mfma_f32_16x16x32_f16(w4[0][1], h3[1], dy, 0, 0, 0);
+      const float2 y = make_float2(dy[0] + b4[0][0], dy[1] + b4[0][1]);
       if (lane < 16 && live) {
         const bool out = zero[ku] != 0.f || zero[S + kv] != 0.f;
         taps[tap] = out ? make_float2(0.f, 0.f) : make_float2(out_scale * y.x, out_scale * y.y);
@@ -459,16 +486,16 @@ grid_mlp_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvis,
     }
     __syncthreads();
     const int oy = rec_y0(r) - win_y0, ox = rec_x0(r) - win_x0;
-    if (cy + 3 < oy || cy >= oy + S || cx + 3 < ox || cx >= ox + S) continue;
+    if (cy + C - 1 < oy || cy >= oy + S || cx + C - 1 < ox || cx >= ox + S) continue;
     float2 vv[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) vv[p] = wvis[(int64_t)(begin + q) * P + p];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < C; ++i) {
       const int ky = cy + i - oy;
       if ((unsigned)ky >= (unsigned)S) continue;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < C; ++j) {
         const int kx = cx + j - ox;
         if ((unsigned)kx >= (unsigned)S) continue;
         const float2 g = taps[ky * S + kx];
@@ -485,10 +512,10 @@ grid_mlp_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvis,
   }
   float* gridf = reinterpret_cast<float*>(grid);
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < C; ++i) {
     const int row = win_y0 + cy + i;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < C; ++j) {
       const int col = win_x0 + cx + j;
       if (row >= d.H || col >= d.W) continue;
 #pragma unroll
@@ -501,9 +528,27 @@ grid_mlp_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvis,
   }
 }
 
+// 32- and 48-cell windows: two waves per SIMD; the 64-cell window's 4 x 4 x P
+// accumulators would spill under that limit, so it runs one
+template <int P, int C>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+grid_mlp_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvis, const int4* __restrict__ segs,
+                const int32_t* __restrict__ n_segs_p, const float* __restrict__ blob, float2* __restrict__ grid,
+                MlpGridDev d) {
+  grid_mlp_body<P, C>(rec, wvis, segs, n_segs_p, blob, grid, d);
+}
+
+template <int P>
+__global__ void __launch_bounds__(256)
+grid_mlp_kernel_w64(const Record* __restrict__ rec, const float2* __restrict__ wvis, const int4* __restrict__ segs,
+                    const int32_t* __restrict__ n_segs_p, const float* __restrict__ blob, float2* __restrict__ grid,
+                    MlpGridDev d) {
+  grid_mlp_body<P, 4>(rec, wvis, segs, n_segs_p, blob, grid, d);
+}
+
 size_t grid_mlp_lds(int S) {
   return sizeof(float) * (24 * 64 + 2 * (size_t)S * 12 + 2 * (size_t)S * 64 + 64 + 2 * (size_t)S) +
-         sizeof(float2) * (size_t)S * S;
+         sizeof(float2) * (size_t)S * S + sizeof(float) * 2 * kHid;
 }
 
 }  // namespace
@@ -520,7 +565,13 @@ gr_status launch_grid_mlp(const void* bins, const BinLayout& L, int n_pol, const
   const auto* nsegs = reinterpret_cast<const int32_t*>(base + L.off_nsegs);
   MlpGridDev d{k.support, k.oversample, L.tile, L.n_tx, height, width};
   const size_t lds = grid_mlp_lds(k.support);
-  auto* fn = n_pol == 4 ? grid_mlp_kernel<4> : grid_mlp_kernel<1>;
+  const int window = L.tile + k.support;             // 32, 48 or 64: the support's window
+  if (window != 32 && window != 48 && window != 64)
+    return fail(GR_EINVAL, "gr_grid_binned (network taps): binning tile does not match a 32, 48 or 64-cell window");
+  using Fn = void (*)(const Record*, const float2*, const int4*, const int32_t*, const float*, float2*, MlpGridDev);
+  Fn fn;
+  if (n_pol == 4) fn = window == 32 ? grid_mlp_kernel<4, 2> : window == 48 ? grid_mlp_kernel<4, 3> : grid_mlp_kernel_w64<4>;
+  else fn = window == 32 ? grid_mlp_kernel<1, 2> : window == 48 ? grid_mlp_kernel<1, 3> : grid_mlp_kernel_w64<1>;
   {
     const gr_status lst = ensure_lds_limit(reinterpret_cast<const void*>(fn), lds, "mlp.hip");
     if (lst != GR_OK) return lst;
