@@ -71,9 +71,24 @@ def cpu_baseline(wl_fn, support: int, budget_s: float, threads: int) -> dict:
     k = int(max(32, min(2016, 32 * budget_s / max(dt, 1e-3))))
     log(f"cpu baseline: calibration 32 baselines {dt:.2f}s -> sample {k} baselines")
     upd, dt = run(k)
+    single_per_bl = dt * threads / k                   # seconds per baseline on one thread, roughly
+    # the same oracle on one thread, over a sample of about 3 s
+    k1 = int(max(1, min(32, 3.0 / max(single_per_bl, 1e-3))))
+    cgrid.set_threads(1)
+    upd1, dt1 = run(k1)
+    cgrid.set_threads(threads)
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), model)
+    except OSError:
+        pass
     return {"value": upd / dt, "unit": "updates/s", "cores": threads, "kind": "oracle",
             "sample": f"first {k} of 2016 baselines x 1024 dumps x 16 channels "
-                      f"({k * per_bl} vis, S={support}, quad pol, 4096^2), C FP64 oracle, {dt:.1f} s"}
+                      f"({k * per_bl} vis, S={support}, quad pol, 4096^2), C FP64 oracle, {dt:.1f} s",
+            "single_thread": {"value": upd1 / dt1, "unit": "updates/s",
+                              "sample": f"first {k1} baselines ({k1 * per_bl} vis, S={support}), {dt1:.1f} s"},
+            "host": {"cpu_model": model, "logical_cpus": os.cpu_count()}}
 
 
 def learned_leg(dev, uvw, vis, wl_plain, rec, wvis, bins, bins_bytes, seg_len, stream, steps: int,
