@@ -47,7 +47,7 @@ def _run(R, wl, ids, n_ids, taps_dev, tap_dtype):
     return g.cpu().numpy().astype(np.complex128), stats.cpu().numpy()
 
 
-@pytest.mark.parametrize("P,S,tdt", [(4, 16, "f32"), (1, 32, "f32"), (4, 8, "f32"), (4, 16, "f16")])
+@pytest.mark.parametrize("P,S,tdt", [(4, 16, "f32"), (1, 32, "f32"), (4, 8, "f32"), (4, 16, "f16"), (1, 40, "f32")])
 def test_aterm_matches_oracle(R, P, S, tdt):
     from paper_1605_07023_amd import binding as B
     _say(f"A-term gridding P={P} S={S} taps {tdt}")

@@ -176,14 +176,16 @@ def test_training_reduces_loss_and_resumes(T, tmp_path):
     assert all(np.isfinite(log1.losses + log2.losses))
 
 
-@pytest.mark.parametrize("P,seg,O", [(1, 0, 8), (4, 37, 8), (4, 0, 128)])
-def test_grid_mlp_matches_oracle_taps(T, P, seg, O):
-    """The fused gridder against the FP64 table gridder fed the FP64 network's taps."""
-    _say(f"fused network gridding P={P} seg={seg} O={O}")
+@pytest.mark.parametrize("P,seg,O,S", [(1, 0, 8, 16), (4, 37, 8, 16), (4, 0, 128, 16), (4, 0, 8, 32),
+                                       (1, 0, 8, 40)])
+def test_grid_mlp_matches_oracle_taps(T, P, seg, O, S):
+    """The fused gridder against the FP64 table gridder fed the FP64 network's taps
+    (S = 16, 32, 40: the 32-, 48- and 64-cell windows)."""
+    _say(f"fused network gridding P={P} seg={seg} O={O} S={S}")
     from paper_1605_07023_amd import binding as B, runner
-    S, planes = 16, 5
-    wl = random_point_workload(1500, P, 80, 72, S, O, seed=P + seg, n_planes=planes, margin=5,
-                               weights=True, kernel="w2d")
+    planes = 5
+    wl = random_point_workload(1500 if S <= 16 else 300, P, 80, 72, S, O, seed=P + seg, n_planes=planes,
+                               margin=5, weights=True, kernel="w2d")
     p = _params(11)
     net = T.TapNet(DEV, params=p)
     wh = wl.plane_w_hat()

@@ -456,10 +456,11 @@ def test_wkernel2d_table_fp64_matches_oracle(R, S, O, planes, fov):
     assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("P,seg", [(4, 0), (1, 37), (4, 5)])
-def test_grid_table2d(R, P, seg):
-    _say(f"grid with the 2-D table P={P} seg={seg}")
-    wl = random_point_workload(2500, P, 96, 72, 16, 4, seed=P + seg, n_planes=5, margin=5,
+@pytest.mark.parametrize("P,seg,S", [(4, 0, 16), (1, 37, 16), (4, 5, 16), (4, 0, 32), (1, 11, 40), (4, 0, 40)])
+def test_grid_table2d(R, P, seg, S):
+    """The 2-D table path over the 32-, 48- and 64-cell windows (S = 16, 32, 40)."""
+    _say(f"grid with the 2-D table P={P} seg={seg} S={S}")
+    wl = random_point_workload(2500, P, 96, 72, S, 4, seed=P + seg, n_planes=5, margin=5,
                                weights=True, kernel="w2d")
     dw = R.upload(wl, DEV)
     stats = torch.zeros(2, dtype=torch.int64, device=DEV)
