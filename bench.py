@@ -513,9 +513,15 @@ def main() -> int:
         vis = torch.from_numpy(halves).to(dev)
         vis_scale = torch.from_numpy(scales).to(dev)
         vis_dt = B.GR_F16
-    taps, kern, grids = {}, {}, {}
+    taps, kern, grids, table_ms = {}, {}, {}, {}
     for S, wl in wls.items():
+        runner.make_taps(wl, dev, tap_dt)                 # untimed first call (kernel load)
+        t_a, t_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t_a.record()
         taps[S] = runner.make_taps(wl, dev, tap_dt)
+        t_b.record()
+        torch.cuda.synchronize()
+        table_ms[S] = t_a.elapsed_time(t_b)
         kern[S] = B.make_kernel(taps[S], S, wl.oversample, wl.n_planes, taps_complex=True,
                                 tap_dtype=tap_dt, w_min=wl.w_min, inv_dw=wl.inv_dw)
         grids[S] = torch.zeros((P, wl.height, wl.width), dtype=torch.complex64, device=dev)
@@ -549,6 +555,9 @@ def main() -> int:
     def step(record: bool):
         for S in supports:
             wl = wls[S]
+            if record:
+                ep = torch.cuda.Event(enable_timing=True)
+                ep.record(stream)
             if variant == 2:
                 # preprocess and bin fused: records and tile counts from uvw, then the
                 # weighted visibilities straight to their binned positions
@@ -567,7 +576,7 @@ def main() -> int:
                 B.gr_grid_records(rec, wvis, N, P, kern[S], grids[S], wl.height, wl.width, tune, stream)
             if record:
                 e1.record(stream)
-                ev[S].append((e0, e1))
+                ev[S].append((ep, e0, e1))
 
     if args.calib_copy_mib > 0:
         n = args.calib_copy_mib << 18                     # float32 elements
@@ -599,9 +608,12 @@ def main() -> int:
     for S in supports:
         upd = n_valid * P * S * S
         total_updates += upd
-        kms = [a.elapsed_time(b) for a, b in ev[S]]
+        kms = [a.elapsed_time(b) for _, a, b in ev[S]]
+        pms = [p.elapsed_time(a) for p, a, _ in ev[S]]
         avg = sum(kms) / len(kms) * 1e-3
         per_support[str(S)] = {"updates_per_step": upd, "grid_kernel_ms": avg * 1e3,
+                               "preprocess_bin_ms": sum(pms) / len(pms),
+                               "table_generation_ms": table_ms[S],
                                "grid_kernel_updates_per_s": upd / avg,
                                "grid_kernel_pct_fp32_valu_peak": 100.0 * 8 * upd / avg / FP32_VALU_PEAK}
     ms_per_step = (t1 - t0) / args.steps * 1e3
