@@ -357,10 +357,25 @@ def aterm_leg(dev, stream, reps: int) -> dict:
             ms.append(a.elapsed_time(b))
         t = sorted(ms)[len(ms) // 2]
         upd = kept * wl.n_pol * S * S
-        log(f"A-term leg S={S}: {t:.2f} ms per call, {upd / (t * 1e-3):.3e} updates/s")
+        # the same table stored as FP16 (half the tap bytes, FP32 arithmetic)
+        t16_dev = t_dev.to(torch.float16)
+        k16 = B.make_kernel(t16_dev, S, wl.oversample, wl.n_planes, taps_complex=True, tap_dtype=B.GR_F16,
+                            w_min=wl.w_min, inv_dw=wl.inv_dw, kind=B.GR_TABLE2D)
+        ms16 = []
+        for _ in range(reps + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            B.gr_grid_aterm(dw.uvw, dw.vis, B.GR_F32, None, None, ids, n_ids, wl.n_vis, wl.n_pol, k16,
+                            wl.inv_cell_u, wl.inv_cell_v, g, wl.height, wl.width, ws, need, st, stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms16.append(a.elapsed_time(b))
+        t16 = sorted(ms16[1:])[len(ms16[1:]) // 2]
+        log(f"A-term leg S={S}: {t:.2f} ms per call, {upd / (t * 1e-3):.3e} updates/s; FP16 taps {t16:.2f} ms")
         out["per_support"][str(S)] = {"n_vis": wl.n_vis, "kept": kept, "call_ms": t,
-                                      "updates_per_s": upd / (t * 1e-3), "tap_GB_per_s": upd * 8 / (t * 1e-3) / 1e9}
-        del g, ws, dw, t_dev, ids
+                                      "updates_per_s": upd / (t * 1e-3), "tap_GB_per_s": upd * 8 / (t * 1e-3) / 1e9,
+                                      "f16_taps_call_ms": t16, "f16_taps_updates_per_s": upd / (t16 * 1e-3)}
+        del g, ws, dw, t_dev, t16_dev, ids
         torch.cuda.empty_cache()
     return out
 

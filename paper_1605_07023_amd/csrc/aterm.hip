@@ -42,17 +42,17 @@ namespace gr {
 
 namespace {
 
-__device__ inline float2 load_tap2(const void* __restrict__ t, int64_t idx, int dtype) {
-  switch (dtype) {
-    case GR_F32: return reinterpret_cast<const float2*>(t)[idx];
-    case GR_F16: {
-      const __half2 h = reinterpret_cast<const __half2*>(t)[idx];
-      return make_float2(__low2float(h), __high2float(h));
-    }
-    default: {
-      const __hip_bfloat16* b = reinterpret_cast<const __hip_bfloat16*>(t) + 2 * idx;
-      return make_float2(__bfloat162float(b[0]), __bfloat162float(b[1]));
-    }
+// complex tap idx of a table stored as TDT (a compile-time choice: no branch per tap)
+template <int TDT>
+__device__ __forceinline__ float2 load_tap2(const void* __restrict__ t, int64_t idx) {
+  if constexpr (TDT == GR_F32) {
+    return reinterpret_cast<const float2*>(t)[idx];
+  } else if constexpr (TDT == GR_F16) {
+    const __half2 h = reinterpret_cast<const __half2*>(t)[idx];
+    return make_float2(__low2float(h), __high2float(h));
+  } else {
+    const uint32_t w = reinterpret_cast<const uint32_t*>(t)[idx];   // (re, im) bf16 pair
+    return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
   }
 }
 
@@ -62,7 +62,7 @@ struct AtermDev {
 
 constexpr int kAtermBatch = 256;
 
-template <int P, int C, bool POL>
+template <int P, int C, bool POL, int TDT>
 __global__ void __launch_bounds__(256)
 grid_nonsep_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvis, const int4* __restrict__ segs,
                   const int32_t* __restrict__ n_segs_p, const void* __restrict__ taps, float2* __restrict__ grid,
@@ -116,10 +116,10 @@ grid_nonsep_kernel(const Record* __restrict__ rec, const float2* __restrict__ wv
         for (int j = 0; j < C; ++j) {
           const int kx = cx + j - ox;
           if ((unsigned)kx >= (unsigned)S) continue;
-          float2 g = load_tap2(taps, base + ky * S + kx, d.tap_dtype);
+          float2 g = load_tap2<TDT>(taps, base + ky * S + kx);
 #pragma unroll
           for (int p = 0; p < P; ++p) {
-            if (POL && p > 0) g = load_tap2(taps, base + p * SS + ky * S + kx, d.tap_dtype);
+            if (POL && p > 0) g = load_tap2<TDT>(taps, base + p * SS + ky * S + kx);
             float2& a = acc[i][j][p];
             a.x = fmaf(g.x, v[p].x, a.x);
             a.x = fmaf(-g.y, v[p].y, a.x);
@@ -150,10 +150,17 @@ grid_nonsep_kernel(const Record* __restrict__ rec, const float2* __restrict__ wv
 
 using AtermFn = void (*)(const Record*, const float2*, const int4*, const int32_t*, const void*, float2*, AtermDev);
 
+template <int P, bool POL, int TDT>
+AtermFn nonsep_fn_t(int window) {
+  return window == 32 ? grid_nonsep_kernel<P, 2, POL, TDT>
+                      : window == 48 ? grid_nonsep_kernel<P, 3, POL, TDT> : grid_nonsep_kernel<P, 4, POL, TDT>;
+}
+
 template <int P, bool POL>
-AtermFn nonsep_fn(int window) {
-  return window == 32 ? grid_nonsep_kernel<P, 2, POL>
-                      : window == 48 ? grid_nonsep_kernel<P, 3, POL> : grid_nonsep_kernel<P, 4, POL>;
+AtermFn nonsep_fn(int window, int tap_dtype) {
+  return tap_dtype == GR_F32   ? nonsep_fn_t<P, POL, GR_F32>(window)
+         : tap_dtype == GR_F16 ? nonsep_fn_t<P, POL, GR_F16>(window)
+                               : nonsep_fn_t<P, POL, GR_BF16>(window);
 }
 
 gr_status launch_nonsep(const void* bins, const BinLayout& L, int n_pol, const gr_kernel& k, float2* grid,
@@ -172,8 +179,8 @@ gr_status launch_nonsep(const void* bins, const BinLayout& L, int n_pol, const g
   if (L.max_segs > 0x7fffffff) return fail(GR_EINVAL, std::string(who) + ": too many segments");
   if (L.max_segs == 0) return check_launch(who);
   AtermFn fn;
-  if (pol) fn = n_pol == 4 ? nonsep_fn<4, true>(window) : nonsep_fn<1, true>(window);
-  else fn = n_pol == 4 ? nonsep_fn<4, false>(window) : nonsep_fn<1, false>(window);
+  if (pol) fn = n_pol == 4 ? nonsep_fn<4, true>(window, k.tap_dtype) : nonsep_fn<1, true>(window, k.tap_dtype);
+  else fn = n_pol == 4 ? nonsep_fn<4, false>(window, k.tap_dtype) : nonsep_fn<1, false>(window, k.tap_dtype);
   hipLaunchKernelGGL(fn, dim3((unsigned)L.max_segs), dim3(256), 0, stream, rec, wv, segs, nsegs, k.taps, grid, d);
   return check_launch(who);
 }

@@ -1,8 +1,8 @@
 """GPU tests of gr_grid_aterm (Section 6: non-separable GCFs that change per
 visibility and per polarisation, as A-projection's do) through the C ABI.
 
-Bars: against the FP64 oracle's grid within 1e-5 relative L2 (FP32 and FP16
-taps, the oracle fed the same rounded taps), P = 1 and 4, S = 8 to 32, with
+Bars: against the FP64 oracle's grid within 1e-5 relative L2 (FP32, FP16 and
+BF16 taps, the oracle fed the same rounded taps), P = 1 and 4, S = 8 to 32, with
 weights, a non-finite coordinate and ids out of range, the statistics
 {kept, dropped} equal to the oracle's; integer taps and visibilities bit for
 bit; an empty stream and a stream of only bad ids leave the grid untouched.
@@ -47,7 +47,8 @@ def _run(R, wl, ids, n_ids, taps_dev, tap_dtype):
     return g.cpu().numpy().astype(np.complex128), stats.cpu().numpy()
 
 
-@pytest.mark.parametrize("P,S,tdt", [(4, 16, "f32"), (1, 32, "f32"), (4, 8, "f32"), (4, 16, "f16"), (1, 40, "f32")])
+@pytest.mark.parametrize("P,S,tdt", [(4, 16, "f32"), (1, 32, "f32"), (4, 8, "f32"), (4, 16, "f16"), (1, 40, "f32"),
+                                     (4, 16, "bf16")])
 def test_aterm_matches_oracle(R, P, S, tdt):
     from paper_1605_07023_amd import binding as B
     _say(f"A-term gridding P={P} S={S} taps {tdt}")
@@ -66,6 +67,11 @@ def test_aterm_matches_oracle(R, P, S, tdt):
         taps_ref = t16.astype(np.float32).view(np.complex64).reshape(taps.shape)
         taps_dev = torch.from_numpy(t16).to(DEV)
         code = B.GR_F16
+    elif tdt == "bf16":
+        tb = torch.from_numpy(np.ascontiguousarray(taps).view(np.float32)).to(torch.bfloat16)   # RNE on the host
+        taps_ref = np.ascontiguousarray(tb.to(torch.float32).numpy()).view(np.complex64).reshape(taps.shape)
+        taps_dev = tb.to(DEV)
+        code = B.GR_BF16
     else:
         taps_ref = taps
         taps_dev = torch.from_numpy(np.ascontiguousarray(taps).view(np.float32)).to(DEV)
