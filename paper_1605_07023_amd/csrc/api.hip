@@ -377,8 +377,8 @@ extern "C" gr_status gr_degrid(const double* uvw, int64_t n_vis, int32_t n_pol, 
   if (workspace_bytes < need) return fail(GR_ENOMEM, "gr_degrid: workspace too small (see gr_degrid_workspace_bytes)");
   if (n_vis == 0) return GR_OK;
   auto* rec_tmp = reinterpret_cast<Record*>(reinterpret_cast<char*>(workspace) + L.bytes);
-  if ((st = launch_degrid_bin(uvw, n_vis, *kernel, inv_cell_u, inv_cell_v, height, width, L, workspace, rec_tmp,
-                              dev_stats, (hipStream_t)stream)) != GR_OK)
+  if ((st = launch_degrid_bin(uvw, n_vis, n_pol, *kernel, inv_cell_u, inv_cell_v, height, width, L, workspace,
+                              rec_tmp, reinterpret_cast<float2*>(vis_out), dev_stats, (hipStream_t)stream)) != GR_OK)
     return st;
   return launch_degrid(workspace, L, n_pol, *kernel, reinterpret_cast<const float2*>(grid), height, width,
                        reinterpret_cast<float2*>(vis_out), n_vis, (hipStream_t)stream);

@@ -283,6 +283,8 @@ prebin_count_kernel(prep::PreArgs a, int tile, int n_tx, int32_t* __restrict__ c
         ++n_ok;
       } else {
         ++n_drop;
+        if (a.zero_dropped != nullptr)
+          for (int p = 0; p < a.n_pol; ++p) a.zero_dropped[i * a.n_pol + p] = make_float2(0.f, 0.f);
       }
     }
     uint64_t todo = __ballot(key >= 0);
@@ -450,9 +452,9 @@ gr_status launch_preprocess_bin(const double* uvw, const void* vis, int vis_dtyp
   return check_launch("gr_preprocess_bin");
 }
 
-gr_status launch_degrid_bin(const double* uvw, int64_t n_vis, const gr_kernel& k, double inv_cell_u,
+gr_status launch_degrid_bin(const double* uvw, int64_t n_vis, int n_pol, const gr_kernel& k, double inv_cell_u,
                             double inv_cell_v, int height, int width, const BinLayout& L, void* bins,
-                            Record* rec_tmp, int64_t* dev_stats, hipStream_t stream) {
+                            Record* rec_tmp, float2* vis_out, int64_t* dev_stats, hipStream_t stream) {
   char* base = reinterpret_cast<char*>(bins);
   auto* count = reinterpret_cast<int32_t*>(base + L.off_count);
   auto* cursor = reinterpret_cast<int32_t*>(base + L.off_cursor);
@@ -465,8 +467,9 @@ gr_status launch_degrid_bin(const double* uvw, int64_t n_vis, const gr_kernel& k
   fill_i32<<<(unsigned)((L.n_tiles + 255) / 256), 256, 0, stream>>>(count, L.n_tiles, 0);
   fill_i32<<<1, 256, 0, stream>>>(nsegs, 1, 0);
   auto* st = reinterpret_cast<unsigned long long*>(dev_stats);
-  const prep::PreArgs a = prep::make_pre_args(uvw, nullptr, nullptr, nullptr, n_vis, 1, k, inv_cell_u, inv_cell_v,
-                                              height, width, rec_tmp, nullptr);
+  prep::PreArgs a = prep::make_pre_args(uvw, nullptr, nullptr, nullptr, n_vis, n_pol, k, inv_cell_u, inv_cell_v,
+                                        height, width, rec_tmp, nullptr);
+  a.zero_dropped = vis_out;
   if (n_vis > 0) {
     const int64_t cblocks = std::min<int64_t>(blocks, (int64_t)prep::device_cu_count() * 16);
     prebin_count_kernel<<<(unsigned)cblocks, 256, 0, stream>>>(a, L.tile, L.n_tx, count, st);

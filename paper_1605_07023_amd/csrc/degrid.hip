@@ -300,11 +300,6 @@ sort_segments_kernel(Record* __restrict__ rec, int32_t* __restrict__ idx, const 
   }
 }
 
-__global__ void __launch_bounds__(256) fill_f32(float* __restrict__ p, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0.f;
-}
-
 __global__ void __launch_bounds__(64) zero_i32(int32_t* c) {
   if (threadIdx.x == 0) *c = 0;
 }
@@ -345,10 +340,7 @@ gr_status launch_degrid(const void* bins, const BinLayout& L, int n_pol, const g
   if (st != GR_OK) return st;
   const int wr = window_for(k.support);
   if (L.tile + k.support > wr) return fail(GR_EINVAL, "gr_degrid: binning tile does not fit the window");
-  if (n_vis > 0) {
-    const int64_t n = n_vis * n_pol * 2;
-    fill_f32<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(reinterpret_cast<float*>(vis_out), n);
-  }
+  // dropped visibilities were zeroed by the binning's count pass; every kept one is written below
   if (L.max_segs == 0 || n_vis == 0) return check_launch("gr_degrid");
   const char* base = reinterpret_cast<const char*>(bins);
   const auto* rec = reinterpret_cast<const Record*>(base + L.off_rec);

@@ -108,9 +108,9 @@ gr_status launch_wslice_partition(const double* uvw, const float2* vis, const fl
 // Degridding's binning: records (rec_tmp) and tile counts from uvw, scan,
 // then kept records and their input indices (int32, in the wvis slot of the
 // layout) to the binned positions.
-gr_status launch_degrid_bin(const double* uvw, int64_t n_vis, const gr_kernel& k, double inv_cell_u,
+gr_status launch_degrid_bin(const double* uvw, int64_t n_vis, int n_pol, const gr_kernel& k, double inv_cell_u,
                             double inv_cell_v, int height, int width, const BinLayout& L, void* bins,
-                            Record* rec_tmp, int64_t* dev_stats, hipStream_t stream);
+                            Record* rec_tmp, float2* vis_out, int64_t* dev_stats, hipStream_t stream);
 // The degridder on such a binned stream (degrid.hip); vis_out complex64
 // [n_vis][n_pol], valid entries written, the caller zeroes the rest.
 gr_status plan_degrid(const gr_kernel& k, int n_pol, size_t* lds_bytes);

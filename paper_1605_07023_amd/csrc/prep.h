@@ -45,6 +45,9 @@ struct PreArgs {
   // id * n_planes + plane, and an id outside [0, n_ids) drops the visibility
   const int32_t* ids = nullptr;
   int n_ids = 0;
+  // degridding's output (NULL: none): a dropped visibility's n_pol values are
+  // zeroed by the count pass, so the output needs no separate fill
+  float2* zero_dropped = nullptr;
 };
 
 // Record of visibility i (< a.n) from its coordinates alone: the drop rule's
