@@ -400,8 +400,12 @@ __device__ __forceinline__ void grid_mlp_body(const Record* __restrict__ rec, co
   const int S = d.S, O = d.O;
   float* W1t = smg;                        // [24][64]  rows 12..35 of W1
   float* F = W1t + 24 * 64;                // [2][S][12] offset features, 0 = u, 1 = v
-  float* UV = F + 2 * S * 12;              // [2][S][64] per-tap layer-1 parts
-  float* cvis = UV + 2 * S * 64;           // [64]
+  // per-tap layer-1 parts stored transposed, [2][64][SP]: the 16 lanes of a tile
+  // read 16 consecutive k of one f, and the lane groups' f offsets (4 apart) land
+  // 16 banks apart (SP = 4 mod 8), so those reads are free of bank conflicts
+  const int SP = S + ((4 - S) & 7);
+  float* UV = F + 2 * S * 12;
+  float* cvis = UV + 2 * 64 * SP;          // [64]
   float* zero = cvis + 64;                 // [2][S] 1 where the offset is outside the support
   float2* taps = reinterpret_cast<float2*>(zero + 2 * S);   // [S * S] (2 S is even: 8-byte aligned)
   float* bias = reinterpret_cast<float*>(taps + S * S);    // [2][64] b2, b3 (S * S * 8 bytes: 16-byte aligned)
@@ -448,14 +452,14 @@ __device__ __forceinline__ void grid_mlp_body(const Record* __restrict__ rec, co
       zero[e] = fabsf(dd) < 1.f ? 0.f : 1.f;
     }
     __syncthreads();
-    for (int e = t; e < 2 * S * 64; e += 256) {         // U[k][j], V[k][j]
-      const int row = e >> 6, j = e & 63, axis = row / S;
+    for (int e = t; e < 2 * S * 64; e += 256) {         // U[j][k], V[j][k]
+      const int row = e >> 6, j = e & 63, axis = row / S, k = row - axis * S;
       const float* fr = F + row * 12;
       const float* wc = W1t + axis * 12 * 64 + j;
       float a = 0.f;
 #pragma unroll
       for (int f = 0; f < 12; ++f) a += fr[f] * wc[f * 64];
-      UV[e] = a;
+      UV[(axis * 64 + j) * SP + k] = a;
     }
     __syncthreads();
     // taps: the waves take 16-tap tiles in turn
@@ -463,15 +467,15 @@ __device__ __forceinline__ void grid_mlp_body(const Record* __restrict__ rec, co
       const int tap = tb + (lane & 15);
       const bool live = tap < n_taps;
       const int ku = live ? tap % S : 0, kv = live ? tap / S : 0;
-      const float* U = UV + ku * 64;
-      const float* V = UV + (S + kv) * 64;
+      const float* U = UV + ku;
+      const float* V = UV + 64 * SP + kv;
       h8 h1[2], h2[2], h3[2];
 #pragma unroll
       for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
         for (int qq = 0; qq < 8; ++qq) {
           const int f = kidx(kk, lane >> 4, qq);
-          h1[kk][qq] = (_Float16)fmaxf(cvis[f] + U[f] + V[f], 0.f);
+          h1[kk][qq] = (_Float16)fmaxf(cvis[f] + U[f * SP] + V[f * SP], 0.f);
         }
       layer_lds_bias(w2, bias, h1, h2, lane);
       layer_lds_bias(w3, bias + kHid, h2, h3, lane);
@@ -547,7 +551,8 @@ grid_mlp_kernel_w64(const Record* __restrict__ rec, const float2* __restrict__ w
 }
 
 size_t grid_mlp_lds(int S) {
-  return sizeof(float) * (24 * 64 + 2 * (size_t)S * 12 + 2 * (size_t)S * 64 + 64 + 2 * (size_t)S) +
+  const size_t sp = (size_t)(S + ((4 - S) & 7));
+  return sizeof(float) * (24 * 64 + 2 * (size_t)S * 12 + 2 * 64 * sp + 64 + 2 * (size_t)S) +
          sizeof(float2) * (size_t)S * S + sizeof(float) * 2 * kHid;
 }
 
