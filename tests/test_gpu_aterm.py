@@ -126,3 +126,29 @@ def test_aterm_edge_cases(R):
     R.grid_aterm(dw, torch.zeros(1, dtype=torch.int32, device=DEV), n_ids, grid_out=g)
     torch.cuda.synchronize()
     assert bool(torch.all(g == (2.0 + 1.0j)))
+
+
+def test_aterm_largest_id_space(R):
+    """n_ids x n_planes = 32767, the most the record's 15-bit plane field holds: the largest id
+    and plane grid correctly, ids past the end are dropped."""
+    import dataclasses
+    from paper_1605_07023_amd import binding as B
+    from synth import random_point_workload
+    _say("A-term gridding, 32767 GCF ids")
+    P, S, n_ids = 1, 2, 32767
+    wl = random_point_workload(20000, P, 64, 64, S, 1, seed=4, n_planes=1, margin=2)
+    wl = dataclasses.replace(wl, kernel="aterm")
+    rng = np.random.default_rng(6)
+    ids = rng.integers(0, n_ids, wl.n_vis).astype(np.int32)
+    ids[:50] = n_ids - 1                                     # the largest id
+    ids[50:60] = n_ids                                       # one past the end: dropped
+    taps = (rng.standard_normal((n_ids, 1, 1, 1, P, S, S))
+            + 1j * rng.standard_normal((n_ids, 1, 1, 1, P, S, S))).astype(np.complex64)
+    taps_dev = torch.from_numpy(np.ascontiguousarray(taps).view(np.float32)).to(DEV)
+    got, stats = _run(R, wl, ids, n_ids, taps_dev, B.GR_F32)
+    want, dropped = G.grid_aterm(wl.vis, wl.uvw, None, ids, taps.astype(np.complex128), wl.inv_cell_u,
+                                 wl.inv_cell_v, 1, wl.height, wl.width, 1, wl.w_min, wl.inv_dw)
+    e = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+    _say(f"  {wl.n_vis} visibilities, {dropped} dropped, rel L2 {e:.2e}")
+    assert stats.tolist() == [wl.n_vis - dropped, dropped] and dropped >= 10
+    assert e <= 1e-5
