@@ -11,9 +11,9 @@
 // it, so that gr_bin / gr_grid_binned take the output with the input's n_vis
 // and no host synchronisation.
 //
-// Three launches: per block of 256 positions the number of run heads; one
-// block scanning those counts (and writing the total); per block the heads'
-// output slots and the runs' sums.
+// Three steps: per block of 256 positions the number of run heads; the scan of
+// those counts (one block, or two levels for long streams), which also writes
+// the total; per block the heads' output slots and the runs' sums.
 #include <algorithm>
 
 #include "internal.h"
@@ -127,14 +127,74 @@ scan_i32_kernel(int32_t* __restrict__ data, int n, int64_t* __restrict__ total) 
   if (t == T - 1 && total != nullptr) *total = s[T - 1];
 }
 
+constexpr int kScanChunk = 4096;     // elements per block of the two-level scan (1024 threads x 4)
+
+// first level: each block scans its chunk of 4096 in place (exclusive) and
+// writes the chunk's total to sums[block]
+__global__ void __launch_bounds__(1024)
+scan_chunk_kernel(int32_t* __restrict__ data, int n, int32_t* __restrict__ sums) {
+  __shared__ int s_w[16];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + 4 * t;
+  int v[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) v[j] = base + j < n ? data[base + j] : 0;
+  const int mine = v[0] + v[1] + v[2] + v[3];
+  int inc = mine;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int x = __shfl_up(inc, o);
+    if (lane >= o) inc += x;
+  }
+  if (lane == 63) s_w[wave] = inc;
+  __syncthreads();
+  int off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < 16; ++w) {
+    if (w < wave) off += s_w[w];
+    tot += s_w[w];
+  }
+  int run = off + inc - mine;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (base + j < n) data[base + j] = run;
+    run += v[j];
+  }
+  if (t == 0) sums[blockIdx.x] = tot;
+}
+
+// second level done by scan_i32_kernel on sums; then each chunk adds its offset
+__global__ void __launch_bounds__(1024)
+scan_add_kernel(int32_t* __restrict__ data, int n, const int32_t* __restrict__ sums) {
+  const int32_t add = sums[blockIdx.x];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + 4 * threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (base + j < n) data[base + j] += add;
+}
+
 }  // namespace
 
-void launch_scan_i32(int32_t* data, int n, int64_t* total, hipStream_t stream) {
-  scan_i32_kernel<<<1, 1024, 0, stream>>>(data, n, total);
+size_t scan_i32_scratch_bytes(int64_t n) {
+  return align256(sizeof(int32_t) * (size_t)((n + kScanChunk - 1) / kScanChunk + 1));
+}
+
+// one block when the counts are few; else chunks of 4096 scanned in parallel,
+// their totals scanned by one block, and the chunk offsets added back
+void launch_scan_i32(int32_t* data, int n, int64_t* total, int32_t* scratch, hipStream_t stream) {
+  if (n <= 4 * kScanChunk) {
+    scan_i32_kernel<<<1, 1024, 0, stream>>>(data, n, total);
+    return;
+  }
+  const int chunks = (n + kScanChunk - 1) / kScanChunk;
+  scan_chunk_kernel<<<chunks, 1024, 0, stream>>>(data, n, scratch);
+  scan_i32_kernel<<<1, 1024, 0, stream>>>(scratch, chunks, total);
+  scan_add_kernel<<<chunks, 1024, 0, stream>>>(data, n, scratch);
 }
 
 size_t compress_workspace_bytes(int64_t n_vis) {
-  return align256(sizeof(int32_t) * (size_t)((n_vis + kCompressBlock - 1) / kCompressBlock)) + 256;
+  const int64_t blocks = (n_vis + kCompressBlock - 1) / kCompressBlock;
+  return align256(sizeof(int32_t) * (size_t)blocks) + scan_i32_scratch_bytes(blocks) + 256;
 }
 
 gr_status launch_compress(const Record* rec, const float2* wvis, int64_t n_vis, int n_pol, Record* out_rec,
@@ -146,7 +206,9 @@ gr_status launch_compress(const Record* rec, const float2* wvis, int64_t n_vis, 
     zero_records<<<(unsigned)((n_vis + 255) / 256), 256, 0, stream>>>(out_rec, n_vis);
     head_count_kernel<<<(unsigned)blocks, kCompressBlock, 0, stream>>>(rec, n_vis, block_heads);
   }
-  launch_scan_i32(block_heads, (int)blocks, out_count, stream);
+  auto* scan_scratch = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(workspace) +
+                                                 align256(sizeof(int32_t) * (size_t)blocks));
+  launch_scan_i32(block_heads, (int)blocks, out_count, scan_scratch, stream);
   if (n_vis > 0) {
     using Fn = void (*)(const Record*, const float2*, int64_t, const int32_t*, Record*, float2*);
     const Fn fn = n_pol == 4 ? compress_write_kernel<4> : compress_write_kernel<1>;

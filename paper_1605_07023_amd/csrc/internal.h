@@ -95,9 +95,11 @@ int aterm_window(int support);
 size_t compress_workspace_bytes(int64_t n_vis);
 gr_status launch_compress(const Record* rec, const float2* wvis, int64_t n_vis, int n_pol, Record* out_rec,
                           float2* out_wvis, int64_t* out_count, void* workspace, hipStream_t stream);
-// One-block exclusive scan of n int32 counts in place (total < 2^31); the
-// total to *total (device int64) when it is non-NULL.
-void launch_scan_i32(int32_t* data, int n, int64_t* total, hipStream_t stream);
+// Exclusive scan of n int32 counts in place (total < 2^31); the total to
+// *total (device int64) when it is non-NULL.  scratch: scan_i32_scratch_bytes(n)
+// of device memory for the two-level form (used when n > 16384).
+size_t scan_i32_scratch_bytes(int64_t n);
+void launch_scan_i32(int32_t* data, int n, int64_t* total, int32_t* scratch, hipStream_t stream);
 // W-stacking's split (wstack.hip): stable partition of (uvw, vis, weights) by
 // w slice; slice_offsets [n_slices + 1] (device int64).
 size_t wslice_workspace_bytes(int64_t n_vis, int n_slices);

@@ -118,7 +118,8 @@ slice_offsets_kernel(const int32_t* __restrict__ offs, int n_blocks, int n_slice
 
 size_t wslice_workspace_bytes(int64_t n_vis, int n_slices) {
   const int64_t blocks = (n_vis + kSliceChunk - 1) / kSliceChunk;
-  return align256(sizeof(int32_t) * (size_t)blocks * (size_t)(n_slices + 1)) + 256;
+  const int64_t entries = blocks * (int64_t)(n_slices + 1);
+  return align256(sizeof(int32_t) * (size_t)entries) + scan_i32_scratch_bytes(entries) + 256;
 }
 
 gr_status launch_wslice_partition(const double* uvw, const float2* vis, const float* wts, int64_t n_vis, int n_pol,
@@ -133,7 +134,9 @@ gr_status launch_wslice_partition(const double* uvw, const float2* vis, const fl
   if (blocks > 0) {
     slice_count_kernel<<<(unsigned)blocks, kSliceBlock, hist_lds, stream>>>(uvw, n_vis, w_first, inv_width,
                                                                             n_slices, counts, (int)blocks);
-    launch_scan_i32(counts, (int)entries, nullptr, stream);
+    auto* scan_scratch = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(workspace) +
+                                                   align256(sizeof(int32_t) * (size_t)entries));
+    launch_scan_i32(counts, (int)entries, nullptr, scan_scratch, stream);
     using Fn = void (*)(const double*, const float2*, const float*, int64_t, double, double, int, const int32_t*,
                         int, double*, float2*, float*);
     Fn fn;
