@@ -81,6 +81,38 @@ def test_degrid_matches_oracle(R, P, S, kern, seg):
     assert stats.cpu().tolist() == [int(valid.sum()), int((~valid).sum())]
 
 
+@pytest.mark.parametrize("P,tdt", [(4, "f16"), (1, "bf16")])
+def test_degrid_reduced_precision_taps(R, P, tdt):
+    """FP16 and BF16 tap tables (rounded on the host from the oracle's FP64 table, the oracle fed the same
+    rounded taps): within 1e-5, the arithmetic being FP32 either way."""
+    from paper_1605_07023_amd import binding as B
+    _say(f"degrid with {tdt} taps P={P}")
+    S = 32
+    rng = np.random.default_rng(90 + P)
+    wl = random_point_workload(2500, P, 120, 104, S, 8, seed=91 + P, n_planes=3, margin=6, kernel="wsep")
+    pair = np.ascontiguousarray(np.stack([_taps(wl).real, _taps(wl).imag], axis=-1), dtype=np.float32)
+    if tdt == "f16":
+        t_host = pair.astype(np.float16)
+        taps_dev = torch.from_numpy(t_host).to(DEV)
+        rounded = t_host.astype(np.float64)
+        code = B.GR_F16
+    else:
+        tb = torch.from_numpy(pair).to(torch.bfloat16)
+        taps_dev = tb.to(DEV)
+        rounded = tb.to(torch.float32).numpy().astype(np.float64)
+        code = B.GR_BF16
+    dw = R.upload(wl, DEV, taps=taps_dev)
+    dw.kernel = B.make_kernel(taps_dev, S, 8, 3, taps_complex=True, tap_dtype=code, w_min=wl.w_min,
+                              inv_dw=wl.inv_dw)
+    g = _random_grid(rng, P, wl.height, wl.width)
+    got = _degrid(R, dw, torch.from_numpy(g).to(DEV))
+    ref = G.degrid_separable(g.astype(np.complex128), wl.uvw, rounded[..., 0] + 1j * rounded[..., 1],
+                             wl.inv_cell_u, wl.inv_cell_v, wl.oversample, wl.n_planes, wl.w_min, wl.inv_dw)
+    err = _rel(got.astype(np.complex128), ref)
+    _say(f"  rel L2 {err:.2e}")
+    assert err <= 1e-5
+
+
 @pytest.mark.parametrize("P", [1, 4])
 def test_degrid_integer_inputs_bit_exact(R, P):
     """Integer grid values and taps: every product and partial sum is an exact

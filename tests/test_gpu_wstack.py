@@ -113,13 +113,13 @@ def test_partition_full_track_set(R):
     assert off[-1] == wl.n_vis                              # every w inside the padded range
 
 
-@pytest.mark.parametrize("mode", ["batch", "per_slice"])
-def test_grid_wstack_matches_oracle(R, mode):
+@pytest.mark.parametrize("mode,P", [("batch", 4), ("per_slice", 4), ("batch", 1)])
+def test_grid_wstack_matches_oracle(R, mode, P):
     from paper_1605_07023_amd import binding as B
-    _say(f"W-stacked gridding ({mode}), 7 slices, 16 residual planes, S=16, 512^2")
-    wl = wstack_workload(n_baselines=30, n_pol=4, grid=512, support=16, planes_per_slice=16)
+    _say(f"W-stacked gridding ({mode}), P={P}, 7 slices, 16 residual planes, S=16, 512^2")
+    wl = wstack_workload(n_baselines=30, n_pol=P, grid=512, support=16, planes_per_slice=16)
     rng = np.random.default_rng(21)
-    wl.weights = rng.uniform(0.5, 2.0, (wl.n_vis, 4)).astype(np.float32)
+    wl.weights = rng.uniform(0.5, 2.0, (wl.n_vis, P)).astype(np.float32)
     taps = (rng.standard_normal((16, 8, 16)) + 1j * rng.standard_normal((16, 8, 16))).astype(np.complex64)
     t = torch.from_numpy(np.ascontiguousarray(taps).view(np.float32).reshape(16, 8, 16, 2)).to(DEV)
     dw = R.upload(wl, DEV, taps=t)
