@@ -193,9 +193,9 @@ gr_status gr_grid_binned(const void* bins, int64_t n_vis, int32_t n_pol, const g
  * (n_vis entries, input order).  out_records / out_wvis (same layouts and
  * sizes, must not overlap the inputs) receive the compressed stream first, one
  * entry per run in input order with the run's weighted visibilities summed in
- * input order (deterministic), then invalid records up to n_vis, so that
- * gr_bin and gr_grid_binned take them with the same n_vis and no host
- * synchronisation; gridding them gives the grid of the input up to FP32
+ * input order (deterministic), then invalid records up to n_vis (their
+ * out_wvis slots are left unwritten), so that gr_bin and gr_grid_binned take
+ * them with the same n_vis and no host synchronisation; gridding them gives the grid of the input up to FP32
  * rounding.  out_count (device int64, or NULL) receives the number of runs
  * (overwritten).  workspace: gr_compress_workspace_bytes(n_vis). */
 size_t gr_compress_workspace_bytes(int64_t n_vis);
