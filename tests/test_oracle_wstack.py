@@ -86,3 +86,18 @@ def test_grid_wstack_sums_to_the_whole_for_a_w_independent_kernel():
     assert outside == int(np.count_nonzero(~inside)) and outside > 0
     assert dropped == d_whole
     np.testing.assert_allclose(grids.sum(axis=0), whole, rtol=0, atol=1e-12)
+
+
+def test_slice_w_min_agrees_with_the_binding():
+    """The host-side w_min of each slice's kernel (paper_1605_07023_amd.runner, used to form the
+    batch items) equals the oracle's, bit for bit, so both sides pick the same planes."""
+    pytest.importorskip("torch")
+    from paper_1605_07023_amd import runner
+    rng = np.random.default_rng(17)
+    for _ in range(2000):
+        w_first = float(rng.uniform(-5e3, 5e3))
+        inv_width = float(10.0 ** rng.uniform(-4, 1))
+        w_min_rel = float(rng.uniform(-1e3, 0.0))
+        s = int(rng.integers(0, 255))
+        assert runner.slice_w_min(w_first, inv_width, s, w_min_rel) == G.wslice_w_min(w_first, inv_width, s,
+                                                                                        w_min_rel)
