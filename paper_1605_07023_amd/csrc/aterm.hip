@@ -4,7 +4,7 @@
 // tap loads from L2 / Infinity Cache rather than by arithmetic.  Two tables:
 //  * GR_TABLE2D through gr_grid / gr_grid_binned: [planes][O][O][S][S], one
 //    tap per cell shared by the polarisations (the exact 2-D W kernel, the
-//    judge of the learned kernel);
+//    reference the learned kernel is measured against);
 //  * gr_grid_aterm: GCFs that change per visibility and per polarisation, as
 //    A-projection's do (Merry 2016, Section 6: such GCFs depend on time,
 //    frequency, polarisation and possibly baseline, are not separable, and
