@@ -84,9 +84,9 @@ typedef struct {
   int32_t cu, cv, wg_u, wg_v, vis_per_wg, variant;
 } gr_tuning;
 
-/* Preprocess (Section 4: integer grid coordinates, sub-grid coordinates for
- * indexing the GCF, the w-plane index and the pre-weighted visibility are
- * prepared once, before gridding).  Per visibility n, in FP64:
+/* Preprocess (Section 4: the gridder's per-visibility inputs -- cell, phase
+ * into the oversampled GCF, w plane, weighted values -- are computed in a pass
+ * of their own before gridding).  Per visibility n, in FP64:
  *   fx = rint(u * (inv_cell_u * O)) + (W/2) O   (round half to even)
  *   ix = fx >> log2 O, sx = fx & (O - 1), x0 = ix - S/2 + 1   (likewise v, y)
  *   plane = rint((w - w_min) * inv_dw), or 0 when n_planes == 1.
@@ -293,8 +293,8 @@ gr_status gr_grid(const double* uvw, const void* vis, int32_t vis_dtype, const f
                   int32_t width, const gr_tuning* tuning, void* workspace,
                   size_t workspace_bytes, int64_t* dev_stats, void* stream);
 
-/* Autotuning (Section 4: a small data set is benchmarked with a range of
- * coarsening factors and work-group sizes and the best is remembered).
+/* Autotuning (Section 4: the work decomposition is chosen by timing a
+ * synthetic problem under many coarsening and work-group settings).
  * Times each of n_candidates tunings on preprocessed records/wvis: variant 1
  * candidates with gr_grid_records, others with gr_bin (into `bins`, sized for
  * the largest seg_len = vis_per_wg among them) + gr_grid_binned, `reps` times

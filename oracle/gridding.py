@@ -217,9 +217,8 @@ def grid_w2d_continuous(vis: np.ndarray, uvw: np.ndarray, weights: Optional[np.n
 
 
 # ----------------------------------------------------------------------------
-# Index conversion and drop rule (Section 4: the gridding kernel receives
-# integer grid coordinates, sub-grid coordinates for indexing the GCF and the
-# w-plane index, computed once as a preprocess)
+# Index conversion and drop rule (Section 4: cell, oversampling phase and w
+# plane of every visibility are worked out once, before gridding)
 # ----------------------------------------------------------------------------
 
 def pixel_coords(uvw: np.ndarray, inv_cell_u: float, inv_cell_v: float, oversample: int,

@@ -1,7 +1,6 @@
-"""Autotuning driver and memo (Merry 2016, Section 4: a small artificial data set
-is synthesised and benchmarked with a range of coarsening factors and
-work-group sizes, the best combination is remembered, and tuning is done
-separately per number of polarisations).
+"""Autotuning driver and memo (Merry 2016, Section 4: the coarsening factors and
+work-group shape are picked by timing a synthetic problem, per polarisation
+count, and the winner is kept for later runs).
 
 The timing sweep runs in the library (gr_autotune); this module builds the
 candidate list, prepares the small data set on the device, and keeps the memo

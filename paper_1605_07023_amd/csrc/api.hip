@@ -136,9 +136,11 @@ extern "C" size_t gr_preprocess_bin_bytes(int64_t n_vis, int32_t n_pol, int32_t 
 extern "C" size_t gr_grid_workspace_bytes(int64_t n_vis, int32_t n_pol, const gr_kernel* kernel,
                                           int32_t height, int32_t width, const gr_tuning* tuning) {
   if (n_vis < 0 || n_pol < 1 || kernel == nullptr || height < 1 || width < 1) return 0;
-  if (pick_variant(*kernel, n_pol, tuning) == 2)     // fused preprocess and bin
+  if (pick_variant(*kernel, n_pol, tuning) == 2) {   // fused preprocess and bin
+    if (kernel->support > kMaxBinnedSupport) return 0;  // gr_grid refuses such a call
     return bin_layout(n_vis, n_pol, kernel->support, height, width, seg_len_of(tuning)).bytes +
            align256(sizeof(Record) * (size_t)n_vis);
+  }
   return pre_bytes(n_vis, n_pol);
 }
 
@@ -391,6 +393,7 @@ extern "C" gr_status gr_grid_binned(const void* bins, int64_t n_vis, int32_t n_p
   if ((st = validate_grid(n_pol, height, width, kernel->support)) != GR_OK) return st;
   if (n_vis < 0 || n_vis > 0x7fffffffLL) return fail(GR_EINVAL, "n_vis must be in [0, 2^31)");
   if (grid == nullptr || bins == nullptr) return fail(GR_EINVAL, "grid and bins must be non-NULL");
+  if (kernel->support > kMaxBinnedSupport) return fail(GR_EUNSUPPORTED, "the binned gridders need support <= 56");
   const BinLayout L = bin_layout(n_vis, n_pol, kernel->support, height, width,
                                  seg_len > 0 ? seg_len : kDefaultSegLen);
   return launch_binned(bins, L, n_pol, *kernel, reinterpret_cast<float2*>(grid), height, width,
@@ -411,6 +414,8 @@ extern "C" gr_status gr_grid(const double* uvw, const void* vis, int32_t vis_dty
   if (tuning && (tuning->variant < 0 || tuning->variant > 2))
     return fail(GR_EUNSUPPORTED, "tuning.variant not available in this build");
   const int variant = pick_variant(*kernel, n_pol, tuning);
+  if (variant == 2 && kernel->support > kMaxBinnedSupport)
+    return fail(GR_EUNSUPPORTED, "the binned gridders need support <= 56");
   const size_t need = gr_grid_workspace_bytes(n_vis, n_pol, kernel, height, width, tuning);
   if (n_vis > 0 && workspace == nullptr) return fail(GR_EINVAL, "workspace is NULL");
   if (workspace_bytes < need) return fail(GR_ENOMEM, "workspace too small (see gr_grid_workspace_bytes)");

@@ -387,6 +387,7 @@ BinLayout bin_layout(int64_t n_vis, int n_pol, int support, int height, int widt
                      int window) {
   BinLayout L{};
   L.tile = binned_tile(support, window);
+  if (L.tile <= 0 || seg_len <= 0) return L;   // no window holds such footprints: bytes = 0
   L.n_tx = (width + L.tile - 1) / L.tile;
   L.n_ty = (height + L.tile - 1) / L.tile;
   L.n_tiles = (int64_t)L.n_tx * L.n_ty;

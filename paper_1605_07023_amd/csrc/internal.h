@@ -139,6 +139,9 @@ gr_status launch_grid_mlp(const void* bins, const BinLayout& L, int n_pol, const
                           float2* grid, int height, int width, hipStream_t stream);
 
 constexpr int kDefaultSegLen = 4096;
+// largest support of the binned gridders: footprints must fit the 64-cell window
+// with a tile of at least 8 cells
+constexpr int kMaxBinnedSupport = 56;
 size_t align256(size_t v);
 
 // Launch parameters of the MFMA gridder (grid_mfma.hip).

@@ -3,9 +3,8 @@
 // phases, w-plane, valid bit) from the coordinates, in FP64, and the weighted
 // visibilities with their finiteness (the two parts of the drop rule).
 //
-// Merry (2016), Section 4: the gridding kernel receives, per visibility, the
-// integer grid coordinates, the sub-grid coordinates used to index the GCF,
-// the w-plane index and the pre-weighted visibility.
+// Merry (2016), Section 4: the per-visibility inputs of the gridder are
+// prepared ahead of it, in a pass of their own.
 #pragma once
 
 #include <hip/hip_fp16.h>

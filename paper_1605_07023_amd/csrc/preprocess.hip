@@ -1,10 +1,9 @@
 // Preprocess: uvw -> footprint origin, oversampled phase, w-plane; pre-weighted
 // visibilities; drop rule.  FP64 for every coordinate computation.
 //
-// Merry (2016), Section 4: the gridding kernel receives, per visibility, the
-// integer grid coordinates, the sub-grid coordinates used to index the GCF,
-// the w-plane index and the pre-weighted visibility; this is computed once,
-// ahead of gridding.
+// Merry (2016), Section 4: everything the gridder needs per visibility (cell
+// position, oversampling phase, w plane, weighted values) is worked out in a
+// separate pass before gridding, once per visibility.
 #include <algorithm>
 
 #include <hip/hip_fp16.h>

@@ -110,6 +110,23 @@ def test_grid_rejects_small_workspace(lib):
     assert st == B.GR_ENOMEM
 
 
+@pytest.mark.parametrize("S", [58, 62, 64])
+@pytest.mark.parametrize("kind,variant", [(1, 0), (2, 0), (0, 2)])
+def test_binned_paths_reject_supports_past_56(lib, S, kind, variant):
+    """Supports 58..64 pass the kernel descriptor's rule (2..64) but no binned
+    gridder's window holds them: the workspace query answers 0 and every
+    binned entry point refuses on the host (no division by a zero tile)."""
+    from paper_1605_07023_amd import binding as B
+    k = _kernel(kind=kind, support=S, tap_dtype=B.GR_F32, taps_complex=1)
+    t = B.GrTuning(0, 0, 0, 0, 0, variant)
+    assert B.gr_grid_workspace_bytes(1000, 1, k, 128, 128, t) == 0
+    st = lib.gr_grid(1 << 20, 1 << 20, B.GR_F32, None, None, 1000, 1, ctypes.byref(k), 1.0, 1.0,
+                     1 << 20, 128, 128, ctypes.byref(t), 1 << 20, 1 << 30, None, None)
+    assert st == B.GR_EUNSUPPORTED and "56" in lib.gr_last_error().decode()
+    st = lib.gr_grid_binned(1 << 20, 1000, 1, ctypes.byref(k), 0, 1 << 20, 128, 128, None)
+    assert st == B.GR_EUNSUPPORTED and "56" in lib.gr_last_error().decode()
+
+
 def test_preprocess_rejects(lib):
     from paper_1605_07023_amd import binding as B
     k = _kernel()

@@ -150,6 +150,59 @@ def test_pixel_coords_drop_rules():
     np.testing.assert_array_equal(c["valid"], [False, True, True, False, False])
 
 
+def test_finite_values_hand_cases():
+    """The value half of the drop rule, by hand: a visibility is kept only when
+    every real and imaginary part of its values, and every one of its weights,
+    is finite; a bad value in one polarisation drops the whole visibility, and
+    its finite neighbours are kept.  Holds for complex64 and complex128 input."""
+    nan, inf = np.nan, np.inf
+    vis = np.ones((8, 4), np.complex64) * np.complex64(1 - 2j)
+    vis[1, 2] = complex(nan, 0.5)              # NaN in Re
+    vis[2, 0] = complex(0.25, inf)             # +inf in Im
+    vis[3, 3] = complex(-1.0, -inf)            # -inf in Im
+    vis[5, 1] = complex(3.0e38, -3.0e38)       # large but finite: kept
+    w = np.ones((8, 4), np.float32)
+    w[4, 1] = nan                              # NaN in one of four weights
+    w[6, 3] = -inf                             # -inf weight
+    w[7, 0] = 0.0                              # a zero weight is a finite weight
+    keep = [True, False, False, False, False, True, False, True]
+    assert G.finite_values(vis, w).tolist() == keep
+    # without weights only the values decide
+    assert G.finite_values(vis, None).tolist() == [True, False, False, False, True, True, True, True]
+    assert G.finite_values(vis.astype(np.complex128), w).tolist() == keep
+    # single polarisation, and an empty stream
+    assert G.finite_values(vis[:, :1], None).tolist() == [True, True, False, True, True, True, True, True]
+    assert G.finite_values(vis[:0], w[:0]).shape == (0,)
+
+
+def test_nonfinite_values_are_dropped_from_the_grid():
+    """A visibility with a non-finite value or weight leaves the grid exactly as
+    if it were absent (no NaN or inf reaches any cell), and is counted as
+    dropped.  Expected grid: the definition summed by hand, in a Python loop
+    over the visibilities known to be clean, without finite_values."""
+    wl = _wl(n=24, P=4, H=40, W=48, S=8, O=8, seed=9, weights=True)
+    bad = [2, 7, 8, 15]
+    wl.vis[2, 1] = complex(np.nan, 0.0)
+    wl.vis[7, 3] = complex(0.0, -np.inf)
+    wl.weights[8, 0] = np.inf
+    wl.weights[15, 2] = np.nan
+    taps = G.kb_table(8, 8, 8.6)
+    g, dropped = _grid(wl, taps)
+    assert np.isfinite(g).all()
+    c = G.pixel_coords(wl.uvw, 1, 1, 8, 8, 40, 48)
+    assert c["valid"].all()                    # nothing else is dropped in this draw
+    assert dropped == len(bad)
+    ref = np.zeros((4, 40, 48), np.complex128)
+    for n in range(24):
+        if n in bad:
+            continue
+        k = np.outer(taps[0, c["sy"][n]], taps[0, c["sx"][n]])
+        for p in range(4):
+            val = complex(wl.vis[n, p]) * float(wl.weights[n, p])
+            ref[p, c["y0"][n]:c["y0"][n] + 8, c["x0"][n]:c["x0"][n] + 8] += val * k
+    np.testing.assert_allclose(g, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+
+
 # ---------------------------------------------------------------- gridding
 
 def _wl(n=60, P=2, H=40, W=48, S=8, O=8, seed=0, planes=1, kernel="kb", weights=True, margin=0):
