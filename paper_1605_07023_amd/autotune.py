@@ -27,26 +27,51 @@ SEG_LENS = (512, 1024, 2048, 4096, 8192, 16384)
 COARSEN = (1, 2, 4, 8)
 
 
+def _bin_blocks(support: int, c: int) -> int:
+    """Blocks per bin along one axis for coarsening c: the smallest n with c n >= S + c - 1."""
+    return (support + 2 * c - 2) // c
+
+
 def candidates(n_pol: int, support: int, variants: Iterable[int] = (1, 2),
-               vis_per_wg: Iterable[int] = (1024,)) -> List[B.GrTuning]:
+               vis_per_wg: Iterable[int] = (0, 1024),
+               tiles: Iterable[str] = ("flat", "rect")) -> List[B.GrTuning]:
     """Work decompositions to try.
 
-    variant 1 (work-item kernel): coarsening cu x cv in {1, 2, 4, 8}^2 (the
-    paper's range) with cu * cv * n_pol <= 64 (register budget), default tile
-    shape, the given visibilities per work-group.  variant 2 (MFMA kernel):
-    segment lengths SEG_LENS."""
+    variant 1 (the VALU work-item kernel): coarsening cu x cv in {1, 2, 4, 8}^2
+    (the paper's range) with cu * cv * n_pol <= 64 (register budget); for each,
+    the wave's tile ("flat": 64 consecutive blocks of the bin, "rect": a
+    rectangle of up to 16 blocks along u and as many rows as fill 64 lanes) and
+    the visibilities per item (0: equal ranges, one item per wave; 1024: the
+    paper's fixed chunk).  variant 2 (MFMA kernel): segment lengths SEG_LENS."""
     out = []
     if 1 in variants:
         for cu in COARSEN:
             for cv in COARSEN:
                 if cu * cv * n_pol > 64:
                     continue
-                for vpw in vis_per_wg:
-                    out.append(B.GrTuning(cu, cv, 0, 0, vpw, 1))
+                nu, nv = _bin_blocks(support, cu), _bin_blocks(support, cv)
+                shapes = []
+                for t in tiles:
+                    if t == "flat":
+                        shapes.append((0, 0))
+                    elif t == "rect":
+                        wgu = min(nu, 16)
+                        shapes.append((wgu, min(nv, max(1, 64 // wgu))))
+                for wgu, wgv in shapes:
+                    for vpw in vis_per_wg:
+                        out.append(B.GrTuning(cu, cv, wgu, wgv, vpw, 1))
     if 2 in variants and support <= 56:
         for sl in SEG_LENS:
             out.append(B.GrTuning(0, 0, 0, 0, sl, 2))
     return out
+
+
+def describe(t: B.GrTuning) -> str:
+    """Short text key of a tuning (for sweep reports)."""
+    if t.variant == 1:
+        tile = "flat" if t.wg_u == 0 else f"{t.wg_u}x{t.wg_v}"
+        return f"valu c{t.cu}x{t.cv} tile {tile} vis {t.vis_per_wg or 'eq'}"
+    return f"mfma seg {t.vis_per_wg or 'default'}" + (f" rg {t.wg_v}" if t.wg_v else "")
 
 
 def memo_key(device_name: str, n_pol: int, support: int, kind: str, tap_dtype: int, side: int,

@@ -202,11 +202,15 @@ def tiny_kb_workload(seed: int = 0) -> Workload:
 
 def full_shape_workload(support: int, seed: int = 0, n_baselines: Optional[int] = None,
                         n_times: int = 1024, n_chan: int = 16, grid: int = 4096,
-                        n_planes: int = 32, n_pol: int = 4, n_ant: int = 64) -> Workload:
+                        n_planes: int = 32, n_pol: int = 4, n_ant: int = 64,
+                        order: str = "btc") -> Workload:
     """64 antennas (2016 baselines) x 1024 dumps over 8 h x 16 channels across
     1.4 GHz +/- 5 %, four polarisations, 4096^2 grid, complex separable W
     kernel with ``support`` taps, 32 w-planes, oversampling 8.  Visibilities are
-    ordered by baseline, then time, then channel.
+    ordered by baseline, then time, then channel (``order="btc"``), or by
+    baseline, then channel, then time (``order="bct"``: the same visibilities,
+    each with its own value, permuted so that consecutive ones are consecutive
+    dumps of one channel).
 
     ``n_baselines`` keeps only the first baselines (same tracks, fewer rows) for
     tests that need the real geometry at a smaller size; the scale factors are
@@ -222,7 +226,14 @@ def full_shape_workload(support: int, seed: int = 0, n_baselines: Optional[int] 
         flat, vis = uvw_full[:n_rows], vis_full[:n_rows]
     else:
         flat, vis = uvw_full, vis_full
-    return Workload(f"full-shape-S{support}", flat, vis, None, grid, grid, support, 8, s, s,
+    if order == "bct":
+        n_bl = flat.shape[0] // (n_times * n_chan)
+        flat = np.ascontiguousarray(flat.reshape(n_bl, n_times, n_chan, 3).transpose(0, 2, 1, 3).reshape(-1, 3))
+        vis = np.ascontiguousarray(vis.reshape(n_bl, n_times, n_chan, n_pol).transpose(0, 2, 1, 3)
+                                   .reshape(-1, n_pol))
+    elif order != "btc":
+        raise ValueError(f"unknown order {order}")
+    return Workload(f"full-shape-S{support}-{order}", flat, vis, None, grid, grid, support, 8, s, s,
                     n_planes=n_planes, w_min=w_min, inv_dw=inv_dw, w_hat_scale=w_hat_scale,
                     kernel="wsep", beta=8.6, support_aa=8)
 
