@@ -3,7 +3,13 @@ accumulation, against the FP64 oracle.
 
 Two errors are reported per case:
   * accuracy: against the oracle with exact FP64 taps and the original
-    complex64 visibilities (the bound is 1e-3 relative L2 for FP16 taps);
+    complex64 visibilities, bound 1e-3 relative L2 for both tap types.  FP16
+    taps meet it.  BF16 taps (8-bit significand, unit roundoff 2^-9) do not:
+    the product of two rounded separable taps carries a relative error of
+    about 1.6e-3 per tap, and the grids measure 1.6e-3 (KB, tiny config) to
+    2.9e-3 (W kernels).  Those cases are strict expected failures that raise
+    AccuracyAboveBound, so a parity failure still fails the test and a BF16
+    result that met the bound would be reported;
   * parity: against the oracle fed the same rounded taps (FP64 -> FP32 ->
     FP16/BF16, the GPU generator's conversion) and the dequantised
     visibilities, which isolates the FP32 accumulation (bound 1e-5).
@@ -21,7 +27,27 @@ from synth import (dequantize_vis_f16, full_shape_workload, quantize_vis_f16,  #
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
-ACCURACY_BOUND = {"f16": 1e-3, "bf16": 5e-3}
+ACCURACY_BOUND = 1e-3
+
+
+class AccuracyAboveBound(Exception):
+    """Relative L2 against the exact-tap oracle above ACCURACY_BOUND."""
+
+
+def _check_accuracy(acc):
+    if acc > ACCURACY_BOUND:
+        raise AccuracyAboveBound(f"relative L2 {acc:.3e} > {ACCURACY_BOUND:.0e}")
+
+
+def _bf16(measured):
+    return pytest.param("bf16", marks=pytest.mark.xfail(
+        strict=True, raises=AccuracyAboveBound,
+        reason=f"BF16 taps measure {measured} relative L2, above the 1e-3 bound"))
+
+
+KINDS_POINTS = ["f16", _bf16("2.46e-3 to 2.47e-3")]
+KINDS_TINY = ["f16", _bf16("1.65e-3")]
+KINDS_FULL = ["f16", _bf16("2.84e-3 to 2.85e-3")]
 
 
 def _say(msg):
@@ -77,7 +103,7 @@ def _run(R, wl, kind, vis16, variant):
     return g, enc
 
 
-@pytest.mark.parametrize("kind", ["f16", "bf16"])
+@pytest.mark.parametrize("kind", KINDS_POINTS)
 @pytest.mark.parametrize("vis16", [False, True])
 @pytest.mark.parametrize("variant", [1, 2])
 def test_points_reduced_precision(R, kind, vis16, variant):
@@ -92,10 +118,10 @@ def test_points_reduced_precision(R, kind, vis16, variant):
     par = _rel_l2(got, _oracle(wl, _round_like_gpu(t64, kind), vis_used))
     _say(f"    accuracy {acc:.3e}  parity {par:.3e}")
     assert par <= 1e-5
-    assert acc <= ACCURACY_BOUND[kind]
+    _check_accuracy(acc)
 
 
-@pytest.mark.parametrize("kind", ["f16", "bf16"])
+@pytest.mark.parametrize("kind", KINDS_TINY)
 def test_tiny_config_reduced_precision(R, kind):
     wl = tiny_kb_workload()
     _say(f"reduced precision tiny KB config: taps {kind}, fp16 vis")
@@ -105,11 +131,12 @@ def test_tiny_config_reduced_precision(R, kind):
     acc = _rel_l2(got, _oracle(wl, t64, wl.vis))
     par = _rel_l2(got, _oracle(wl, _round_like_gpu(t64, kind), dequantize_vis_f16(*enc)))
     _say(f"    accuracy {acc:.3e}  parity {par:.3e}")
-    assert par <= 1e-5 and acc <= ACCURACY_BOUND[kind]
+    assert par <= 1e-5
+    _check_accuracy(acc)
 
 
 @pytest.mark.parametrize("S", [16, 32])
-@pytest.mark.parametrize("kind", ["f16", "bf16"])
+@pytest.mark.parametrize("kind", KINDS_FULL)
 def test_full_shape_reduced_precision(R, c_oracle, S, kind):
     """The full 33M-visibility quad-pol 4096^2 workload with FP16/BF16 taps and
     scaled-FP16 visibilities, default launch; accuracy on sampled rows."""
@@ -123,4 +150,4 @@ def test_full_shape_reduced_precision(R, c_oracle, S, kind):
     t64 = _taps64(wl)
     acc = _rel_l2(got, _oracle(wl, t64, wl.vis, rows, c_oracle))
     _say(f"    S={S} {kind}: sampled-row accuracy {acc:.3e}")
-    assert acc <= ACCURACY_BOUND[kind]
+    _check_accuracy(acc)
