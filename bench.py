@@ -306,8 +306,7 @@ def wstack_leg(dev, stream, reps: int) -> dict:
         off = offs.cpu().numpy()
         sizes = [int(off[s + 1] - off[s]) for s in range(n_sl)]
         grids = torch.zeros((n_sl, P, wl.height, wl.width), dtype=torch.complex64, device=dev)
-        kernels = [runner.slice_kernel(dw.kernel, runner.slice_w_min(m["w_first"], m["inv_width"], s, wl.w_min))
-                   for s in range(n_sl)]
+        kernels = [B.gr_wslice_kernel(dw.kernel, m["w_first"], m["inv_width"], s) for s in range(n_sl)]
         items = [B.make_batch_item(uvw_p[int(off[s]):], vis_p[int(off[s]):], B.GR_F32, P, None, None, sizes[s],
                                    kernels[s], wl.inv_cell_u, wl.inv_cell_v, grids[s], wl.height, wl.width)
                  for s in range(n_sl)]
@@ -537,25 +536,36 @@ def batch_leg(dev, stream, reps: int) -> dict:
     return out
 
 
-def _romein_tuning(dw, n_baselines: int = 256, reps: int = 2, quick: bool = False):
-    """Coarsening and work-group shape of the VALU kernel from the autotuner,
-    timed on the first ``n_baselines`` baselines' worth of the workload (2016
-    baselines in all); ``quick``: flat tiles and equal ranges only."""
+_FIXED_ROMEIN = None   # --romein-tuning: one VALU-kernel configuration instead of a sweep
+
+
+def _romein_tuning(dw, n_baselines: int = 2016, reps: int = 2, quick: bool = False):
+    """Coarsening, block order and chunk length of the VALU kernel from the
+    autotuner, timed on the first ``n_baselines`` baselines' worth of the
+    workload (2016 baselines in all: the whole set by default, since the
+    kernel's parallelism is chunks x residues and a subset shortens every
+    chunk); ``quick``: row-by-row block order and equal chunks only."""
     import copy
     from paper_1605_07023_amd import autotune, runner
+    if _FIXED_ROMEIN is not None:
+        return _FIXED_ROMEIN, {}
     wl = dw.wl
     n = min(wl.n_vis, n_baselines * max(1, wl.n_vis // 2016))
-    small = copy.copy(wl)
-    small.uvw, small.vis = wl.uvw[:n], wl.vis[:n]
-    sdw = runner.upload(small, dw.uvw.device, taps=dw.taps)
-    sdw.kernel = dw.kernel
+    if n < wl.n_vis:
+        small = copy.copy(wl)
+        small.uvw, small.vis = wl.uvw[:n], wl.vis[:n]
+        sdw = runner.upload(small, dw.uvw.device, taps=dw.taps)
+        sdw.kernel = dw.kernel
+    else:
+        sdw = dw
     cands = autotune.candidates(wl.n_pol, wl.support, variants=(1,),
-                                **(dict(tiles=("flat",), vis_per_wg=(0,)) if quick else {}))
+                                **(dict(tiles=("flat",), vis_per_wg=(0,)) if quick else
+                                   dict(tiles=("flat",), vis_per_wg=(0, 512, 1024, 2048))))
     best, times = autotune.tune(sdw, cands, reps=reps)
     return best, {autotune.describe(c): round(t, 4) for c, t in zip(cands, times)}
 
 
-def order_leg(dev, stream, reps: int) -> dict:
+def order_leg(dev, stream, reps: int, supports=(16, 32)) -> dict:
     """The full-shape visibilities in two orders: baseline, time, channel (the
     timed step's order) and baseline, channel, time (consecutive visibilities
     are consecutive dumps of one channel).  Per support: the whole binned MFMA
@@ -568,7 +578,7 @@ def order_leg(dev, stream, reps: int) -> dict:
                        "(baseline, time, channel) and (baseline, channel, time) order", "per_order": {}}
     for order in ("btc", "bct"):
         res = {}
-        for S in (16, 32):
+        for S in supports:
             wl = full_shape_workload(S, order=order)
             dw = runner.upload(wl, dev)
             g = torch.zeros((wl.n_pol, wl.height, wl.width), dtype=torch.complex64, device=dev)
@@ -578,7 +588,7 @@ def order_leg(dev, stream, reps: int) -> dict:
             ws = torch.empty(nw, dtype=torch.uint8, device=dev)
             t_mfma = _timed(stream, lambda: runner.grid(dw, g, t2, ws, stream=stream), reps)
             del ws
-            best, sweep = _romein_tuning(dw, n_baselines=32, quick=True)
+            best, sweep = _romein_tuning(dw, n_baselines=64, quick=True)
             nw1 = B.gr_grid_workspace_bytes(wl.n_vis, wl.n_pol, dw.kernel, wl.height, wl.width, best)
             ws1 = torch.empty(nw1, dtype=torch.uint8, device=dev)
             t_val = _timed(stream, lambda: runner.grid(dw, g, best, ws1, stream=stream), 1 if order == "btc" else reps)
@@ -595,7 +605,7 @@ def order_leg(dev, stream, reps: int) -> dict:
 
 
 
-def romein_tracks_leg(dev, stream, reps: int) -> dict:
+def romein_tracks_leg(dev, stream, reps: int, supports=(16, 32)) -> dict:
     """The paper's own method (variant 1: Romein work distribution with thread
     coarsening on the vector units, FP32 atomic flushes) beside the MFMA path on
     the paper-like single-channel tracks (2016 baselines x 3600 dumps of 2 s,
@@ -607,7 +617,7 @@ def romein_tracks_leg(dev, stream, reps: int) -> dict:
     from synth import compression_workload
     out = {"workload": "2016 baselines x 3600 dumps of 2 s over 2 h, 1 channel at 1.4 GHz, quad pol, 2048^2, "
                        "separable W kernel, 32 planes, oversampling 8 (uncompressed)", "per_support": {}}
-    for S in (16, 32):
+    for S in supports:
         wl = compression_workload(support=S)
         dw = runner.upload(wl, dev)
         g = torch.zeros((wl.n_pol, wl.height, wl.width), dtype=torch.complex64, device=dev)
@@ -716,6 +726,12 @@ def main() -> int:
                     help="skip the batch leg (32 uneven instances, one graph launch)")
     ap.add_argument("--no-order", action="store_true",
                     help="skip the order leg ((baseline, channel, time) against (baseline, time, channel))")
+    ap.add_argument("--only", default="",
+                    help="run only these legs (comma list of compression, wstack, aterm, batch, order, "
+                         "romein_tracks), without the timed step, and print their JSON (for profiling)")
+    ap.add_argument("--romein-tuning", default="",
+                    help="cu,cv,wg_u,wg_v,vis_per_wg of the VALU kernel in the romein_tracks and order legs "
+                         "(given: no sweep; for profiling one configuration)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this size before timing "
                          "(reference dispatch for HBM byte counters)")
@@ -734,6 +750,30 @@ def main() -> int:
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    global _FIXED_ROMEIN
+    if args.romein_tuning:
+        f = [int(x) for x in args.romein_tuning.split(",")]
+        _FIXED_ROMEIN = B.GrTuning(*(f + [0] * (5 - len(f)))[:5], 1)
+    if args.only:
+        supports = tuple(int(x) for x in args.supports.split(","))
+        legs = {"compression": lambda st: compression_leg(dev, st, reps=5),
+                "wstack": lambda st: wstack_leg(dev, st, reps=5),
+                "aterm": lambda st: aterm_leg(dev, st, reps=3),
+                "batch": lambda st: batch_leg(dev, st, reps=5),
+                "order": lambda st: order_leg(dev, st, reps=3, supports=supports),
+                "romein_tracks": lambda st: romein_tracks_leg(dev, st, reps=3, supports=supports)}
+        names = [n for n in args.only.split(",") if n]
+        unknown = [n for n in names if n not in legs]
+        if unknown:
+            print(json.dumps({"error": f"unknown legs {unknown}", "legs": sorted(legs)}), flush=True)
+            return 2
+        stream = torch.cuda.current_stream(dev)
+        out = {"only": names}
+        for n in names:
+            log(f"leg {n}")
+            out[n] = legs[n](stream)
+        print(json.dumps(out), flush=True)
+        return 0
     supports = [int(s) for s in args.supports.split(",")]
     log("generating inputs")
     wls = {S: full_shape_workload(S) for S in supports}

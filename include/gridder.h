@@ -75,11 +75,25 @@ typedef struct {
  * Section 4).  Any field <= 0 selects the library default for it.
  *   cu, cv      thread-coarsening factors: each work-item owns a cu x cv block
  *               of cells (Section 3); 1, 2, 4 or 8
- *   wg_u, wg_v  tile shape in blocks handled by one wave (Section 2.2 tiles)
- *   vis_per_wg  visibilities per work-group (Section 4 uses 1024) for the VALU
- *               kernel; maximum segment length for the binned MFMA kernel
+ *   wg_u, wg_v  VALU kernel: the bin's blocks are visited in tiles of
+ *               wg_u x wg_v blocks (Section 2.2 tiles; u first, edge tiles
+ *               clipped), and consecutive work-items of a visibility chunk
+ *               take consecutive blocks in that order; <= 64 each (default:
+ *               the whole bin, row by row).  MFMA kernel, with variant = 2
+ *               given explicitly: wg_v is the number of 4-row (n_pol = 4) or
+ *               16-row (n_pol = 1) groups of the window one wave accumulates
+ *               (the work-group shape of the wave form: 2, 4 or 8 for the
+ *               32-cell window, 2, 3, 4 or 6 for 48, 2 or 4 for 64 at
+ *               n_pol = 4; 1 or 2, 1 or 3, 1, 2 or 4 at n_pol = 1); other
+ *               values give GR_EUNSUPPORTED
+ *   vis_per_wg  visibilities per work-item chunk (Section 4 uses 1024 per
+ *               work-group; default: equal chunks, about four 64-lane runs
+ *               per wave) for the VALU kernel; maximum segment length for the
+ *               binned MFMA kernel
  *   variant     0 = library choice, 1 = VALU work-item kernel on the input
- *               order (gr_grid_records), 2 = MFMA kernel on the binned stream */
+ *               order (gr_grid_records), 2 = MFMA kernel on the binned stream
+ * A NULL tuning means the library's tuning memo (gr_tuning_memo_put), else
+ * the defaults. */
 typedef struct {
   int32_t cu, cv, wg_u, wg_v, vis_per_wg, variant;
 } gr_tuning;
@@ -112,11 +126,13 @@ gr_status gr_preprocess(const double* uvw, const void* vis, int32_t vis_dtype,
 /* Grid preprocessed visibilities (records/wvis from gr_preprocess, in the same
  * order as the input) onto grid, complex64 [n_pol][height][width], which is
  * ACCUMULATED into (+=).  This is the Romein work distribution with thread
- * coarsening (Sections 2.2-4): work-groups take fixed chunks of consecutive
- * visibilities x tiles of the bin; each work-item keeps a register block of
+ * coarsening (Sections 2.2-4): one work-item per (chunk of consecutive
+ * visibilities, residue of the bin); each keeps a register block of
  * cu x cv cells per polarisation and flushes it with atomic adds when the
- * block leaves the bounding box, and at the end of the chunk.
- * tuning may be NULL (defaults). */
+ * block leaves the bounding box, and at the end of the chunk.  One block per
+ * compute unit stages the tap table in LDS once.  tuning may be NULL (the
+ * memo's slot 1 entry for this problem class, else defaults); cu * cv * n_pol
+ * <= 64. */
 gr_status gr_grid_records(const void* records, const void* wvis, int64_t n_vis, int32_t n_pol,
                           const gr_kernel* kernel, void* grid, int32_t height, int32_t width,
                           const gr_tuning* tuning, void* stream);
@@ -177,8 +193,9 @@ gr_status gr_preprocess_bin(const double* uvw, const void* vis, int32_t vis_dtyp
  * support <= 56; the FP32 tap table [planes][O][S + 2] as (Re, Im) pairs plus
  * 12 KiB of staging must fit in 160 KiB.
  * With a GR_TABLE2D kernel the non-separable taps are read per visibility
- * from the [planes][O][O][S][S] table instead: each work-item keeps a 4 x 4
- * block of the window per polarisation in registers.  With a GR_MLP kernel
+ * from the [planes][O][O][S][S] table instead: one 256-work-item block per
+ * segment keeps the window in registers, C x C cells per polarisation and
+ * work-item (C = window / 16).  With a GR_MLP kernel
  * the block evaluates each visibility's S x S taps with the network into LDS
  * first (FP16 matrix-core layers, FP32 accumulation), then updates the window
  * the same way. */
@@ -221,6 +238,16 @@ gr_status gr_compress(const void* records, const void* wvis, int64_t n_vis, int3
  * pointing into the outputs) with the kernel's w_min moved to that slice.
  * No host synchronisation.  workspace: gr_wslice_partition_workspace_bytes. */
 size_t gr_wslice_partition_workspace_bytes(int64_t n_vis, int32_t n_slices);
+
+/* The GCF descriptor of W-stacking slice `slice` (Section 5: each slice has
+ * its own GCF for the w offset from the slice's centre): *out is a copy of
+ * *table, whose plane rule is relative to the centre, with w_min moved there,
+ *   out->w_min = w_first + (slice + 1/2) / inv_width + table->w_min   (FP64),
+ * so that plane = rint((w - out->w_min) * inv_dw) for the slice's
+ * visibilities.  w_first and inv_width as gr_wslice_partition; 0 <= slice <=
+ * 254.  Host-only. */
+gr_status gr_wslice_kernel(const gr_kernel* table, double w_first, double inv_width, int32_t slice,
+                           gr_kernel* out);
 gr_status gr_wslice_partition(const double* uvw, const void* vis, const float* weights, int64_t n_vis,
                               int32_t n_pol, double w_first, double inv_width, int32_t n_slices,
                               double* uvw_out, void* vis_out, float* weights_out, int64_t* slice_offsets,
@@ -279,14 +306,17 @@ gr_status gr_degrid(const double* uvw, int64_t n_vis, int32_t n_pol, const gr_ke
                     size_t workspace_bytes, int64_t* dev_stats, void* stream);
 
 /* Bytes of workspace gr_grid needs (depends on the variant gr_grid selects
- * for these arguments; 0 if they are invalid). */
+ * for these arguments, a NULL tuning read from the memo as gr_grid does; 0
+ * if they are invalid). */
 size_t gr_grid_workspace_bytes(int64_t n_vis, int32_t n_pol, const gr_kernel* kernel,
                                int32_t height, int32_t width, const gr_tuning* tuning);
 
-/* The whole hot path: either gr_preprocess into `workspace` then
- * gr_grid_records (variant 1), or gr_preprocess_bin into `workspace` then
+/* The whole hot path: either gr_preprocess into `workspace` then the kernel
+ * of gr_grid_records (variant 1; its waves take their work in turn from a
+ * counter at the end of the workspace), or gr_preprocess_bin into `workspace` then
  * gr_grid_binned (variant 2; chosen by default when the kernel allows it).
- * Same semantics as those calls. */
+ * Same semantics as those calls.  A NULL tuning takes the memo's slot 0
+ * entry for this problem class (gr_tuning_memo_put), else the defaults. */
 gr_status gr_grid(const double* uvw, const void* vis, int32_t vis_dtype, const float* vis_scale,
                   const float* weights, int64_t n_vis, int32_t n_pol, const gr_kernel* kernel,
                   double inv_cell_u, double inv_cell_v, void* grid, int32_t height,
@@ -301,13 +331,32 @@ gr_status gr_grid(const double* uvw, const void* vis, int32_t vis_dtype, const f
  * after one warm-up, accumulating into `grid` (scratch: its contents become
  * meaningless).  times_ms[c] receives the mean time (+inf when the candidate
  * is unsupported); *best the fastest index.  Unlike every other entry point
- * this one SYNCHRONISES `stream` (once per candidate).  The memo of chosen
- * tunings is kept by the caller. */
+ * this one SYNCHRONISES `stream` (once per candidate).  The winner is stored
+ * in the tuning memo for (n_pol, kernel, height, width): slot 0 (with its
+ * variant made explicit), and the fastest variant-1 candidate in slot 1. */
 gr_status gr_autotune(const void* records, const void* wvis, int64_t n_vis, int32_t n_pol,
                       const gr_kernel* kernel, void* grid, int32_t height, int32_t width,
                       void* bins, size_t bins_bytes, const gr_tuning* candidates,
                       int32_t n_candidates, int32_t reps, float* times_ms, int32_t* best,
                       void* stream);
+
+/* The library's tuning memo (Section 4: the autotuner's choice is remembered
+ * and used again).  An entry is keyed by the current device, n_pol, the
+ * kernel's kind, taps_complex, tap_dtype and support, the grid's side class
+ * (the power of two >= max(height, width)) and a slot: slot 0 is read by
+ * gr_grid and gr_grid_workspace_bytes, slot 1 by gr_grid_records, when their
+ * tuning is NULL.  gr_autotune writes both; gr_tuning_memo_put writes one
+ * (slot 1 takes variant 0 or 1).  gr_tuning_memo_get copies an entry to *out
+ * (GR_EINVAL when there is none).  Entries last until gr_tuning_memo_clear
+ * or the end of the process; callers that keep tunings across processes
+ * read them out and put them back.  Host-only (the kernel's taps pointer is
+ * not used), thread-safe; a change of the memo between
+ * gr_grid_workspace_bytes and gr_grid can make gr_grid report GR_ENOMEM. */
+gr_status gr_tuning_memo_put(int32_t n_pol, const gr_kernel* kernel, int32_t height, int32_t width,
+                             int32_t slot, const gr_tuning* tuning);
+gr_status gr_tuning_memo_get(int32_t n_pol, const gr_kernel* kernel, int32_t height, int32_t width,
+                             int32_t slot, gr_tuning* out);
+void gr_tuning_memo_clear(void);
 
 /* Kaiser-Bessel taps (real, one plane), evaluated in FP64 on the device and
  * stored as out_dtype (GR_F64, GR_F32, GR_F16 or GR_BF16), layout [O][S]:

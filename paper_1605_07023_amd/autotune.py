@@ -1,12 +1,14 @@
-"""Autotuning driver and memo (Merry 2016, Section 4: the coarsening factors and
-work-group shape are picked by timing a synthetic problem, per polarisation
-count, and the winner is kept for later runs).
+"""Autotuning driver and memo (Merry 2016, Section 4: the work decomposition --
+coarsening factors and work-group shape -- is chosen by timing a synthetic
+problem, per polarisation count, and the choice is kept for later runs).
 
-The timing sweep runs in the library (gr_autotune); this module builds the
-candidate list, prepares the small data set on the device, and keeps the memo
-of chosen tunings as JSON.  The memo key is
+The timing sweep runs in the library (gr_autotune), which also keeps the
+winner in its in-process tuning memo: calls without a tuning then use it.
+This module builds the candidate list, prepares the small data set on the
+device, and keeps the memo across processes as JSON (Memo.save / Memo.install
+move entries between the file and the library).  The file's key is
 (device name, n_pol, support, tap kind, tap dtype, grid side class, variant
-set).  A missing or unreadable memo falls back to the library defaults.
+set).  A missing or unreadable file leaves the library defaults.
 """
 from __future__ import annotations
 
@@ -32,17 +34,33 @@ def _bin_blocks(support: int, c: int) -> int:
     return (support + 2 * c - 2) // c
 
 
+def _window(support: int) -> int:
+    return 32 if support <= 16 else 48 if support <= 32 else 64
+
+
+def row_group_options(n_pol: int, support: int) -> Tuple[int, ...]:
+    """Row groups per wave the MFMA gridder's wave form is built for (per window)."""
+    w = _window(support)
+    if n_pol == 4:
+        return {32: (2, 4, 8), 48: (2, 3, 4, 6), 64: (2, 4)}[w]
+    return {32: (1, 2), 48: (1, 3), 64: (1, 2, 4)}[w]
+
+
 def candidates(n_pol: int, support: int, variants: Iterable[int] = (1, 2),
                vis_per_wg: Iterable[int] = (0, 1024),
-               tiles: Iterable[str] = ("flat", "rect")) -> List[B.GrTuning]:
+               tiles: Iterable[str] = ("flat", "rect"),
+               seg_lens: Iterable[int] = SEG_LENS,
+               row_groups: Optional[Iterable[int]] = None) -> List[B.GrTuning]:
     """Work decompositions to try.
 
     variant 1 (the VALU work-item kernel): coarsening cu x cv in {1, 2, 4, 8}^2
     (the paper's range) with cu * cv * n_pol <= 64 (register budget); for each,
-    the wave's tile ("flat": 64 consecutive blocks of the bin, "rect": a
-    rectangle of up to 16 blocks along u and as many rows as fill 64 lanes) and
-    the visibilities per item (0: equal ranges, one item per wave; 1024: the
-    paper's fixed chunk).  variant 2 (MFMA kernel): segment lengths SEG_LENS."""
+    the order in which a chunk's work-items take the bin's blocks ("flat": row
+    by row over the whole bin, "rect": tiles of up to 16 blocks along u and as
+    many rows as make 64) and the visibilities per chunk (0: equal chunks, about
+    four 64-lane runs per wave; 1024: the paper's chunk).  variant 2 (MFMA
+    kernel): segment lengths x row groups per wave (the wave form's work-group
+    shape; None: every option of the window)."""
     out = []
     if 1 in variants:
         for cu in COARSEN:
@@ -61,8 +79,10 @@ def candidates(n_pol: int, support: int, variants: Iterable[int] = (1, 2),
                     for vpw in vis_per_wg:
                         out.append(B.GrTuning(cu, cv, wgu, wgv, vpw, 1))
     if 2 in variants and support <= 56:
-        for sl in SEG_LENS:
-            out.append(B.GrTuning(0, 0, 0, 0, sl, 2))
+        rgs = tuple(row_groups) if row_groups is not None else row_group_options(n_pol, support)
+        for sl in seg_lens:
+            for rg in rgs:
+                out.append(B.GrTuning(0, 0, 0, rg, sl, 2))
     return out
 
 
@@ -78,6 +98,11 @@ def memo_key(device_name: str, n_pol: int, support: int, kind: str, tap_dtype: i
              variants: Iterable[int]) -> str:
     side_class = 1 << max(0, (int(side) - 1).bit_length())
     return f"{device_name}|P{n_pol}|S{support}|{kind}|t{tap_dtype}|g{side_class}|v{''.join(map(str, sorted(variants)))}"
+
+
+def _c_class(n_pol: int, kernel: B.GrKernel, side: int, slot: int) -> list:
+    """What the library's memo needs to rebuild an entry's key."""
+    return [n_pol, kernel.kind, kernel.taps_complex, kernel.tap_dtype, kernel.support, int(side), slot]
 
 
 class Memo:
@@ -108,9 +133,32 @@ class Memo:
         except (TypeError, ValueError):
             return None
 
-    def put(self, key: str, tuning: B.GrTuning, time_ms: float) -> None:
-        self.data[key] = {"tuning": [tuning.cu, tuning.cv, tuning.wg_u, tuning.wg_v,
-                                     tuning.vis_per_wg, tuning.variant], "time_ms": time_ms}
+    def put(self, key: str, tuning: B.GrTuning, time_ms: float, c_class: Optional[list] = None) -> None:
+        e = {"tuning": [tuning.cu, tuning.cv, tuning.wg_u, tuning.wg_v, tuning.vis_per_wg, tuning.variant],
+             "time_ms": time_ms}
+        if c_class is not None:
+            e["c_class"] = list(c_class)
+        self.data[key] = e
+
+    def install(self, device_name: str) -> int:
+        """Put this device's entries into the library's tuning memo (calls
+        without a tuning then use them); returns how many were installed."""
+        n = 0
+        for key, e in self.data.items():
+            cc = e.get("c_class")
+            if not key.startswith(device_name + "|") or not isinstance(cc, list) or len(cc) != 7:
+                continue
+            t = self.get(key)
+            if t is None:
+                continue
+            n_pol, kind, cplx, dtype, support, side, slot = (int(x) for x in cc)
+            k = B.GrKernel(kind, dtype, cplx, support, 8, 1, 0.0, 1.0, None)
+            try:
+                B.gr_tuning_memo_put(n_pol, k, side, side, slot, t)
+                n += 1
+            except B.GridderError as err:
+                print(f"[autotune] memo entry {key} not installed: {err}", file=sys.stderr)
+        return n
 
     def save(self) -> None:
         d = os.path.dirname(self.path)
@@ -139,15 +187,19 @@ def tune(dw: runner.DeviceWorkload, cands: List[B.GrTuning], reps: int = 3,
 
 
 def tune_and_remember(dw: runner.DeviceWorkload, variants: Iterable[int] = (2,), reps: int = 3,
-                      memo: Optional[Memo] = None, vis_per_wg: Iterable[int] = (1024,)) -> B.GrTuning:
-    """Tune on the given (small) workload and store the winner in the memo."""
+                      memo: Optional[Memo] = None, vis_per_wg: Iterable[int] = (0, 1024)) -> B.GrTuning:
+    """Tune on the given (small) workload; the library keeps the winner for
+    calls without a tuning, and the memo keeps it for later processes."""
     wl = dw.wl
     memo = memo if memo is not None else Memo()
     cands = candidates(wl.n_pol, wl.support, variants, vis_per_wg)
     best, times = tune(dw, cands, reps)
     name = torch.cuda.get_device_name(dw.uvw.device)
-    key = memo_key(name, wl.n_pol, wl.support, wl.kernel, dw.tap_dtype, max(wl.height, wl.width), variants)
-    memo.put(key, best, min(times))
+    side = max(wl.height, wl.width)
+    key = memo_key(name, wl.n_pol, wl.support, wl.kernel, dw.tap_dtype, side, variants)
+    side_class = 1 << max(0, (int(side) - 1).bit_length())
+    slot = 1 if set(variants) == {1} else 0          # a VALU-only sweep feeds gr_grid_records
+    memo.put(key, best, min(times), _c_class(wl.n_pol, dw.kernel, side_class, slot))
     return best
 
 

@@ -120,6 +120,14 @@ def load_library():
     lib.gr_mlp_blob_floats.restype = I32
     lib.gr_version.argtypes = []
     lib.gr_version.restype = I32
+    lib.gr_tuning_memo_put.argtypes = [I32, KP, I32, I32, I32, TP]
+    lib.gr_tuning_memo_put.restype = ctypes.c_int
+    lib.gr_tuning_memo_get.argtypes = [I32, KP, I32, I32, I32, TP]
+    lib.gr_tuning_memo_get.restype = ctypes.c_int
+    lib.gr_tuning_memo_clear.argtypes = []
+    lib.gr_tuning_memo_clear.restype = None
+    lib.gr_wslice_kernel.argtypes = [KP, D, D, I32, KP]
+    lib.gr_wslice_kernel.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -151,6 +159,33 @@ def gr_version() -> int:
 
 def gr_last_error() -> str:
     return load_library().gr_last_error().decode()
+
+
+def gr_tuning_memo_put(n_pol: int, kernel: GrKernel, height: int, width: int, slot: int,
+                       tuning: GrTuning) -> None:
+    _check(load_library().gr_tuning_memo_put(n_pol, ctypes.byref(kernel), height, width, slot,
+                                             ctypes.byref(tuning)))
+
+
+def gr_tuning_memo_get(n_pol: int, kernel: GrKernel, height: int, width: int, slot: int) -> Optional[GrTuning]:
+    """The memo's entry, or None when there is none."""
+    out = GrTuning()
+    st = load_library().gr_tuning_memo_get(n_pol, ctypes.byref(kernel), height, width, slot, ctypes.byref(out))
+    if st == GR_EINVAL and "no entry" in gr_last_error():
+        return None
+    _check(st)
+    return out
+
+
+def gr_tuning_memo_clear() -> None:
+    load_library().gr_tuning_memo_clear()
+
+
+def gr_wslice_kernel(table: GrKernel, w_first: float, inv_width: float, slice_index: int) -> GrKernel:
+    out = GrKernel()
+    _check(load_library().gr_wslice_kernel(ctypes.byref(table), w_first, inv_width, slice_index,
+                                           ctypes.byref(out)))
+    return out
 
 
 def gr_grid_workspace_bytes(n_vis: int, n_pol: int, kernel: GrKernel, height: int, width: int,

@@ -1,4 +1,5 @@
 // C-ABI entry points: host-side validation, workspace layout, dispatch.
+#include <algorithm>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -87,9 +88,60 @@ extern "C" const char* gr_last_error(void) { return g_last_error.c_str(); }
 
 extern "C" int32_t gr_version(void) { return 1; }
 
+namespace gr {
+
+// ---- tuning memo: the autotuner's winners, per device and problem class
+namespace {
+struct MemoKey {
+  int dev, n_pol, kind, cplx, dtype, support, side, slot;
+  bool operator<(const MemoKey& o) const {
+    const int a[8] = {dev, n_pol, kind, cplx, dtype, support, side, slot};
+    const int b[8] = {o.dev, o.n_pol, o.kind, o.cplx, o.dtype, o.support, o.side, o.slot};
+    for (int i = 0; i < 8; ++i)
+      if (a[i] != b[i]) return a[i] < b[i];
+    return false;
+  }
+};
+std::mutex g_memo_mu;
+std::map<MemoKey, gr_tuning> g_memo;
+
+MemoKey memo_key(int n_pol, const gr_kernel& k, int height, int width, int slot) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+  int side = 1;
+  while (side < std::max(height, width)) side <<= 1;
+  return MemoKey{dev, n_pol, k.kind, k.taps_complex != 0, k.tap_dtype, k.support, side, slot};
+}
+}  // namespace
+
+void memo_store(int n_pol, const gr_kernel& k, int height, int width, int slot, const gr_tuning& t) {
+  std::lock_guard<std::mutex> lock(g_memo_mu);
+  g_memo[memo_key(n_pol, k, height, width, slot)] = t;
+}
+
+bool memo_find(int n_pol, const gr_kernel& k, int height, int width, int slot, gr_tuning* out) {
+  std::lock_guard<std::mutex> lock(g_memo_mu);
+  const auto it = g_memo.find(memo_key(n_pol, k, height, width, slot));
+  if (it == g_memo.end()) return false;
+  *out = it->second;
+  return true;
+}
+
+}  // namespace gr
+
 namespace {
 
 int seg_len_of(const gr_tuning* t) { return t && t->vis_per_wg > 0 ? t->vis_per_wg : kDefaultSegLen; }
+
+// the tuning a call uses: the caller's, else the memo's entry for the call's
+// class, else NULL (library defaults); `slot` 0 for gr_grid, 1 for gr_grid_records
+const gr_tuning* resolve_tuning(const gr_tuning* t, int n_pol, const gr_kernel& k, int height, int width,
+                                int slot, gr_tuning* buf) {
+  if (t != nullptr) return t;
+  return memo_find(n_pol, k, height, width, slot, buf) ? buf : nullptr;
+}
+
+bool valid_slot(int slot) { return slot == 0 || slot == 1; }
 
 // variant actually used by gr_grid: 1 = VALU work-item kernel on the input order,
 // 2 = MFMA kernel on the binned stream
@@ -108,15 +160,19 @@ size_t pre_bytes(int64_t n_vis, int n_pol) {
   return align256(sizeof(Record) * (size_t)n_vis) + align256(sizeof(float2) * (size_t)n_vis * n_pol);
 }
 
+// gr_grid's variant-1 workspace: the preprocessed stream, then the VALU
+// kernel's work counter
+size_t valu_ws_bytes(int64_t n_vis, int n_pol) { return pre_bytes(n_vis, n_pol) + 256; }
+
 }  // namespace
 
 namespace gr {
 // binned gridder for the kernel's kind
 gr_status launch_binned(const void* bins, const BinLayout& L, int n_pol, const gr_kernel& k,
-                        float2* grid, int height, int width, hipStream_t stream) {
+                        float2* grid, int height, int width, hipStream_t stream, int ng) {
   if (k.kind == GR_TABLE2D) return launch_table2d(bins, L, n_pol, k, grid, height, width, stream);
   if (k.kind == GR_MLP) return launch_grid_mlp(bins, L, n_pol, k, grid, height, width, stream);
-  return launch_mfma(bins, L, n_pol, k, grid, height, width, stream);
+  return launch_mfma(bins, L, n_pol, k, grid, height, width, stream, ng);
 }
 }  // namespace gr
 
@@ -136,12 +192,14 @@ extern "C" size_t gr_preprocess_bin_bytes(int64_t n_vis, int32_t n_pol, int32_t 
 extern "C" size_t gr_grid_workspace_bytes(int64_t n_vis, int32_t n_pol, const gr_kernel* kernel,
                                           int32_t height, int32_t width, const gr_tuning* tuning) {
   if (n_vis < 0 || n_pol < 1 || kernel == nullptr || height < 1 || width < 1) return 0;
+  gr_tuning memo_t;
+  tuning = resolve_tuning(tuning, n_pol, *kernel, height, width, 0, &memo_t);
   if (pick_variant(*kernel, n_pol, tuning) == 2) {   // fused preprocess and bin
     if (kernel->support > kMaxBinnedSupport) return 0;  // gr_grid refuses such a call
     return bin_layout(n_vis, n_pol, kernel->support, height, width, seg_len_of(tuning)).bytes +
            align256(sizeof(Record) * (size_t)n_vis);
   }
-  return pre_bytes(n_vis, n_pol);
+  return valu_ws_bytes(n_vis, n_pol);
 }
 
 namespace {
@@ -195,6 +253,8 @@ extern "C" gr_status gr_grid_records(const void* records, const void* wvis, int6
     return fail(GR_EUNSUPPORTED, "gr_grid_records runs the VALU work-item kernel (variant 0 or 1)");
   if (kernel->kind != GR_SEPARABLE)
     return fail(GR_EUNSUPPORTED, "gr_grid_records needs a separable kernel");
+  gr_tuning memo_t;
+  tuning = resolve_tuning(tuning, n_pol, *kernel, height, width, 1, &memo_t);
   RomeinPlan plan;
   if ((st = plan_romein(*kernel, n_pol, tuning, &plan)) != GR_OK) return st;
   return launch_romein(reinterpret_cast<const Record*>(records), reinterpret_cast<const float2*>(wvis),
@@ -388,6 +448,11 @@ extern "C" gr_status gr_degrid(const double* uvw, int64_t n_vis, int32_t n_pol, 
 
 extern "C" gr_status gr_grid_binned(const void* bins, int64_t n_vis, int32_t n_pol, const gr_kernel* kernel,
                                     int32_t seg_len, void* grid, int32_t height, int32_t width, void* stream) {
+  return grid_binned(bins, n_vis, n_pol, kernel, seg_len, grid, height, width, stream, 0);
+}
+
+gr_status gr::grid_binned(const void* bins, int64_t n_vis, int32_t n_pol, const gr_kernel* kernel, int32_t seg_len,
+                          void* grid, int32_t height, int32_t width, void* stream, int ng) {
   gr_status st = validate_kernel(kernel, true);
   if (st != GR_OK) return st;
   if ((st = validate_grid(n_pol, height, width, kernel->support)) != GR_OK) return st;
@@ -397,7 +462,7 @@ extern "C" gr_status gr_grid_binned(const void* bins, int64_t n_vis, int32_t n_p
   const BinLayout L = bin_layout(n_vis, n_pol, kernel->support, height, width,
                                  seg_len > 0 ? seg_len : kDefaultSegLen);
   return launch_binned(bins, L, n_pol, *kernel, reinterpret_cast<float2*>(grid), height, width,
-                       (hipStream_t)stream);
+                       (hipStream_t)stream, ng);
 }
 
 extern "C" gr_status gr_grid(const double* uvw, const void* vis, int32_t vis_dtype,
@@ -411,6 +476,8 @@ extern "C" gr_status gr_grid(const double* uvw, const void* vis, int32_t vis_dty
   if ((st = validate_grid(n_pol, height, width, kernel->support)) != GR_OK) return st;
   if (n_vis < 0) return fail(GR_EINVAL, "n_vis must be >= 0");
   if (grid == nullptr) return fail(GR_EINVAL, "grid is NULL");
+  gr_tuning memo_t;
+  tuning = resolve_tuning(tuning, n_pol, *kernel, height, width, 0, &memo_t);
   if (tuning && (tuning->variant < 0 || tuning->variant > 2))
     return fail(GR_EUNSUPPORTED, "tuning.variant not available in this build");
   const int variant = pick_variant(*kernel, n_pol, tuning);
@@ -434,8 +501,9 @@ extern "C" gr_status gr_grid(const double* uvw, const void* vis, int32_t vis_dty
     st = gr_preprocess(uvw, vis, vis_dtype, vis_scale, weights, n_vis, n_pol, kernel, inv_cell_u,
                        inv_cell_v, height, width, rec, wv, dev_stats, stream);
     if (st != GR_OK) return st;
+    auto* counter = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(workspace) + pre_bytes(n_vis, n_pol));
     return launch_romein(rec, wv, n_vis, n_pol, *kernel, reinterpret_cast<float2*>(grid), height, width,
-                         plan, (hipStream_t)stream);
+                         plan, (hipStream_t)stream, counter);
   }
   // binned path: preprocess and bin fused, then the binned gridder
   st = gr_preprocess_bin(uvw, vis, vis_dtype, vis_scale, weights, n_vis, n_pol, kernel, inv_cell_u, inv_cell_v,
@@ -443,5 +511,54 @@ extern "C" gr_status gr_grid(const double* uvw, const void* vis, int32_t vis_dty
   if (st != GR_OK) return st;
   const BinLayout L = bin_layout(n_vis, n_pol, kernel->support, height, width, seg_len_of(tuning));
   return launch_binned(workspace, L, n_pol, *kernel, reinterpret_cast<float2*>(grid), height, width,
-                       (hipStream_t)stream);
+                       (hipStream_t)stream, tuning && tuning->variant == 2 ? tuning->wg_v : 0);
 }
+
+extern "C" gr_status gr_tuning_memo_put(int32_t n_pol, const gr_kernel* kernel, int32_t height, int32_t width,
+                                        int32_t slot, const gr_tuning* tuning) {
+  gr_status st = validate_kernel(kernel, false);
+  if (st != GR_OK) return st;
+  if ((st = validate_grid(n_pol, height, width, kernel->support)) != GR_OK) return st;
+  if (!valid_slot(slot)) return fail(GR_EINVAL, "gr_tuning_memo_put: slot must be 0 or 1");
+  if (tuning == nullptr) return fail(GR_EINVAL, "gr_tuning_memo_put: tuning is NULL");
+  if (tuning->variant < 0 || tuning->variant > 2 || (slot == 1 && tuning->variant == 2))
+    return fail(GR_EINVAL, "gr_tuning_memo_put: variant must be 0..2 (0 or 1 in slot 1)");
+  memo_store(n_pol, *kernel, height, width, slot, *tuning);
+  return GR_OK;
+}
+
+extern "C" gr_status gr_tuning_memo_get(int32_t n_pol, const gr_kernel* kernel, int32_t height, int32_t width,
+                                        int32_t slot, gr_tuning* out) {
+  gr_status st = validate_kernel(kernel, false);
+  if (st != GR_OK) return st;
+  if ((st = validate_grid(n_pol, height, width, kernel->support)) != GR_OK) return st;
+  if (!valid_slot(slot)) return fail(GR_EINVAL, "gr_tuning_memo_get: slot must be 0 or 1");
+  if (out == nullptr) return fail(GR_EINVAL, "gr_tuning_memo_get: out is NULL");
+  if (!memo_find(n_pol, *kernel, height, width, slot, out))
+    return fail(GR_EINVAL, "gr_tuning_memo_get: no entry for this problem class");
+  return GR_OK;
+}
+
+extern "C" void gr_tuning_memo_clear(void) {
+  std::lock_guard<std::mutex> lock(g_memo_mu);
+  g_memo.clear();
+}
+
+extern "C" gr_status gr_wslice_kernel(const gr_kernel* table, double w_first, double inv_width, int32_t slice,
+                                      gr_kernel* out) {
+  gr_status st = validate_kernel(table, false);
+  if (st != GR_OK) return st;
+  if (out == nullptr) return fail(GR_EINVAL, "gr_wslice_kernel: out is NULL");
+  if (!std::isfinite(w_first) || !std::isfinite(inv_width) || inv_width <= 0)
+    return fail(GR_EINVAL, "gr_wslice_kernel: w_first must be finite and inv_width finite and > 0");
+  if (slice < 0 || slice > 254) return fail(GR_EINVAL, "gr_wslice_kernel: slice must be in 0..254");
+  gr_kernel k = *table;
+  {
+#pragma clang fp contract(off)
+    k.w_min = w_first + (slice + 0.5) / inv_width + table->w_min;
+  }
+  if (!std::isfinite(k.w_min)) return fail(GR_EINVAL, "gr_wslice_kernel: the slice's w_min is not finite");
+  *out = k;
+  return GR_OK;
+}
+

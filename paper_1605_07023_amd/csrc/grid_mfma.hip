@@ -711,13 +711,10 @@ using MfmaFn = void (*)(const Record*, const float2*, const int4*, const int32_t
 using WaveFn = void (*)(const Record*, const float2*, const int4*, const int32_t*, int32_t*,
                         const void*, float2*, MfmaDev, uint32_t);
 
-// Wave-form launch shape: threads per block and blocks per CU (16 waves per CU).
-struct WaveShape {
-  int threads, blocks_per_cu;
-};
-// P = 4 with the 32-cell window: one wave takes all 8 row groups (no parts), so
-// the accumulators allow three waves per SIMD (12 per CU)
-WaveShape wave_shape(int wr, int n_pol) { return WaveShape{wr == 32 && n_pol == 4 ? 768 : 1024, 1}; }
+// Wave-form launch shape: threads per block (one block per CU) from the
+// accumulator registers of a wave, NG x WCG x 4: four waves per SIMD up to 72,
+// three up to 128, else two.
+constexpr int wave_threads(int ng, int wcg) { return ng * wcg * 4 <= 72 ? 1024 : ng * wcg * 4 <= 128 ? 768 : 512; }
 using PersistFn = void (*)(const BatchInst*, const int32_t*, int, const int32_t*, int32_t*);
 
 // window edge (cells) for a support: footprints of a tile of edge WR - S fit it
@@ -754,28 +751,59 @@ PersistFn persist_fn_for(int n_pol, bool cplx, int wr) {
   return cplx ? persist_fn<1, true, TRI>(wr) : persist_fn<1, false, TRI>(wr);
 }
 
-// Wave-form configurations: NG row groups per wave and block size.  The
-// accumulators take NG x WCG x 4 registers; 4 waves per SIMD where they leave
-// room, 3 for P = 4 with the 32-cell window, where one wave taking the whole
-// window (8 row groups) measured faster than two parts at 4 waves per SIMD.
-template <int P, bool CPLX>
-WaveFn wave_fn(int wr) {
-  if constexpr (P == 4) {
-    if (wr == 32) return grid_mfma_waves<4, CPLX, 32, 4, 8, 768>;
-    if (wr == 48) return grid_mfma_waves<4, CPLX, 48, 6, 3, 1024>;
-    return grid_mfma_waves<4, CPLX, 64, 8, 2, 1024>;
-  } else {
-    if (wr == 32) return grid_mfma_waves<1, CPLX, 32, 4, 1, 1024>;
-    if (wr == 48) return grid_mfma_waves<1, CPLX, 48, 6, 1, 1024>;
-    return grid_mfma_waves<1, CPLX, 64, 8, 1, 1024>;
-  }
+// Wave-form configurations: NG row groups per wave (a part of the window is
+// NG row groups, PARTS = WR / RG / NG parts per segment); the block size
+// follows from NG (wave_threads).  Default NG: 8 for P = 4 with the 32-cell
+// window (one wave takes the whole window: measured faster than two parts at
+// four waves per SIMD), 3 with the 48-cell window, 2 with the 64-cell window;
+// 1 for P = 1.
+struct WaveCfg {
+  WaveFn fn;
+  int threads, ng;
+};
+
+template <int P, bool CPLX, int WR, int WCG, int NG>
+WaveCfg wave_cfg() {
+  return WaveCfg{grid_mfma_waves<P, CPLX, WR, WCG, NG, wave_threads(NG, WCG)>, wave_threads(NG, WCG), NG};
 }
 
-int wave_parts(int n_pol, int wr) {
-  const int rg = 16 / n_pol;
-  const int ng = n_pol == 4 ? (wr == 48 ? 3 : wr == 32 ? 8 : 2) : 1;
-  return wr / rg / ng;
+int default_ng(int n_pol, int wr) { return n_pol == 4 ? (wr == 48 ? 3 : wr == 32 ? 8 : 2) : 1; }
+
+// ng <= 0: the default; an NG with no instance: fn = nullptr
+template <int P, bool CPLX>
+WaveCfg wave_fn(int wr, int ng) {
+  if (ng <= 0) ng = default_ng(P, wr);
+  if constexpr (P == 4) {
+    if (wr == 32) {
+      if (ng == 2) return wave_cfg<4, CPLX, 32, 4, 2>();
+      if (ng == 4) return wave_cfg<4, CPLX, 32, 4, 4>();
+      if (ng == 8) return wave_cfg<4, CPLX, 32, 4, 8>();
+    } else if (wr == 48) {
+      if (ng == 2) return wave_cfg<4, CPLX, 48, 6, 2>();
+      if (ng == 3) return wave_cfg<4, CPLX, 48, 6, 3>();
+      if (ng == 4) return wave_cfg<4, CPLX, 48, 6, 4>();
+      if (ng == 6) return wave_cfg<4, CPLX, 48, 6, 6>();
+    } else {
+      if (ng == 2) return wave_cfg<4, CPLX, 64, 8, 2>();
+      if (ng == 4) return wave_cfg<4, CPLX, 64, 8, 4>();
+    }
+  } else {
+    if (wr == 32) {
+      if (ng == 1) return wave_cfg<1, CPLX, 32, 4, 1>();
+      if (ng == 2) return wave_cfg<1, CPLX, 32, 4, 2>();
+    } else if (wr == 48) {
+      if (ng == 1) return wave_cfg<1, CPLX, 48, 6, 1>();
+      if (ng == 3) return wave_cfg<1, CPLX, 48, 6, 3>();
+    } else {
+      if (ng == 1) return wave_cfg<1, CPLX, 64, 8, 1>();
+      if (ng == 2) return wave_cfg<1, CPLX, 64, 8, 2>();
+      if (ng == 4) return wave_cfg<1, CPLX, 64, 8, 4>();
+    }
+  }
+  return WaveCfg{nullptr, 0, ng};
 }
+
+int wave_parts(int n_pol, int wr, int ng) { return wr / (16 / n_pol) / ng; }
 
 // wave = true: the wave form's (-Im, Re, Im) entries; false: the block forms' (Re, Im)
 size_t tap_lds_bytes(const gr_kernel& k, bool wave = false) {
@@ -811,7 +839,7 @@ gr_status plan_mfma(const gr_kernel& k, int n_pol, size_t* lds_bytes) {
 }
 
 gr_status launch_mfma(const void* bins, const BinLayout& L, int n_pol, const gr_kernel& k,
-                      float2* grid, int height, int width, hipStream_t stream) {
+                      float2* grid, int height, int width, hipStream_t stream, int ng) {
   size_t lds = 0;
   gr_status st = plan_mfma(k, n_pol, &lds);
   if (st != GR_OK) return st;
@@ -830,22 +858,22 @@ gr_status launch_mfma(const void* bins, const BinLayout& L, int n_pol, const gr_
   const int wr = window_of(k.support);
   if (L.tile + k.support > wr) return fail(GR_EINVAL, "binning tile does not fit the gridder window");
   // wave form when the table leaves room for the wave slices
-  const WaveShape ws = wave_shape(wr, n_pol);
-  const size_t wave_lds = tap_lds_bytes(k, true) +
-                          (size_t)(ws.threads / 64) * wave_slice_bytes(n_pol);
+  WaveCfg wc;
+  if (n_pol == 4) wc = k.taps_complex ? wave_fn<4, true>(wr, ng) : wave_fn<4, false>(wr, ng);
+  else wc = k.taps_complex ? wave_fn<1, true>(wr, ng) : wave_fn<1, false>(wr, ng);
+  if (wc.fn == nullptr)
+    return fail(GR_EUNSUPPORTED, "tuning: no MFMA gridder with this many row groups per wave for the window");
+  const size_t wave_lds = tap_lds_bytes(k, true) + (size_t)(wc.threads / 64) * wave_slice_bytes(n_pol);
   if (wave_lds <= 160 * 1024) {
-    WaveFn fn;
-    if (n_pol == 4) fn = k.taps_complex ? wave_fn<4, true>(wr) : wave_fn<4, false>(wr);
-    else fn = k.taps_complex ? wave_fn<1, true>(wr) : wave_fn<1, false>(wr);
-    if ((st = ensure_lds_limit(reinterpret_cast<const void*>(fn), wave_lds, "gr_grid_binned")) != GR_OK)
+    if ((st = ensure_lds_limit(reinterpret_cast<const void*>(wc.fn), wave_lds, "gr_grid_binned")) != GR_OK)
       return st;
     // the work counter sits after the segment count in the bins workspace
     int32_t* counter = const_cast<int32_t*>(nsegs) + 16;
     zero_counter<<<1, 64, 0, stream>>>(counter);
-    const int64_t items = nb * wave_parts(n_pol, wr);
-    const int waves = ws.threads / 64;
-    const int blocks = (int)std::min<int64_t>((int64_t)device_cus() * ws.blocks_per_cu, (items + waves - 1) / waves);
-    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(ws.threads), wave_lds, stream, rec, wv, segs,
+    const int64_t items = nb * wave_parts(n_pol, wr, wc.ng);
+    const int waves = wc.threads / 64;
+    const int blocks = (int)std::min<int64_t>((int64_t)device_cus(), (items + waves - 1) / waves);
+    hipLaunchKernelGGL(wc.fn, dim3((unsigned)blocks), dim3(wc.threads), wave_lds, stream, rec, wv, segs,
                        nsegs, counter, k.taps, grid, d, (uint32_t)tap_lds_bytes(k, true));
     return check_launch("gr_grid_binned (mfma waves)");
   }

@@ -8,20 +8,29 @@
 //    B = c * n >= S + c - 1 cells wide; padding taps are zero (Section 3);
 //  * a work-item keeps register accumulators for its current block and flushes
 //    them with atomic adds when the block leaves the bounding box (Section 2.2);
-//  * the bin is split into tiles, one per wave here, processed in parallel;
-//    each work-group takes a fixed number of consecutive visibilities in the
-//    given order (Section 4 uses 1024);
+//  * work-items take a fixed number of consecutive visibilities in the given
+//    order (Section 4 uses 1024 per work-group), one per residue of the bin;
 //  * the separable GCF: each work-item loads cu + cv taps and forms the
 //    products in registers (Section 4), using the factored form
-//    G^u_i (G^v_j V_p) named as future work in Section 6.
+//    G^u_i (G^v_j V_p) named as future work in Section 6 (the factor shared
+//    along the shorter side of the block is formed first).
 //
-// gfx950 mapping: a tile is one wave64; the visibility record and the P
-// visibility values are wave-uniform and are read with scalar loads; the tap
-// table, zero-padded so that every block index in the bounding box is a valid
-// address, is staged once per work-group in LDS as FP32; flushes are FP32
-// global atomic adds (no-return), skipping zero values.
+// gfx950 mapping.  Work-items of the method are independent, so their
+// grouping into waves is free: the work-items (chunk c, residue r) are ordered
+// chunk-major, and each wave takes 64 consecutive ones, so no lane idles at
+// the edge of a bin (a wave may straddle two or three chunks; its lanes then
+// read different visibilities, each group one address).  One block per
+// compute unit stages the zero-padded tap table in LDS once, as FP32, and its
+// waves (16 per CU, or 8 for 64 accumulators) take 64-lane runs in turn from a
+// work counter (gr_grid's workspace holds one), or with a fixed stride over
+// the launch (gr_grid_records, which has no workspace).  A work-item streams its chunk with the next
+// visibility's loads in flight while it updates the current one; flushes are
+// FP32 global atomic adds (no-return), skipping zero values.
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
+
+#include <algorithm>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -30,11 +39,14 @@ namespace gr {
 namespace {
 
 struct RomeinDev {
-  int nu, nv, wgu, wgv, tiles_u, tiles_v, n_tgroups, waves_per_block;
-  int vis_per_wg, lpad, pad_off, n_rows_tab, S, H, W, O, tap_dtype;
-  uint32_t magic_u, magic_v;
-  int64_t n_vis;
-  uint32_t n_blocks;
+  int nu, nv, n_res;              // blocks per bin per axis, residues per bin
+  int wgu, wgv, tiles_u;          // residue order: tiles of wgu x wgv blocks, u first
+  int lpad, pad_off, n_rows_tab, S, H, W, O, tap_dtype;
+  uint32_t magic_u, magic_v;      // ceil(2^32 / n): x mod n by one high multiply
+  int koff_u, koff_v;             // multiples of nu, nv above any block index
+  int n_vis, chunk_len;           // this launch's piece of the stream (< 2^26)
+  int n_runs;                     // runs: 64 consecutive work-items (< 2^31)
+  int32_t* counter;               // runs taken in turn from it, or NULL: fixed stride
 };
 
 __device__ inline float load_tap(const void* __restrict__ t, int64_t idx, int dtype) {
@@ -45,26 +57,30 @@ __device__ inline float load_tap(const void* __restrict__ t, int64_t idx, int dt
   }
 }
 
-// Blocks are dispatched round-robin over the 8 XCDs.  Map the dispatch index
-// so that consecutive logical blocks (the tiles of one chunk, then the next
-// chunk of the same visibility stream) run on the same XCD and share its L2.
-__device__ inline uint32_t xcd_logical_block(uint32_t b, uint32_t nb) {
-  const uint32_t q = nb / 8, r = nb % 8;
-  const uint32_t xcd = b % 8, slot = b / 8;
-  return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ float uni(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
+// Threads per block for a work-item holding A = cu * cv * n_pol complex
+// accumulators: 4 waves per SIMD (128 registers each) up to 32, 2 above.
+__host__ __device__ constexpr int romein_threads(int acc) { return acc <= 32 ? 1024 : 512; }
+
 template <int CU, int CV, int P, bool CPLX>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(romein_threads(CU * CV * P))
 romein_valu_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvis,
                    const void* __restrict__ taps, float2* __restrict__ grid, RomeinDev d) {
   using Tap = typename std::conditional<CPLX, float2, float>::type;
+  constexpr int THREADS = romein_threads(CU * CV * P);
+  constexpr int WAVES = THREADS / 64;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   Tap* lds = reinterpret_cast<Tap*>(lds_raw);
+  // residue order: res_of[q] = ru | rv << 8 for the q-th residue
+  uint16_t* res_of = reinterpret_cast<uint16_t*>(lds_raw + (size_t)d.n_rows_tab * d.lpad * sizeof(Tap));
 
   // ---- stage the zero-padded tap table: [plane * O + s][lpad], FP32
   const int n_elem = d.n_rows_tab * d.lpad;
-  for (int e = threadIdx.x; e < n_elem; e += blockDim.x) {
+  for (int e = threadIdx.x; e < n_elem; e += THREADS) {
     const int row = e / d.lpad;
     const int k = e - row * d.lpad - d.pad_off;
     Tap v;
@@ -80,115 +96,175 @@ romein_valu_kernel(const Record* __restrict__ rec, const float2* __restrict__ wv
     }
     lds[e] = v;
   }
+  // ---- residue order: tiles of wgu x wgv blocks (edge tiles clipped), u first
+  for (int e = threadIdx.x; e < d.n_res; e += THREADS) {
+    const int rv = e / d.nu, ru = e - rv * d.nu;
+    const int tu = ru / d.wgu, tv = rv / d.wgv;
+    const int h = min(d.wgv, d.nv - tv * d.wgv), w = min(d.wgu, d.nu - tu * d.wgu);
+    const int q = tv * d.wgv * d.nu + tu * d.wgu * h + (rv - tv * d.wgv) * w + (ru - tu * d.wgu);
+    res_of[q] = (uint16_t)(ru | (rv << 8));
+  }
   __syncthreads();
 
-  // ---- which chunk of visibilities and which tile of the bin
-  const uint32_t logical = xcd_logical_block(blockIdx.x, d.n_blocks);
-  const int chunk = (int)(logical / (uint32_t)d.n_tgroups);
-  const int tgroup = (int)(logical % (uint32_t)d.n_tgroups);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int tile = tgroup * d.waves_per_block + wave;
-  if (tile >= d.tiles_u * d.tiles_v) return;                 // idle wave (no more barriers)
-  const int tu = tile % d.tiles_u, tv = tile / d.tiles_u;
-  const int lu = lane % d.wgu, lv = lane / d.wgu;
-  const int ru = tu * d.wgu + lu;                            // block residue along u
-  const int rv = tv * d.wgv + lv;
-  const bool active = lane < d.wgu * d.wgv && ru < d.nu && rv < d.nv;
-
-  const int64_t i0 = (int64_t)chunk * d.vis_per_wg;
-  const int64_t i1 = min(d.n_vis, i0 + d.vis_per_wg);
-
-  float2 acc[CU][CV][P];
-#pragma unroll
-  for (int i = 0; i < CU; ++i)
-#pragma unroll
-    for (int j = 0; j < CV; ++j)
-#pragma unroll
-      for (int p = 0; p < P; ++p) acc[i][j][p] = make_float2(0.f, 0.f);
-  int cju = -1, cjv = -1;                                    // current block (block units)
-
-  auto flush = [&]() {
-    if (cju < 0) return;
-#pragma unroll
-    for (int j = 0; j < CV; ++j) {
-      const int row = cjv * CV + j;
-#pragma unroll
-      for (int i = 0; i < CU; ++i) {
-        const int col = cju * CU + i;
-        const bool inside = row < d.H && col < d.W;
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-          float* cell = reinterpret_cast<float*>(grid + ((int64_t)p * d.H + row) * d.W + col);
-          const float2 a = acc[i][j][p];
-          if (inside && a.x != 0.f) unsafeAtomicAdd(cell, a.x);
-          if (inside && a.y != 0.f) unsafeAtomicAdd(cell + 1, a.y);
-          acc[i][j][p] = make_float2(0.f, 0.f);
-        }
-      }
-    }
+  const int stride = (int)gridDim.x * WAVES;
+  const char* rec_b = reinterpret_cast<const char*>(rec);
+  const char* vis_b = reinterpret_cast<const char*>(wvis);
+  // the wave's next run: from the counter (wave-uniform), or the fixed stride
+  auto next_run = [&](int prev) -> int {
+    if (d.counter == nullptr) return prev < 0 ? (int)blockIdx.x * WAVES + wave : prev + stride;
+    int r = 0;
+    if (lane == 0) r = atomicAdd(d.counter, 1);
+    return __builtin_amdgcn_readfirstlane(r);
   };
+  for (int run = next_run(-1); run < d.n_runs; run = next_run(run)) {
+    // this lane's work-item: (chunk, residue) number run * 64 + lane
+    const int64_t e = (int64_t)run * 64 + lane;
+    const int chunk = (int)(e / d.n_res);
+    const int q = (int)(e - (int64_t)chunk * d.n_res);
+    const int nbase = chunk * d.chunk_len;                    // < 2^26 + chunk_len: no overflow
+    const int len = nbase < d.n_vis ? min(d.chunk_len, d.n_vis - nbase) : 0;
+    const uint32_t rr = res_of[q];
+    // residues offset by a multiple of n above any block index: (r - b) mod n
+    // is then taken of a non-negative number
+    const int ru_k = (int)(rr & 0xffu) + d.koff_u, rv_k = (int)(rr >> 8) + d.koff_v;
+    // every lane of the run in one chunk: the visibility is wave-uniform and is
+    // decoded on the scalar unit
+    const int64_t e0 = (int64_t)run * 64;
+    const bool uniform_run = e0 / d.n_res == (e0 + 63) / d.n_res;
 
-  for (int64_t n = i0; n < i1; ++n) {
-    const Record r = rec[n];                                 // wave-uniform
-    if (!rec_valid(r)) continue;
-    const int x0 = rec_x0(r), y0 = rec_y0(r);
-    const int sx = rec_sx(r), sy = rec_sy(r), plane = rec_plane(r);
-    // aligned bounding box origin (blocks) and its residue modulo the bin
-    const int bu = x0 / CU, bv = y0 / CV;
-    const int mu = bu - (int)__umulhi((uint32_t)bu, d.magic_u) * d.nu;
-    const int mv = bv - (int)__umulhi((uint32_t)bv, d.magic_v) * d.nv;
-    int du = ru - mu;
-    du += du < 0 ? d.nu : 0;
-    int dv = rv - mv;
-    dv += dv < 0 ? d.nv : 0;
-    const int ju = bu + du, jv = bv + dv;                    // this work-item's block
-    if (!active) continue;
-    if (ju != cju || jv != cjv) {
-      flush();
-      cju = ju;
-      cjv = jv;
-    }
-    // taps: cu along u, cv along v, from the padded LDS rows
-    const Tap* tu_row = lds + (plane * d.O + sx) * d.lpad + (ju * CU - x0 + d.pad_off);
-    const Tap* tv_row = lds + (plane * d.O + sy) * d.lpad + (jv * CV - y0 + d.pad_off);
-    Tap gu[CU], gv[CV];
+    auto body = [&](auto uniform_tag) {
+      constexpr bool UNI = decltype(uniform_tag)::value;
+      float2 acc[CU][CV][P];
 #pragma unroll
-    for (int i = 0; i < CU; ++i) gu[i] = tu_row[i];
+      for (int i = 0; i < CU; ++i)
 #pragma unroll
-    for (int j = 0; j < CV; ++j) gv[j] = tv_row[j];
-    float2 vis[P];
+        for (int j = 0; j < CV; ++j)
 #pragma unroll
-    for (int p = 0; p < P; ++p) vis[p] = wvis[n * P + p];   // wave-uniform
-    // t_jp = G^v_j V_p, then acc_ijp += G^u_i t_jp
+          for (int p = 0; p < P; ++p) acc[i][j][p] = make_float2(0.f, 0.f);
+      int cju = -1, cjv = -1;                                 // current block (block units)
+
+      auto flush = [&]() {
 #pragma unroll
-    for (int j = 0; j < CV; ++j) {
+        for (int j = 0; j < CV; ++j) {
+          const int row = cjv * CV + j;
 #pragma unroll
-      for (int p = 0; p < P; ++p) {
-        float2 t;
-        if constexpr (CPLX) {
-          t.x = gv[j].x * vis[p].x - gv[j].y * vis[p].y;
-          t.y = gv[j].x * vis[p].y + gv[j].y * vis[p].x;
-        } else {
-          t.x = gv[j] * vis[p].x;
-          t.y = gv[j] * vis[p].y;
-        }
+          for (int i = 0; i < CU; ++i) {
+            const int col = cju * CU + i;
+            const bool inside = row < d.H && col < d.W;
 #pragma unroll
-        for (int i = 0; i < CU; ++i) {
-          float2& a = acc[i][j][p];
-          if constexpr (CPLX) {
-            a.x = fmaf(gu[i].x, t.x, a.x);
-            a.x = fmaf(-gu[i].y, t.y, a.x);
-            a.y = fmaf(gu[i].x, t.y, a.y);
-            a.y = fmaf(gu[i].y, t.x, a.y);
-          } else {
-            a.x = fmaf(gu[i], t.x, a.x);
-            a.y = fmaf(gu[i], t.y, a.y);
+            for (int p = 0; p < P; ++p) {
+              float* cell = reinterpret_cast<float*>(grid + ((int64_t)p * d.H + row) * d.W + col);
+              const float2 a = acc[i][j][p];
+              if (inside && a.x != 0.f) unsafeAtomicAdd(cell, a.x);
+              if (inside && a.y != 0.f) unsafeAtomicAdd(cell + 1, a.y);
+              acc[i][j][p] = make_float2(0.f, 0.f);
+            }
           }
         }
+      };
+
+      // the next visibility's record and values, loaded one step ahead (a lane
+      // past its chunk's end re-reads the chunk's last entry, one past the
+      // piece's end reads entry 0, and both ignore what they read); 32-bit
+      // byte offsets (a piece holds < 2^26 visibilities)
+      auto load = [&](int k, Record& r, float2 (&v)[P]) {
+        const uint32_t n = len > 0 ? (uint32_t)(nbase + min(k, len - 1)) : 0u;
+        r = *reinterpret_cast<const Record*>(rec_b + n * 8u);
+        if constexpr (P == 4) {
+          const float4* src = reinterpret_cast<const float4*>(vis_b + n * 32u);
+          const float4 a = src[0], b = src[1];
+          v[0] = make_float2(a.x, a.y); v[1] = make_float2(a.z, a.w);
+          v[2] = make_float2(b.x, b.y); v[3] = make_float2(b.z, b.w);
+        } else {
+          v[0] = *reinterpret_cast<const float2*>(vis_b + n * 8u);
+        }
+      };
+      const int len_w = UNI ? (int)uni((uint32_t)len) : len;
+      // one visibility: its record r and weighted values vis, at position k
+      auto step = [&](int k, Record r, const float2 (&vis_in)[P]) {
+        float2 vis[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) vis[p] = vis_in[p];
+        if constexpr (UNI) {
+          r.x = uni(r.x);
+          r.y = uni(r.y);
+#pragma unroll
+          for (int p = 0; p < P; ++p) vis[p] = make_float2(uni(vis[p].x), uni(vis[p].y));
+        }
+        if (k < len_w && rec_valid(r)) {
+          const int x0 = rec_x0(r), y0 = rec_y0(r);
+          // aligned bounding box origin (blocks); this work-item's block is the
+          // one in [b, b + n) congruent to its residue: b + (r - b) mod n
+          const int bu = x0 / CU, bv = y0 / CV;
+          const uint32_t tu = (uint32_t)(ru_k - bu), tv = (uint32_t)(rv_k - bv);
+          const int ju = bu + (int)(tu - __umulhi(tu, d.magic_u) * (uint32_t)d.nu);
+          const int jv = bv + (int)(tv - __umulhi(tv, d.magic_v) * (uint32_t)d.nv);
+          if (ju != cju || jv != cjv) {
+            if (cju >= 0) flush();
+            cju = ju;
+            cjv = jv;
+          }
+          // taps: cu along u, cv along v, from the padded LDS rows
+          const int row_u = (rec_plane(r) * d.O + rec_sx(r)) * d.lpad - x0 + d.pad_off;
+          const int row_v = (rec_plane(r) * d.O + rec_sy(r)) * d.lpad - y0 + d.pad_off;
+          const Tap* tu_row = lds + row_u + ju * CU;
+          const Tap* tv_row = lds + row_v + jv * CV;
+          Tap gu[CU], gv[CV];
+#pragma unroll
+          for (int i = 0; i < CU; ++i) gu[i] = tu_row[i];
+#pragma unroll
+          for (int j = 0; j < CV; ++j) gv[j] = tv_row[j];
+          // the shorter side's taps times the visibilities first, then the
+          // longer side's taps times those: acc_ijp += G^u_i (G^v_j V_p)
+          constexpr bool V_FIRST = CV <= CU;
+          constexpr int NS = V_FIRST ? CV : CU, NL = V_FIRST ? CU : CV;
+#pragma unroll
+          for (int s = 0; s < NS; ++s) {
+            const Tap gs = V_FIRST ? gv[s] : gu[s];
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+              float2 t;
+              if constexpr (CPLX) {
+                t.x = gs.x * vis[p].x - gs.y * vis[p].y;
+                t.y = gs.x * vis[p].y + gs.y * vis[p].x;
+              } else {
+                t.x = gs * vis[p].x;
+                t.y = gs * vis[p].y;
+              }
+#pragma unroll
+              for (int l = 0; l < NL; ++l) {
+                const Tap g = V_FIRST ? gu[l] : gv[l];
+                float2& a = V_FIRST ? acc[l][s][p] : acc[s][l][p];
+                if constexpr (CPLX) {
+                  a.x = fmaf(g.x, t.x, a.x);
+                  a.x = fmaf(-g.y, t.y, a.x);
+                  a.y = fmaf(g.x, t.y, a.y);
+                  a.y = fmaf(g.y, t.x, a.y);
+                } else {
+                  a.x = fmaf(g, t.x, a.x);
+                  a.y = fmaf(g, t.y, a.y);
+                }
+              }
+            }
+          }
+        }
+      };
+      // two register sets for the loads in flight, used in turn
+      Record ra, rb;
+      float2 va[P], vb[P];
+      load(0, ra, va);
+      for (int k = 0; k < d.chunk_len; k += 2) {
+        load(k + 1, rb, vb);
+        step(k, ra, va);
+        load(k + 2, ra, va);
+        step(k + 1, rb, vb);
       }
-    }
+      if (cju >= 0) flush();
+    };
+    if (uniform_run) body(std::true_type{});
+    else body(std::false_type{});
   }
-  if (active) flush();
 }
 
 using KernFn = void (*)(const Record*, const float2*, const void*, float2*, RomeinDev);
@@ -196,7 +272,9 @@ using KernFn = void (*)(const Record*, const float2*, const void*, float2*, Rome
 template <int CU, int CV>
 KernFn pick_pc(int n_pol, bool cplx) {
   if (n_pol == 1) return cplx ? romein_valu_kernel<CU, CV, 1, true> : romein_valu_kernel<CU, CV, 1, false>;
-  return cplx ? romein_valu_kernel<CU, CV, 4, true> : romein_valu_kernel<CU, CV, 4, false>;
+  if constexpr (CU * CV <= 16)
+    return cplx ? romein_valu_kernel<CU, CV, 4, true> : romein_valu_kernel<CU, CV, 4, false>;
+  return nullptr;
 }
 
 template <int CU>
@@ -222,6 +300,17 @@ KernFn pick(int cu, int cv, int n_pol, bool cplx) {
 
 bool valid_c(int c) { return c == 1 || c == 2 || c == 4 || c == 8; }
 
+int g_cus = 0;
+
+int device_cus() {
+  if (g_cus > 0) return g_cus;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+    g_cus = cus;
+  return g_cus > 0 ? g_cus : 256;
+}
+
 }  // namespace
 
 gr_status plan_romein(const gr_kernel& k, int n_pol, const gr_tuning* t, RomeinPlan* plan) {
@@ -232,7 +321,7 @@ gr_status plan_romein(const gr_kernel& k, int n_pol, const gr_tuning* t, RomeinP
   if (cu == 0 || cv == 0) {
     int du, dv;
     if (S <= 8) { du = 2; dv = 2; }
-    else if (n_pol == 4) { du = 4; dv = 2; }
+    else if (n_pol == 4) { du = 8; dv = 1; }
     else { du = 4; dv = 4; }
     if (cu == 0) cu = du;
     if (cv == 0) cv = dv;
@@ -244,57 +333,79 @@ gr_status plan_romein(const gr_kernel& k, int n_pol, const gr_tuning* t, RomeinP
   p.cv = cv;
   p.nu = (S + cu - 1 + cu - 1) / cu;   // smallest n with c n >= S + c - 1
   p.nv = (S + cv - 1 + cv - 1) / cv;
-  int wgu = t && t->wg_u > 0 ? t->wg_u : std::min(p.nu, 16);
-  int wgv = t && t->wg_v > 0 ? t->wg_v : std::min(p.nv, std::max(1, 64 / wgu));
-  if (wgu * wgv > 64) return fail(GR_EINVAL, "tuning: wg_u * wg_v must be <= 64 (one wave per tile)");
-  wgu = std::min(wgu, p.nu);
-  wgv = std::min(wgv, p.nv);
-  p.wgu = wgu;
-  p.wgv = wgv;
-  p.tiles_u = (p.nu + wgu - 1) / wgu;
-  p.tiles_v = (p.nv + wgv - 1) / wgv;
-  p.waves_per_block = std::min(p.tiles_u * p.tiles_v, 4);
-  p.vis_per_wg = t && t->vis_per_wg > 0 ? t->vis_per_wg : 1024;
+  if (p.nu > 255 || p.nv > 255) return fail(GR_EUNSUPPORTED, "more than 255 blocks per bin axis");
+  if (t && (t->wg_u > 64 || t->wg_v > 64)) return fail(GR_EINVAL, "tuning: wg_u and wg_v must be <= 64");
+  p.wgu = std::min(t && t->wg_u > 0 ? t->wg_u : p.nu, p.nu);
+  p.wgv = std::min(t && t->wg_v > 0 ? t->wg_v : p.nv, p.nv);
+  p.vis_per_wg = t && t->vis_per_wg > 0 ? t->vis_per_wg : 0;
+  p.threads = romein_threads(cu * cv * n_pol);
   p.pad_off = std::max(cu, cv) - 1;
   p.lpad = std::max(cu * p.nu, cv * p.nv) + p.pad_off;
   const size_t elem = k.taps_complex ? 8 : 4;
-  p.lds_bytes = (size_t)k.n_planes * k.oversample * p.lpad * elem;
+  p.lds_bytes = (size_t)k.n_planes * k.oversample * p.lpad * elem + (size_t)p.nu * p.nv * sizeof(uint16_t);
   if (p.lds_bytes > 160 * 1024)
     return fail(GR_EUNSUPPORTED, "tap table does not fit in LDS (planes * O * padded row)");
   *plan = p;
   return GR_OK;
 }
 
+__global__ void __launch_bounds__(64) zero_run_counter(int32_t* c) {
+  if (threadIdx.x == 0) *c = 0;
+}
+
 gr_status launch_romein(const Record* rec, const float2* wvis, int64_t n_vis, int n_pol,
                         const gr_kernel& k, float2* grid, int height, int width,
-                        const RomeinPlan& p, hipStream_t stream) {
+                        const RomeinPlan& p, hipStream_t stream, int32_t* counter) {
   if (n_vis == 0) return GR_OK;
   KernFn fn = pick(p.cu, p.cv, n_pol, k.taps_complex != 0);
   if (fn == nullptr) return fail(GR_EUNSUPPORTED, "no kernel instance for this tuning");
   RomeinDev d{};
-  d.nu = p.nu; d.nv = p.nv; d.wgu = p.wgu; d.wgv = p.wgv;
-  d.tiles_u = p.tiles_u; d.tiles_v = p.tiles_v;
-  d.waves_per_block = p.waves_per_block;
-  d.n_tgroups = (p.tiles_u * p.tiles_v + p.waves_per_block - 1) / p.waves_per_block;
-  d.vis_per_wg = p.vis_per_wg;
+  d.nu = p.nu; d.nv = p.nv; d.n_res = p.nu * p.nv;
+  d.wgu = p.wgu; d.wgv = p.wgv; d.tiles_u = (p.nu + p.wgu - 1) / p.wgu;
   d.lpad = p.lpad; d.pad_off = p.pad_off;
   d.n_rows_tab = k.n_planes * k.oversample;
   d.S = k.support; d.H = height; d.W = width; d.O = k.oversample;
   d.tap_dtype = k.tap_dtype;
   d.magic_u = (uint32_t)((0x100000000ull + p.nu - 1) / p.nu);
   d.magic_v = (uint32_t)((0x100000000ull + p.nv - 1) / p.nv);
-  d.n_vis = n_vis;
-  const int64_t n_chunks = (n_vis + p.vis_per_wg - 1) / p.vis_per_wg;
-  const int64_t nb = n_chunks * d.n_tgroups;
-  if (nb > 0x7fffffff) return fail(GR_EINVAL, "too many work-groups; raise vis_per_wg");
-  d.n_blocks = (uint32_t)nb;
+  // block indices are below 2^15 (x0, y0 < 32768): a multiple of n at or above that
+  d.koff_u = (32768 + p.nu - 1) / p.nu * p.nu;
+  d.koff_v = (32768 + p.nv - 1) / p.nv * p.nv;
+  const int waves = p.threads / 64;
+  const int64_t slots = (int64_t)device_cus() * waves;      // waves of one full launch
   {
     const gr_status lst = ensure_lds_limit(reinterpret_cast<const void*>(fn), p.lds_bytes, "grid_romein.hip");
     if (lst != GR_OK) return lst;
   }
-  hipLaunchKernelGGL(fn, dim3((unsigned)nb), dim3(64 * p.waves_per_block), p.lds_bytes, stream, rec,
-                     wvis, k.taps, grid, d);
-  return check_launch("gr_grid_records (romein)");
+  // the stream in pieces of < 2^26 visibilities (32-bit offsets in the kernel),
+  // each piece its own launch; chunks never straddle pieces
+  constexpr int64_t kPiece = (int64_t)1 << 26;
+  for (int64_t first = 0; first < n_vis; first += kPiece) {
+    const int64_t n = std::min(kPiece, n_vis - first);
+    int64_t len = p.vis_per_wg;
+    if (len <= 0) {
+      // equal chunks: about four 64-lane runs per wave of the launch (eight
+      // when the waves take them in turn from the counter)
+      const int64_t per_wave = counter != nullptr ? 8 : 4;
+      const int64_t chunks = std::max<int64_t>(1, per_wave * slots * 64 / d.n_res);
+      len = (n + chunks - 1) / chunks;
+      len = std::max<int64_t>(64, (len + 63) / 64 * 64);
+    }
+    len = std::min<int64_t>(len, kPiece);
+    d.n_vis = (int)n;
+    d.chunk_len = (int)len;
+    const int64_t n_chunks = (n + len - 1) / len;
+    const int64_t n_runs = (n_chunks * d.n_res + 63) / 64;    // < 2^20 chunks x 2^16 residues / 64
+    d.n_runs = (int)n_runs;
+    d.counter = counter;
+    const int64_t blocks = std::min<int64_t>(device_cus(), (n_runs + waves - 1) / waves);
+    if (counter != nullptr) zero_run_counter<<<1, 64, 0, stream>>>(counter);
+    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(p.threads), p.lds_bytes, stream, rec + first,
+                       wvis + first * n_pol, k.taps, grid, d);
+    const gr_status st = check_launch("gr_grid_records (romein)");
+    if (st != GR_OK) return st;
+  }
+  return GR_OK;
 }
 
 }  // namespace gr

@@ -41,6 +41,11 @@ __host__ __device__ inline bool rec_valid(Record r) { return (r.y & kValidBit) !
 // Host-side validation of a kernel descriptor (shared by preprocess and grid).
 gr_status validate_kernel(const gr_kernel* k, bool need_taps);
 
+// The library's tuning memo (api.hip): slot 0 is read by gr_grid, slot 1 by
+// gr_grid_records, when they are called without a tuning.
+void memo_store(int n_pol, const gr_kernel& k, int height, int width, int slot, const gr_tuning& t);
+bool memo_find(int n_pol, const gr_kernel& k, int height, int width, int slot, gr_tuning* out);
+
 // Preprocess launcher (preprocess.hip).
 gr_status launch_preprocess(const double* uvw, const void* vis, int vis_dtype, const float* vis_scale,
                             const float* weights, int64_t n_vis, int n_pol, const gr_kernel& k,
@@ -51,17 +56,18 @@ gr_status launch_preprocess(const double* uvw, const void* vis, int vis_dtype, c
 struct RomeinPlan {
   int cu, cv;          // coarsening (cells per block, per axis)
   int nu, nv;          // blocks per bin, per axis (bin = c * n >= S + c - 1)
-  int wgu, wgv;        // blocks per tile (one tile per wave)
-  int tiles_u, tiles_v;
-  int waves_per_block;
-  int vis_per_wg;
+  int wgu, wgv;        // residue order: tiles of wgu x wgv blocks take consecutive lanes
+  int vis_per_wg;      // visibilities per work-item chunk (0: equal ranges)
+  int threads;         // threads per block (one block per compute unit)
   int lpad, pad_off;   // padded tap row length and offset in LDS
   size_t lds_bytes;
 };
 gr_status plan_romein(const gr_kernel& k, int n_pol, const gr_tuning* t, RomeinPlan* plan);
+// counter (device int32, or NULL): work counter for a dynamic assignment of
+// the 64-lane runs to waves; NULL: a fixed assignment (stride over the launch)
 gr_status launch_romein(const Record* rec, const float2* wvis, int64_t n_vis, int n_pol,
                         const gr_kernel& k, float2* grid, int height, int width,
-                        const RomeinPlan& plan, hipStream_t stream);
+                        const RomeinPlan& plan, hipStream_t stream, int32_t* counter = nullptr);
 
 // Binning of the preprocessed stream by footprint tile (bin.hip).
 struct BinLayout {
@@ -127,8 +133,16 @@ gr_status plan_mfma(const gr_kernel& k, int n_pol, size_t* lds_bytes);
 // LDS bytes of the block-form MFMA gridder: tri = (-Im, Re, Im) table entries
 // (the form used where they fit), else (Re, Im) pairs (what plan_mfma checks)
 size_t block_lds_bytes(const gr_kernel& k, int n_pol, bool tri);
+// ng: row groups per wave of the wave form (<= 0: the default for the window)
 gr_status launch_mfma(const void* bins, const BinLayout& L, int n_pol, const gr_kernel& k,
-                      float2* grid, int height, int width, hipStream_t stream);
+                      float2* grid, int height, int width, hipStream_t stream, int ng = 0);
+
+// gr_grid_binned with the wave form's row groups per wave (api.hip; ng as launch_mfma).
+gr_status grid_binned(const void* bins, int64_t n_vis, int32_t n_pol, const gr_kernel* kernel, int32_t seg_len,
+                      void* grid, int32_t height, int32_t width, void* stream, int ng);
+// The binned gridder for the kernel's kind (api.hip); ng as launch_mfma.
+gr_status launch_binned(const void* bins, const BinLayout& L, int n_pol, const gr_kernel& k,
+                        float2* grid, int height, int width, hipStream_t stream, int ng = 0);
 
 // Non-separable table gridder over the binned stream (aterm.hip).
 gr_status launch_table2d(const void* bins, const BinLayout& L, int n_pol, const gr_kernel& k,

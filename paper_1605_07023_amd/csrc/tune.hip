@@ -1,8 +1,9 @@
 // Autotuning (Merry 2016, Section 4): a small data set is gridded with each
 // candidate work decomposition (coarsening factors, tile shape, visibilities
 // per work-group, kernel variant) and the fastest is kept.  This translation
-// unit holds the timing sweep; the candidate list and the memo of results
-// are the caller's.
+// unit holds the timing sweep; the winner goes to the library's tuning memo
+// (api.hip), which calls without a tuning read.  The candidate list, and
+// keeping tunings across processes, are the caller's.
 #include <cmath>
 #include <vector>
 
@@ -10,8 +11,6 @@
 
 using namespace gr;
 
-extern "C" gr_status gr_grid_binned(const void* bins, int64_t n_vis, int32_t n_pol, const gr_kernel* kernel,
-                                    int32_t seg_len, void* grid, int32_t height, int32_t width, void* stream);
 extern "C" gr_status gr_bin(const void* records, const void* wvis, int64_t n_vis, int32_t n_pol,
                             int32_t support, int32_t height, int32_t width, int32_t seg_len, void* bins,
                             size_t bins_bytes, void* stream);
@@ -62,7 +61,7 @@ extern "C" gr_status gr_autotune(const void* records, const void* wvis, int64_t 
       gr_status r = gr_bin(records, wvis, n_vis, n_pol, kernel->support, height, width, t.vis_per_wg, bins,
                            bins_bytes, stream);
       if (r != GR_OK) return r;
-      return gr_grid_binned(bins, n_vis, n_pol, kernel, t.vis_per_wg, grid, height, width, stream);
+      return grid_binned(bins, n_vis, n_pol, kernel, t.vis_per_wg, grid, height, width, stream, t.wg_v);
     };
     // warm-up call; unsupported candidates are skipped with time +inf
     if (run() != GR_OK) continue;
@@ -81,6 +80,16 @@ extern "C" gr_status gr_autotune(const void* records, const void* wvis, int64_t 
   }
   *best = best_i;
   if (best_i < 0) return fail(GR_EUNSUPPORTED, "gr_autotune: no candidate ran");
+  // remember the winner for calls without a tuning: slot 0 (gr_grid) takes the
+  // fastest candidate, slot 1 (gr_grid_records) the fastest VALU one
+  gr_tuning win = candidates[best_i];
+  win.variant = win.variant == 1 ? 1 : 2;
+  memo_store(n_pol, *kernel, height, width, 0, win);
+  int best_v1 = -1;
+  for (int c = 0; c < n_candidates; ++c)
+    if (candidates[c].variant == 1 && std::isfinite(times_ms[c]) && (best_v1 < 0 || times_ms[c] < times_ms[best_v1]))
+      best_v1 = c;
+  if (best_v1 >= 0) memo_store(n_pol, *kernel, height, width, 1, candidates[best_v1]);
   set_error("");
   return GR_OK;
 }

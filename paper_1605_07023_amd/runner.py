@@ -179,12 +179,6 @@ class BatchGraph:
             pass
 
 
-def slice_w_min(w_first: float, inv_width: float, s: int, w_min_rel: float) -> float:
-    """w_min of slice s's kernel: the slice centre w_first + (s + 1/2) / inv_width
-    plus the w_min of the residual-w table (planes relative to the centre)."""
-    return w_first + (s + 0.5) / inv_width + w_min_rel
-
-
 def wslice_partition(dw: DeviceWorkload, w_first: float, inv_width: float, n_slices: int,
                      workspace: Optional[torch.Tensor] = None, stream=None):
     """gr_wslice_partition of a device workload into fresh buffers: returns
@@ -205,17 +199,11 @@ def wslice_partition(dw: DeviceWorkload, w_first: float, inv_width: float, n_sli
     return uvw_p, vis_p, w_p, offs
 
 
-def slice_kernel(k: B.GrKernel, w_min: float) -> B.GrKernel:
-    """The same tap table with another w_min."""
-    return B.GrKernel(k.kind, k.tap_dtype, k.taps_complex, k.support, k.oversample, k.n_planes,
-                      w_min, k.inv_dw, k.taps)
-
-
 def grid_wstack(dw: DeviceWorkload, w_first: float, inv_width: float, n_slices: int,
                 grids: Optional[torch.Tensor] = None, mode: str = "batch", stream=None):
     """W-stacking: partition by w slice (gr_wslice_partition), then grid each
     slice into its own grid with dw.kernel's table, whose w_min is taken as
-    relative to the slice centre (slice_w_min).  mode "batch": one
+    relative to the slice centre (gr_wslice_kernel).  mode "batch": one
     gr_grid_batch over the slices; "per_slice": one gr_grid per slice.  The
     slice offsets are copied to the host (one synchronisation) to form the
     calls.  Returns (grids complex64 [n_slices][P][H][W], host offsets)."""
@@ -232,7 +220,7 @@ def grid_wstack(dw: DeviceWorkload, w_first: float, inv_width: float, n_slices: 
             a, b = int(off[s]), int(off[s + 1])
             items.append(B.make_batch_item(uvw_p[a:], vis_p[a:], B.GR_F32, wl.n_pol, None,
                                            None if w_p is None else w_p[a:], b - a,
-                                           slice_kernel(k, slice_w_min(w_first, inv_width, s, k.w_min)),
+                                           B.gr_wslice_kernel(k, w_first, inv_width, s),
                                            wl.inv_cell_u, wl.inv_cell_v, grids[s], wl.height, wl.width))
         need = B.gr_grid_batch_workspace_bytes(items)
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
@@ -243,7 +231,7 @@ def grid_wstack(dw: DeviceWorkload, w_first: float, inv_width: float, n_slices: 
             a, b = int(off[s]), int(off[s + 1])
             if b == a:
                 continue
-            ks = slice_kernel(k, slice_w_min(w_first, inv_width, s, k.w_min))
+            ks = B.gr_wslice_kernel(k, w_first, inv_width, s)
             need = B.gr_grid_workspace_bytes(b - a, wl.n_pol, ks, wl.height, wl.width, None)
             if ws is None or ws.numel() < need:
                 ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)

@@ -15,7 +15,7 @@ def _declared():
     for f in os.listdir(os.path.join(ROOT, "include")):
         if f.endswith(".h"):
             txt = open(os.path.join(ROOT, "include", f)).read()
-            names |= set(re.findall(r"^\s*(?:gr_status|size_t|int32_t|const char\*)\s+(gr_\w+)\(", txt, re.M))
+            names |= set(re.findall(r"^\s*(?:gr_status|size_t|int32_t|void|const char\*)\s+(gr_\w+)\(", txt, re.M))
     return sorted(names)
 
 
@@ -95,7 +95,7 @@ def test_tuning_validation(lib):
     k = _kernel()
     for t, code in [(B.GrTuning(3, 2, 0, 0, 0, 0), B.GR_EINVAL),
                     (B.GrTuning(8, 8, 0, 0, 0, 0), B.GR_EUNSUPPORTED),
-                    (B.GrTuning(2, 2, 16, 16, 0, 0), B.GR_EINVAL),
+                    (B.GrTuning(2, 2, 65, 1, 0, 0), B.GR_EINVAL),
                     (B.GrTuning(0, 0, 0, 0, 0, 7), B.GR_EUNSUPPORTED)]:
         st = lib.gr_grid_records(1 << 20, 1 << 20, 10, 4, ctypes.byref(k), 1 << 20, 64, 64,
                                  ctypes.byref(t), None)
@@ -353,3 +353,41 @@ def test_batch_graph_validation(lib):
     assert lib.gr_grid_batch_graph(arr, 1, 1 << 20, need, None) == B.GR_EINVAL
     assert lib.gr_graph_launch(None, None) == B.GR_EINVAL
     assert lib.gr_graph_destroy(None) == B.GR_OK
+
+
+def test_tuning_memo_round_trip(lib):
+    """The library's tuning memo: an entry put for a problem class comes back
+    from get, gr_grid_workspace_bytes with no tuning follows it (a VALU-kernel
+    entry needs the preprocess buffers, the default binned path the bins), other
+    classes (support, side class, n_pol, slot) are unaffected, and clear removes it."""
+    from paper_1605_07023_amd import binding as B
+    B.gr_tuning_memo_clear()
+    k = _kernel()
+    binned = B.gr_grid_workspace_bytes(1000, 4, k, 64, 64)
+    valu = B.gr_grid_workspace_bytes(1000, 4, k, 64, 64, B.GrTuning(0, 0, 0, 0, 0, 1))
+    assert binned != valu
+    assert B.gr_tuning_memo_get(4, k, 64, 64, 0) is None
+    t = B.GrTuning(4, 2, 3, 5, 512, 1)
+    B.gr_tuning_memo_put(4, k, 64, 64, 0, t)
+    got = B.gr_tuning_memo_get(4, k, 60, 50, 0)            # same side class (64)
+    assert (got.cu, got.cv, got.wg_u, got.wg_v, got.vis_per_wg, got.variant) == (4, 2, 3, 5, 512, 1)
+    assert B.gr_grid_workspace_bytes(1000, 4, k, 64, 64) == valu
+    assert B.gr_tuning_memo_get(4, k, 128, 128, 0) is None  # other side class
+    assert B.gr_tuning_memo_get(1, k, 64, 64, 0) is None    # other n_pol
+    assert B.gr_tuning_memo_get(4, _kernel(support=8), 64, 64, 0) is None
+    assert B.gr_tuning_memo_get(4, _kernel(tap_dtype=B.GR_F16), 64, 64, 0) is None
+    assert B.gr_tuning_memo_get(4, k, 64, 64, 1) is None
+    assert B.gr_grid_workspace_bytes(1000, 4, k, 128, 128) == B.gr_grid_workspace_bytes(
+        1000, 4, k, 128, 128, B.GrTuning(0, 0, 0, 0, 0, 2))
+    # slot 1 (gr_grid_records) takes VALU tunings only
+    for bad in [B.GrTuning(0, 0, 0, 0, 0, 2), B.GrTuning(0, 0, 0, 0, 0, 3)]:
+        assert lib.gr_tuning_memo_put(4, ctypes.byref(k), 64, 64, 1, ctypes.byref(bad)) == B.GR_EINVAL
+    assert lib.gr_tuning_memo_put(4, ctypes.byref(k), 64, 64, 2, ctypes.byref(t)) == B.GR_EINVAL
+    assert lib.gr_tuning_memo_put(4, ctypes.byref(k), 64, 64, 0, None) == B.GR_EINVAL
+    assert lib.gr_tuning_memo_put(3, ctypes.byref(k), 64, 64, 0, ctypes.byref(t)) == B.GR_EINVAL
+    B.gr_tuning_memo_put(4, k, 64, 64, 1, B.GrTuning(8, 1, 0, 0, 0, 1))
+    assert B.gr_tuning_memo_get(4, k, 64, 64, 1).cu == 8
+    B.gr_tuning_memo_clear()
+    assert B.gr_tuning_memo_get(4, k, 64, 64, 0) is None
+    assert B.gr_tuning_memo_get(4, k, 64, 64, 1) is None
+    assert B.gr_grid_workspace_bytes(1000, 4, k, 64, 64) == binned

@@ -298,15 +298,35 @@ def test_grid_points_wkernel_p4(R, cu, cv, S):
     assert stats.cpu().tolist() == [wl.n_vis - dropped, dropped] and dropped > 0
 
 
-@pytest.mark.parametrize("wg_u,wg_v,vpw", [(3, 5, 7), (16, 4, 1), (1, 1, 100000), (5, 1, 33)])
-def test_grid_tile_shapes_and_ragged_chunks(R, wg_u, wg_v, vpw):
-    _say(f"grid tile shape {wg_u}x{wg_v} vis_per_wg={vpw}")
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("wg_u,wg_v,vpw", [(3, 5, 7), (16, 4, 1), (1, 1, 100000), (5, 1, 33), (64, 64, 64)])
+def test_grid_tile_shapes_and_ragged_chunks(R, wg_u, wg_v, vpw, variant):
+    """Variant 1: the VALU kernel with its blocks taken in tiles of wg_u x wg_v
+    and chunks of vpw visibilities (ragged); variant 0: the library's choice
+    (the binned MFMA path, which ignores the tile fields and takes vpw as its
+    segment length)."""
+    _say(f"grid tile shape {wg_u}x{wg_v} vis_per_wg={vpw} variant={variant}")
     wl = random_point_workload(777, 1, 64, 48, 16, 8, seed=5, n_planes=3, margin=2,
                                weights=False, kernel="wsep")
     dw = R.upload(wl, DEV)
-    g = R.grid(dw, tune=R.tuning(2, 4, wg_u, wg_v, vpw)).cpu().numpy()
+    g = R.grid(dw, tune=R.tuning(2, 4, wg_u, wg_v, vpw, variant=variant)).cpu().numpy()
     ref, _ = _oracle_grid(wl, _oracle_taps(wl))
     assert _rel_l2(g, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("P,S", [(4, 16), (4, 32), (1, 16), (1, 32), (4, 56)])
+def test_mfma_row_groups_per_wave(R, P, S):
+    """Every row-group count the autotuner offers for the MFMA wave form grids
+    the same points as the oracle (the work-group shape dimension of the sweep)."""
+    from paper_1605_07023_amd import autotune as A
+    wl = random_point_workload(2500, P, 160, 144, S, 8, seed=40 + S + P, n_planes=5, margin=3,
+                               weights=True, kernel="wsep")
+    ref, _ = _oracle_grid(wl, _oracle_taps(wl))
+    dw = R.upload(wl, DEV)
+    for rg in A.row_group_options(P, S):
+        _say(f"mfma P={P} S={S} row groups per wave {rg}")
+        g = R.grid(dw, tune=R.tuning(0, 0, 0, rg, 512, variant=2)).cpu().numpy()
+        assert _rel_l2(g, ref) <= 1e-5, rg
 
 
 def _custom_taps_run(R, wl, taps_np, tune):

@@ -88,16 +88,29 @@ def test_grid_wstack_sums_to_the_whole_for_a_w_independent_kernel():
     np.testing.assert_allclose(grids.sum(axis=0), whole, rtol=0, atol=1e-12)
 
 
-def test_slice_w_min_agrees_with_the_binding():
-    """The host-side w_min of each slice's kernel (paper_1605_07023_amd.runner, used to form the
-    batch items) equals the oracle's, bit for bit, so both sides pick the same planes."""
-    pytest.importorskip("torch")
-    from paper_1605_07023_amd import runner
+def test_slice_w_min_agrees_with_the_library():
+    """The w_min of each slice's kernel descriptor, formed by the library's
+    gr_wslice_kernel (a host-only C entry point), equals the oracle's bit for
+    bit, so both sides pick the same planes; the rest of the descriptor is
+    copied unchanged."""
+    from paper_1605_07023_amd import binding as B
     rng = np.random.default_rng(17)
     for _ in range(2000):
         w_first = float(rng.uniform(-5e3, 5e3))
         inv_width = float(10.0 ** rng.uniform(-4, 1))
         w_min_rel = float(rng.uniform(-1e3, 0.0))
         s = int(rng.integers(0, 255))
-        assert runner.slice_w_min(w_first, inv_width, s, w_min_rel) == G.wslice_w_min(w_first, inv_width, s,
-                                                                                        w_min_rel)
+        table = B.GrKernel(B.GR_SEPARABLE, B.GR_F32, 1, 16, 8, 32, w_min_rel, 0.25, 1 << 20)
+        k = B.gr_wslice_kernel(table, w_first, inv_width, s)
+        assert k.w_min == G.wslice_w_min(w_first, inv_width, s, w_min_rel)
+        assert (k.kind, k.tap_dtype, k.taps_complex, k.support, k.oversample, k.n_planes, k.inv_dw, k.taps) == \
+            (table.kind, table.tap_dtype, table.taps_complex, table.support, table.oversample, table.n_planes,
+             table.inv_dw, table.taps)
+
+
+def test_slice_kernel_rejects_bad_arguments():
+    from paper_1605_07023_amd import binding as B
+    table = B.GrKernel(B.GR_SEPARABLE, B.GR_F32, 1, 16, 8, 32, -10.0, 0.25, 1 << 20)
+    for args in [(0.0, 0.0, 0), (0.0, -1.0, 0), (float("nan"), 1.0, 0), (0.0, 1.0, -1), (0.0, 1.0, 255)]:
+        with pytest.raises(B.GridderError):
+            B.gr_wslice_kernel(table, *args)
