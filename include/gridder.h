@@ -323,6 +323,24 @@ gr_status gr_grid(const double* uvw, const void* vis, int32_t vis_dtype, const f
                   int32_t width, const gr_tuning* tuning, void* workspace,
                   size_t workspace_bytes, int64_t* dev_stats, void* stream);
 
+/* gr_grid for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same arguments and result as gr_grid without `workspace`, which comes from
+ * a static device array of gr_grid_noalloc_scratch_bytes() bytes (64 MiB)
+ * that the library holds on every device it runs on until the process ends
+ * (its address is looked up once per device, on the first call there).
+ * Calls whose gr_grid_workspace_bytes exceeds it return GR_ENOMEM before
+ * anything is enqueued: with n_pol = 4, about 1.3 million visibilities on a
+ * 4096^2 grid.  Nothing is allocated and no allocating routine is called.
+ * Every call on one device shares that device's array, and the kernels
+ * clear what must start at zero; calls that overlap on one device (other
+ * streams, other threads) race on it and must be serialised by the caller. */
+size_t gr_grid_noalloc_scratch_bytes(void);
+gr_status gr_grid_noalloc(const double* uvw, const void* vis, int32_t vis_dtype, const float* vis_scale,
+                          const float* weights, int64_t n_vis, int32_t n_pol, const gr_kernel* kernel,
+                          double inv_cell_u, double inv_cell_v, void* grid, int32_t height,
+                          int32_t width, const gr_tuning* tuning, int64_t* dev_stats, void* stream);
+
 /* Autotuning (Section 4: the work decomposition is chosen by timing a
  * synthetic problem under many coarsening and work-group settings).
  * Times each of n_candidates tunings on preprocessed records/wvis: variant 1

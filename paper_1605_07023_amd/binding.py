@@ -128,6 +128,10 @@ def load_library():
     lib.gr_tuning_memo_clear.restype = None
     lib.gr_wslice_kernel.argtypes = [KP, D, D, I32, KP]
     lib.gr_wslice_kernel.restype = ctypes.c_int
+    lib.gr_grid_noalloc.argtypes = [P, P, I32, P, P, I64, I32, KP, D, D, P, I32, I32, TP, P, P]
+    lib.gr_grid_noalloc.restype = ctypes.c_int
+    lib.gr_grid_noalloc_scratch_bytes.argtypes = []
+    lib.gr_grid_noalloc_scratch_bytes.restype = SZ
     _lib = lib
     return lib
 
@@ -305,6 +309,19 @@ def gr_grid(uvw, vis, vis_dtype, vis_scale, weights, n_vis, n_pol, kernel: GrKer
                        width, ctypes.byref(tuning) if tuning is not None else None,
                        _ptr(workspace), workspace_bytes, _ptr(dev_stats),
                        _stream(stream, grid, uvw)))
+
+
+def gr_grid_noalloc(uvw, vis, vis_dtype, vis_scale, weights, n_vis, n_pol, kernel: GrKernel, inv_cell_u,
+                    inv_cell_v, grid, height, width, tuning: Optional[GrTuning], dev_stats, stream=None):
+    lib = load_library()
+    _check(lib.gr_grid_noalloc(_ptr(uvw), _ptr(vis), vis_dtype, _ptr(vis_scale), _ptr(weights), n_vis,
+                               n_pol, ctypes.byref(kernel), inv_cell_u, inv_cell_v, _ptr(grid), height,
+                               width, ctypes.byref(tuning) if tuning is not None else None,
+                               _ptr(dev_stats), _stream(stream, grid, uvw)))
+
+
+def gr_grid_noalloc_scratch_bytes() -> int:
+    return int(load_library().gr_grid_noalloc_scratch_bytes())
 
 
 def gr_make_kb_table(beta, support, oversample, out_dtype, out, stream=None):

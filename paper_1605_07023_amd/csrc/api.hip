@@ -562,3 +562,54 @@ extern "C" gr_status gr_wslice_kernel(const gr_kernel* table, double w_first, do
   return GR_OK;
 }
 
+// ---- gr_grid without a caller workspace: a static scratch array per device.
+// In host code `scratch` names a host-side stand-in, not device memory: its
+// device address is taken once per device with hipGetSymbolAddress (with that
+// device current) and only that address is passed on.
+namespace {
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;   // device ordinal -> address of `scratch` on it
+
+gr_status scratch_on_current_device(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(GR_EDEVICE, "gr_grid_noalloc: no current device");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  const auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return GR_OK;
+  }
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || ptr == nullptr)
+    return fail(GR_EDEVICE, std::string("gr_grid_noalloc: hipGetSymbolAddress of the scratch array: ") +
+                                hipGetErrorString(e));
+  g_scratch_ptr[dev] = ptr;
+  *out = ptr;
+  return GR_OK;
+}
+}  // namespace
+
+extern "C" size_t gr_grid_noalloc_scratch_bytes(void) { return kNoAllocScratchBytes; }
+
+extern "C" gr_status gr_grid_noalloc(const double* uvw, const void* vis, int32_t vis_dtype, const float* vis_scale,
+                                     const float* weights, int64_t n_vis, int32_t n_pol, const gr_kernel* kernel,
+                                     double inv_cell_u, double inv_cell_v, void* grid, int32_t height,
+                                     int32_t width, const gr_tuning* tuning, int64_t* dev_stats, void* stream) {
+  gr_status st = validate_kernel(kernel, true);
+  if (st != GR_OK) return st;
+  // resolve a NULL tuning once, so the size check and the call agree
+  gr_tuning memo_t;
+  tuning = resolve_tuning(tuning, n_pol, *kernel, height, width, 0, &memo_t);
+  const size_t need = gr_grid_workspace_bytes(n_vis, n_pol, kernel, height, width, tuning);
+  if (need > kNoAllocScratchBytes)
+    return fail(GR_ENOMEM, "gr_grid_noalloc: these arguments need " + std::to_string(need) +
+                               " bytes of scratch; the static scratch holds " +
+                               std::to_string(kNoAllocScratchBytes) + " (use gr_grid with a workspace)");
+  void* ws = nullptr;
+  if ((st = scratch_on_current_device(&ws)) != GR_OK) return st;
+  return gr_grid(uvw, vis, vis_dtype, vis_scale, weights, n_vis, n_pol, kernel, inv_cell_u, inv_cell_v, grid,
+                 height, width, tuning, ws, kNoAllocScratchBytes, dev_stats, stream);
+}
