@@ -700,6 +700,8 @@ def main() -> int:
     ap.add_argument("--cv", type=int, default=0)
     ap.add_argument("--variant", type=int, default=2, help="1: VALU work-item kernel, 2: MFMA")
     ap.add_argument("--seg-len", type=int, default=0)
+    ap.add_argument("--row-groups", type=int, default=0,
+                    help="MFMA gridder: row groups per wave (with --seg-len or --no-autotune; 0: default)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["f32", "f16", "bf16"], default="f32",
@@ -809,20 +811,27 @@ def main() -> int:
     seg_len = {S: args.seg_len for S in supports}
     tuned = {}
     if variant == 2 and not args.no_autotune and args.seg_len <= 0:
-        # Section 4: tune on a small synthetic data set (the first 128 baselines of
-        # the same geometry), then run the full batch with the winner
+        # Section 4: time the candidate decompositions, then run with the winner.  The
+        # sweep runs on the workload itself: on a 128-baseline subset the segments are
+        # shorter, and the row-group count it picked at S = 32 ran 6 % slower at full size
         from paper_1605_07023_amd import autotune
         for S in supports:
-            small = full_shape_workload(S, n_baselines=128)
-            sdw = runner.upload(small, dev, tap_dtype=tap_dt, taps=taps[S])
-            best, times = autotune.tune(sdw, autotune.candidates(P, S, variants=(2,)), reps=3)
+            sdw = runner.DeviceWorkload(wls[S], uvw, vis, None, taps[S], kern[S], tap_dt, vis_dt, vis_scale)
+            cands = autotune.candidates(P, S, variants=(2,))
+            # gr_autotune keeps the winner in the library's memo, where gr_grid_binned
+            # finds its row groups per wave for this problem class
+            best, times = autotune.tune(sdw, cands, reps=3)
             seg_len[S] = best.vis_per_wg
-            tuned[str(S)] = {"seg_len": best.vis_per_wg,
-                             "sweep_ms": {str(c.vis_per_wg): round(t, 4) for c, t in
-                                          zip(autotune.candidates(P, S, variants=(2,)), times)}}
-            log(f"autotune S={S}: seg_len {best.vis_per_wg}")
+            tuned[str(S)] = {"seg_len": best.vis_per_wg, "row_groups": best.wg_v,
+                             "sweep_ms": {f"{c.vis_per_wg}/rg{c.wg_v}": round(t, 4) for c, t in zip(cands, times)}}
+            log(f"autotune S={S}: seg_len {best.vis_per_wg}, row groups per wave {best.wg_v}")
             del sdw
         torch.cuda.synchronize()
+    elif variant == 2 and args.row_groups > 0:
+        for S in supports:     # a fixed configuration: into the memo that gr_grid_binned reads
+            B.gr_tuning_memo_put(P, kern[S], wls[S].height, wls[S].width, 0,
+                                 runner.tuning(0, 0, 0, args.row_groups, seg_len[S], 2))
+            tuned[str(S)] = {"seg_len": seg_len[S], "row_groups": args.row_groups, "sweep_ms": {}}
     rec = torch.empty((N, 2), dtype=torch.int32, device=dev)
     wvis = torch.empty((N, P), dtype=torch.complex64, device=dev)
     stats = torch.zeros(2, dtype=torch.int64, device=dev)

@@ -190,6 +190,9 @@ gr_status gr_preprocess_bin(const double* uvw, const void* vis, int32_t vis_dtyp
  * row part) work from a counter in the bins workspace and stage their own
  * visibility batches, or, when the table leaves too little LDS for that, one
  * 256-thread block per segment.
+ * The number of row groups one wave accumulates comes from the tuning memo's
+ * slot 0 entry for this problem class when that entry is a variant-2 tuning
+ * (its wg_v; see gr_tuning), else the default for the window.
  * support <= 56; the FP32 tap table [planes][O][S + 2] as (Re, Im) pairs plus
  * 12 KiB of staging must fit in 160 KiB.
  * With a GR_TABLE2D kernel the non-separable taps are read per visibility

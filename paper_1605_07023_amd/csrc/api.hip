@@ -448,7 +448,7 @@ extern "C" gr_status gr_degrid(const double* uvw, int64_t n_vis, int32_t n_pol, 
 
 extern "C" gr_status gr_grid_binned(const void* bins, int64_t n_vis, int32_t n_pol, const gr_kernel* kernel,
                                     int32_t seg_len, void* grid, int32_t height, int32_t width, void* stream) {
-  return grid_binned(bins, n_vis, n_pol, kernel, seg_len, grid, height, width, stream, 0);
+  return grid_binned(bins, n_vis, n_pol, kernel, seg_len, grid, height, width, stream, -1);
 }
 
 gr_status gr::grid_binned(const void* bins, int64_t n_vis, int32_t n_pol, const gr_kernel* kernel, int32_t seg_len,
@@ -461,6 +461,10 @@ gr_status gr::grid_binned(const void* bins, int64_t n_vis, int32_t n_pol, const 
   if (kernel->support > kMaxBinnedSupport) return fail(GR_EUNSUPPORTED, "the binned gridders need support <= 56");
   const BinLayout L = bin_layout(n_vis, n_pol, kernel->support, height, width,
                                  seg_len > 0 ? seg_len : kDefaultSegLen);
+  if (ng < 0) {   // the row groups per wave of the memo's variant-2 entry, else the default
+    gr_tuning t;
+    ng = memo_find(n_pol, *kernel, height, width, 0, &t) && t.variant == 2 ? t.wg_v : 0;
+  }
   return launch_binned(bins, L, n_pol, *kernel, reinterpret_cast<float2*>(grid), height, width,
                        (hipStream_t)stream, ng);
 }

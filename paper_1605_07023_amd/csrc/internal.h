@@ -137,7 +137,8 @@ size_t block_lds_bytes(const gr_kernel& k, int n_pol, bool tri);
 gr_status launch_mfma(const void* bins, const BinLayout& L, int n_pol, const gr_kernel& k,
                       float2* grid, int height, int width, hipStream_t stream, int ng = 0);
 
-// gr_grid_binned with the wave form's row groups per wave (api.hip; ng as launch_mfma).
+// gr_grid_binned with the wave form's row groups per wave (api.hip; ng as
+// launch_mfma; ng < 0: the memo's variant-2 entry for the problem class, if any).
 gr_status grid_binned(const void* bins, int64_t n_vis, int32_t n_pol, const gr_kernel* kernel, int32_t seg_len,
                       void* grid, int32_t height, int32_t width, void* stream, int ng);
 // The binned gridder for the kernel's kind (api.hip); ng as launch_mfma.

@@ -34,6 +34,18 @@ namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+
+// relu of two FP32 values rounded to FP16 (round to nearest even), as one packed
+// word: max(round(x), 0) = round(max(x, 0)), since rounding is monotonic and
+// keeps 0 (v_cvt_pk_f16_f32 and v_pk_max_f16, one instruction each per pair)
+__device__ __forceinline__ uint32_t relu_h2(f2v v) {
+  const h2v zero = {(_Float16)0.f, (_Float16)0.f};
+  const h2v h = __builtin_elementwise_max(__builtin_convertvector(v, h2v), zero);
+  return __builtin_bit_cast(uint32_t, h);
+}
 
 constexpr int kIn = 64, kHid = 64, kFeat = 36;
 
@@ -381,15 +393,23 @@ struct MlpGridDev {
 // the accumulator: relu(b + W^T h).
 __device__ __forceinline__ void layer_lds_bias(const h8 (&w)[4][2], const float* __restrict__ bias,
                                                const h8 (&h)[2], h8 (&out)[2], int lane) {
+  u4 words[2];
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt) {
     f4 d = *reinterpret_cast<const f4*>(bias + 16 * mt + 4 * (lane >> 4));
     d = __builtin_amdgcn_mfma_f32_16x16x32_f16(w[mt][0], h[0], d, 0, 0, 0);
     d = __builtin_amdgcn_mfma_f32_16x16x32_f16(w[mt][1], h[1], d, 0, 0, 0);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) out[mt >> 1][4 * (mt & 1) + i] = (_Float16)fmaxf(d[i], 0.f);
+    // element 4 (mt & 1) + i of out[mt / 2] is relu(d[i]); two elements per word
+    words[mt >> 1][2 * (mt & 1)] = relu_h2(f2v{d[0], d[1]});
+    words[mt >> 1][2 * (mt & 1) + 1] = relu_h2(f2v{d[2], d[3]});
   }
+  out[0] = __builtin_bit_cast(h8, words[0]);
+  out[1] = __builtin_bit_cast(h8, words[1]);
 }
+
+// pitch of the transposed layer-1 parts for the window of C x 16 cells: at
+// least its largest support (16, 32, 56), and 4 mod 8
+__host__ __device__ constexpr int mlp_pitch(int c) { return c == 2 ? 20 : c == 3 ? 36 : 60; }
 
 template <int P, int C>
 __device__ __forceinline__ void grid_mlp_body(const Record* __restrict__ rec, const float2* __restrict__ wvis,
@@ -402,11 +422,13 @@ __device__ __forceinline__ void grid_mlp_body(const Record* __restrict__ rec, co
   float* F = W1t + 24 * 64;                // [2][S][12] offset features, 0 = u, 1 = v
   // per-tap layer-1 parts stored transposed, [2][64][SP]: the 16 lanes of a tile
   // read 16 consecutive k of one f, and the lane groups' f offsets (4 apart) land
-  // 16 banks apart (SP = 4 mod 8), so those reads are free of bank conflicts
-  const int SP = S + ((4 - S) & 7);
+  // 16 banks apart (SP = 4 mod 8), so those reads are free of bank conflicts;
+  // SP is the window's largest support rounded so, a compile-time pitch, so
+  // every read's offset is an immediate of the LDS instruction
+  constexpr int SP = mlp_pitch(C);
   float* UV = F + 2 * S * 12;
-  float* cvis = UV + 2 * 64 * SP;          // [64]
-  float* zero = cvis + 64;                 // [2][S] 1 where the offset is outside the support
+  float* E = UV + 2 * 64 * SP;             // [64] the visibility's w features (12 used)
+  float* zero = E + 64;                    // [2][S] 1 where the offset is outside the support
   float2* taps = reinterpret_cast<float2*>(zero + 2 * S);   // [S * S] (2 S is even: 8-byte aligned)
   float* bias = reinterpret_cast<float*>(taps + S * S);    // [2][64] b2, b3 (S * S * 8 bytes: 16-byte aligned)
   const int seg = (int)blockIdx.x;
@@ -438,28 +460,43 @@ __device__ __forceinline__ void grid_mlp_body(const Record* __restrict__ rec, co
   for (int q = 0; q < len; ++q) {
     const Record r = rec[begin + q];
     __syncthreads();                                    // the previous visibility's LDS is consumed
-    if (t < 64) {                                       // per-visibility part of layer 1
-      const float x[3] = {x0_off + (float)rec_plane(r) * x0_step, 0.f, 0.f};
-      float a = blob[kB1 + t];
-      for (int f = 0; f < 12; ++f) a += feature(x, f) * blob[kW1 + f * kHid + t];
-      cvis[t] = a;
-    } else if (t < 64 + 2 * S) {                        // offset features, one (axis, k) each
-      const int e = t - 64, axis = e / S, k = e % S;
-      const int s = axis ? rec_sy(r) : rec_sx(r);
-      const float dd = ((float)k - half + 1.f - (float)s / (float)O) / half;
-      const float x[3] = {0.f, dd, dd};
-      for (int f = 0; f < 12; ++f) F[e * 12 + f] = feature(x, 12 * (1 + axis) + f);
-      zero[e] = fabsf(dd) < 1.f ? 0.f : 1.f;
+    // the features: sin and cos of pi 2^kf x for the visibility's w (items 0..5)
+    // and for the offset of every (axis, k) (items 6 + 6 e + kf), one sincos each
+    const float xw = x0_off + (float)rec_plane(r) * x0_step;
+    for (int it = t; it < 6 + 12 * S; it += 256) {
+      if (it < 6) {
+        float sn, cs;
+        sincospif(xw * (float)(1 << it), &sn, &cs);
+        E[2 * it] = sn;
+        E[2 * it + 1] = cs;
+      } else {
+        const int e = (it - 6) / 6, kf = (it - 6) - 6 * e, axis = e / S, k = e - axis * S;
+        const int s = axis ? rec_sy(r) : rec_sx(r);
+        const float dd = ((float)k - half + 1.f - (float)s / (float)O) / half;
+        float sn, cs;
+        sincospif(dd * (float)(1 << kf), &sn, &cs);
+        F[e * 12 + 2 * kf] = sn;
+        F[e * 12 + 2 * kf + 1] = cs;
+        if (kf == 0) zero[e] = fabsf(dd) < 1.f ? 0.f : 1.f;
+      }
     }
     __syncthreads();
-    for (int e = t; e < 2 * S * 64; e += 256) {         // U[j][k], V[j][k]
-      const int row = e >> 6, j = e & 63, axis = row / S, k = row - axis * S;
-      const float* fr = F + row * 12;
-      const float* wc = W1t + axis * 12 * 64 + j;
-      float a = 0.f;
+    {
+      // the per-visibility part of layer 1 for this thread's j (every e below has
+      // j = t mod 64), joined to the u part once per (j, k) in the order (c + U) + V
+      // of the layer-1 sum
+      const int j = t & 63;
+      float cj = blob[kB1 + j];
+      for (int f = 0; f < 12; ++f) cj += E[f] * blob[kW1 + f * kHid + j];
+      for (int e = t; e < 2 * S * 64; e += 256) {       // c[j] + U[j][k], V[j][k]
+        const int row = e >> 6, axis = row / S, k = row - axis * S;
+        const float* fr = F + row * 12;
+        const float* wc = W1t + axis * 12 * 64 + j;
+        float a = 0.f;
 #pragma unroll
-      for (int f = 0; f < 12; ++f) a += fr[f] * wc[f * 64];
-      UV[(axis * 64 + j) * SP + k] = a;
+        for (int f = 0; f < 12; ++f) a += fr[f] * wc[f * 64];
+        UV[(axis * 64 + j) * SP + k] = axis == 0 ? cj + a : a;
+      }
     }
     __syncthreads();
     // taps: the waves take 16-tap tiles in turn
@@ -471,12 +508,15 @@ __device__ __forceinline__ void grid_mlp_body(const Record* __restrict__ rec, co
       const float* V = UV + 64 * SP + kv;
       h8 h1[2], h2[2], h3[2];
 #pragma unroll
-      for (int kk = 0; kk < 2; ++kk)
+      for (int kk = 0; kk < 2; ++kk) {
+        u4 words;
 #pragma unroll
-        for (int qq = 0; qq < 8; ++qq) {
-          const int f = kidx(kk, lane >> 4, qq);
-          h1[kk][qq] = (_Float16)fmaxf(cvis[f] + U[f * SP] + V[f * SP], 0.f);
+        for (int qq = 0; qq < 8; qq += 2) {
+          const int f = kidx(kk, lane >> 4, qq);            // f + 1 is element qq + 1's
+          words[qq >> 1] = relu_h2(f2v{U[f * SP] + V[f * SP], U[(f + 1) * SP] + V[(f + 1) * SP]});
         }
+        h1[kk] = __builtin_bit_cast(h8, words);
+      }
       layer_lds_bias(w2, bias, h1, h2, lane);
       layer_lds_bias(w3, bias + kHid, h2, h3, lane);
       f4 dy = {0.f, 0.f, 0.f, 0.f};
@@ -550,8 +590,8 @@ grid_mlp_kernel_w64(const Record* __restrict__ rec, const float2* __restrict__ w
   grid_mlp_body<P, 4>(rec, wvis, segs, n_segs_p, blob, grid, d);
 }
 
-size_t grid_mlp_lds(int S) {
-  const size_t sp = (size_t)(S + ((4 - S) & 7));
+size_t grid_mlp_lds(int S, int window) {
+  const size_t sp = (size_t)mlp_pitch(window / 16);
   return sizeof(float) * (24 * 64 + 2 * (size_t)S * 12 + 2 * 64 * sp + 64 + 2 * (size_t)S) +
          sizeof(float2) * (size_t)S * S + sizeof(float) * 2 * kHid;
 }
@@ -569,10 +609,12 @@ gr_status launch_grid_mlp(const void* bins, const BinLayout& L, int n_pol, const
   const auto* segs = reinterpret_cast<const int4*>(base + L.off_segs);
   const auto* nsegs = reinterpret_cast<const int32_t*>(base + L.off_nsegs);
   MlpGridDev d{k.support, k.oversample, L.tile, L.n_tx, height, width};
-  const size_t lds = grid_mlp_lds(k.support);
   const int window = L.tile + k.support;             // 32, 48 or 64: the support's window
   if (window != 32 && window != 48 && window != 64)
     return fail(GR_EINVAL, "gr_grid_binned (network taps): binning tile does not match a 32, 48 or 64-cell window");
+  if (k.support > mlp_pitch(window / 16))
+    return fail(GR_EINVAL, "gr_grid_binned (network taps): support larger than its window's layer-1 pitch");
+  const size_t lds = grid_mlp_lds(k.support, window);
   using Fn = void (*)(const Record*, const float2*, const int4*, const int32_t*, const float*, float2*, MlpGridDev);
   Fn fn;
   if (n_pol == 4) fn = window == 32 ? grid_mlp_kernel<4, 2> : window == 48 ? grid_mlp_kernel<4, 3> : grid_mlp_kernel_w64<4>;
