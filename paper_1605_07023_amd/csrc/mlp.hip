@@ -411,6 +411,32 @@ __device__ __forceinline__ void layer_lds_bias(const h8 (&w)[4][2], const float*
 // least its largest support (16, 32, 56), and 4 mod 8
 __host__ __device__ constexpr int mlp_pitch(int c) { return c == 2 ? 20 : c == 3 ? 36 : 60; }
 
+// layer_lds_bias on two independent tiles with the same weights, their
+// products interleaved
+__device__ __forceinline__ void layer_lds_bias2(const h8 (&w)[4][2], const float* __restrict__ bias,
+                                                const h8 (&h)[2][2], h8 (&out)[2][2], int lane) {
+  u4 words[2][2];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    const f4 b = *reinterpret_cast<const f4*>(bias + 16 * mt + 4 * (lane >> 4));
+    f4 d[2] = {b, b};
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) d[c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w[mt][kk], h[c][kk], d[c], 0, 0, 0);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      words[c][mt >> 1][2 * (mt & 1)] = relu_h2(f2v{d[c][0], d[c][1]});
+      words[c][mt >> 1][2 * (mt & 1) + 1] = relu_h2(f2v{d[c][2], d[c][3]});
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    out[c][0] = __builtin_bit_cast(h8, words[c][0]);
+    out[c][1] = __builtin_bit_cast(h8, words[c][1]);
+  }
+}
+
 template <int P, int C>
 __device__ __forceinline__ void grid_mlp_body(const Record* __restrict__ rec, const float2* __restrict__ wvis,
                                               const int4* __restrict__ segs, const int32_t* __restrict__ n_segs_p,
@@ -418,8 +444,8 @@ __device__ __forceinline__ void grid_mlp_body(const Record* __restrict__ rec, co
                                               const MlpGridDev& d) {
   extern __shared__ __align__(16) float smg[];
   const int S = d.S, O = d.O;
-  float* W1t = smg;                        // [24][64]  rows 12..35 of W1
-  float* F = W1t + 24 * 64;                // [2][S][12] offset features, 0 = u, 1 = v
+  float* W1e = smg;                        // [12][64] rows 0..11 of W1 (w features)
+  float* F = W1e + 12 * 64;                // [2][S][12] offset features, 0 = u, 1 = v
   // per-tap layer-1 parts stored transposed, [2][64][SP]: the 16 lanes of a tile
   // read 16 consecutive k of one f, and the lane groups' f offsets (4 apart) land
   // 16 banks apart (SP = 4 mod 8), so those reads are free of bank conflicts;
@@ -434,7 +460,17 @@ __device__ __forceinline__ void grid_mlp_body(const Record* __restrict__ rec, co
   const int seg = (int)blockIdx.x;
   if (seg >= *n_segs_p) return;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  for (int e = t; e < 24 * 64; e += 256) W1t[e] = blob[kW1 + 12 * 64 + e];
+  // layer-1 weights of this thread's hidden unit j (every (j, k) entry it forms
+  // below has j = t mod 64): w features, u features, v features, and the bias
+  const int jh = t & 63;
+  float w1u[12], w1v[12];
+#pragma unroll
+  for (int f = 0; f < 12; ++f) {
+    w1u[f] = blob[kW1 + (12 + f) * kHid + jh];
+    w1v[f] = blob[kW1 + (24 + f) * kHid + jh];
+  }
+  const float b1j = blob[kB1 + jh];
+  for (int e = t; e < 12 * 64; e += 256) W1e[e] = blob[kW1 + e];
   if (t < 2 * kHid) bias[t] = t < kHid ? blob[kB2 + t] : blob[kB3 + t - kHid];
   h8 w2[4][2], w3[4][2], w4[1][2];
   float b4[1][4];
@@ -482,50 +518,80 @@ __device__ __forceinline__ void grid_mlp_body(const Record* __restrict__ rec, co
     }
     __syncthreads();
     {
-      // the per-visibility part of layer 1 for this thread's j (every e below has
-      // j = t mod 64), joined to the u part once per (j, k) in the order (c + U) + V
-      // of the layer-1 sum
-      const int j = t & 63;
-      float cj = blob[kB1 + j];
-      for (int f = 0; f < 12; ++f) cj += E[f] * blob[kW1 + f * kHid + j];
-      for (int e = t; e < 2 * S * 64; e += 256) {       // c[j] + U[j][k], V[j][k]
-        const int row = e >> 6, axis = row / S, k = row - axis * S;
-        const float* fr = F + row * 12;
-        const float* wc = W1t + axis * 12 * 64 + j;
-        float a = 0.f;
+      // the per-visibility part of layer 1 for this thread's j, joined to the u
+      // part once per (j, k) in the order (c + U) + V of the layer-1 sum
+      float ef[12];
 #pragma unroll
-        for (int f = 0; f < 12; ++f) a += fr[f] * wc[f * 64];
-        UV[(axis * 64 + j) * SP + k] = axis == 0 ? cj + a : a;
+      for (int q = 0; q < 3; ++q) {
+        const float4 v4 = reinterpret_cast<const float4*>(E)[q];
+        ef[4 * q] = v4.x; ef[4 * q + 1] = v4.y; ef[4 * q + 2] = v4.z; ef[4 * q + 3] = v4.w;
+      }
+      float cj = b1j;
+#pragma unroll
+      for (int f = 0; f < 12; ++f) cj += ef[f] * W1e[f * 64 + jh];
+      for (int e = t; e < 2 * S * 64; e += 256) {       // c[j] + U[j][k], V[j][k]
+        const int row = e >> 6, axis = row / S, k = row - axis * S;   // axis is uniform in a wave
+        const float4* fr = reinterpret_cast<const float4*>(F + row * 12);
+        float fv[12];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const float4 v4 = fr[q];
+          fv[4 * q] = v4.x; fv[4 * q + 1] = v4.y; fv[4 * q + 2] = v4.z; fv[4 * q + 3] = v4.w;
+        }
+        float a = 0.f;
+        if (axis == 0) {
+#pragma unroll
+          for (int f = 0; f < 12; ++f) a += fv[f] * w1u[f];
+        } else {
+#pragma unroll
+          for (int f = 0; f < 12; ++f) a += fv[f] * w1v[f];
+        }
+        UV[(axis * 64 + jh) * SP + k] = axis == 0 ? cj + a : a;
       }
     }
     __syncthreads();
-    // taps: the waves take 16-tap tiles in turn
-    for (int tb = wave * 16; tb < n_taps; tb += 64) {
-      const int tap = tb + (lane & 15);
-      const bool live = tap < n_taps;
-      const int ku = live ? tap % S : 0, kv = live ? tap / S : 0;
-      const float* U = UV + ku;
-      const float* V = UV + 64 * SP + kv;
-      h8 h1[2], h2[2], h3[2];
+    // taps: the waves take 16-tap tiles in turn, two at a time (tiles tb and
+    // tb + 64), so that each wave has two independent chains of layer products
+    // in flight
+    for (int tb = wave * 16; tb < n_taps; tb += 128) {
+      int tap[2], ku[2], kv[2];
+      bool live[2];
+      h8 h1[2][2], h2[2][2], h3[2][2];
 #pragma unroll
-      for (int kk = 0; kk < 2; ++kk) {
-        u4 words;
+      for (int c = 0; c < 2; ++c) {
+        tap[c] = tb + 64 * c + (lane & 15);
+        live[c] = tap[c] < n_taps;
+        ku[c] = live[c] ? tap[c] % S : 0;
+        kv[c] = live[c] ? tap[c] / S : 0;
+        const float* U = UV + ku[c];
+        const float* V = UV + 64 * SP + kv[c];
 #pragma unroll
-        for (int qq = 0; qq < 8; qq += 2) {
-          const int f = kidx(kk, lane >> 4, qq);            // f + 1 is element qq + 1's
-          words[qq >> 1] = relu_h2(f2v{U[f * SP] + V[f * SP], U[(f + 1) * SP] + V[(f + 1) * SP]});
+        for (int kk = 0; kk < 2; ++kk) {
+          u4 words;
+#pragma unroll
+          for (int qq = 0; qq < 8; qq += 2) {
+            const int f = kidx(kk, lane >> 4, qq);          // f + 1 is element qq + 1's
+            words[qq >> 1] = relu_h2(f2v{U[f * SP] + V[f * SP], U[(f + 1) * SP] + V[(f + 1) * SP]});
+          }
+          h1[c][kk] = __builtin_bit_cast(h8, words);
         }
-        h1[kk] = __builtin_bit_cast(h8, words);
       }
-      layer_lds_bias(w2, bias, h1, h2, lane);
-      layer_lds_bias(w3, bias + kHid, h2, h3, lane);
-      f4 dy = {0.f, 0.f, 0.f, 0.f};
-      dy = __builtin_amdgcn_mfma_f32_16x16x32_f16(w4[0][0], h3[0], dy, 0, 0, 0);
-      dy = __builtin_amdgcn_mfma_f32_16x16x32_f16(w4[0][1], h3[1], dy, 0, 0, 0);
-      const float2 y = make_float2(dy[0] + b4[0][0], dy[1] + b4[0][1]);
-      if (lane < 16 && live) {
-        const bool out = zero[ku] != 0.f || zero[S + kv] != 0.f;
-        taps[tap] = out ? make_float2(0.f, 0.f) : make_float2(out_scale * y.x, out_scale * y.y);
+      layer_lds_bias2(w2, bias, h1, h2, lane);
+      layer_lds_bias2(w3, bias + kHid, h2, h3, lane);
+      f4 dy[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) dy[c] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) dy[c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w4[0][kk], h3[c][kk], dy[c], 0, 0, 0);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const float2 y = make_float2(dy[c][0] + b4[0][0], dy[c][1] + b4[0][1]);
+        if (lane < 16 && live[c]) {
+          const bool out = zero[ku[c]] != 0.f || zero[S + kv[c]] != 0.f;
+          taps[tap[c]] = out ? make_float2(0.f, 0.f) : make_float2(out_scale * y.x, out_scale * y.y);
+        }
       }
     }
     __syncthreads();
@@ -592,7 +658,7 @@ grid_mlp_kernel_w64(const Record* __restrict__ rec, const float2* __restrict__ w
 
 size_t grid_mlp_lds(int S, int window) {
   const size_t sp = (size_t)mlp_pitch(window / 16);
-  return sizeof(float) * (24 * 64 + 2 * (size_t)S * 12 + 2 * 64 * sp + 64 + 2 * (size_t)S) +
+  return sizeof(float) * (12 * 64 + 2 * (size_t)S * 12 + 2 * 64 * sp + 64 + 2 * (size_t)S) +
          sizeof(float2) * (size_t)S * S + sizeof(float) * 2 * kHid;
 }
 
