@@ -493,6 +493,7 @@ __device__ __forceinline__ void grid_mlp_body(const Record* __restrict__ rec, co
 #pragma unroll
       for (int p = 0; p < P; ++p) acc[i][j][p] = make_float2(0.f, 0.f);
   const int n_taps = S * S;
+  const uint32_t magic_s = (uint32_t)((0x100000000ull + (uint64_t)S - 1) / (uint64_t)S);   // ceil(2^32 / S)
   for (int q = 0; q < len; ++q) {
     const Record r = rec[begin + q];
     __syncthreads();                                    // the previous visibility's LDS is consumed
@@ -529,8 +530,9 @@ __device__ __forceinline__ void grid_mlp_body(const Record* __restrict__ rec, co
       float cj = b1j;
 #pragma unroll
       for (int f = 0; f < 12; ++f) cj += ef[f] * W1e[f * 64 + jh];
-      for (int e = t; e < 2 * S * 64; e += 256) {       // c[j] + U[j][k], V[j][k]
-        const int row = e >> 6, axis = row / S, k = row - axis * S;   // axis is uniform in a wave
+      // the 2 S rows (axis, k) of F, four per pass of the block (one per wave):
+      // c[j] + U[j][k] for the u rows, V[j][k] for the v rows
+      auto row_part = [&](int row, const float (&w)[12]) -> float {
         const float4* fr = reinterpret_cast<const float4*>(F + row * 12);
         float fv[12];
 #pragma unroll
@@ -539,15 +541,12 @@ __device__ __forceinline__ void grid_mlp_body(const Record* __restrict__ rec, co
           fv[4 * q] = v4.x; fv[4 * q + 1] = v4.y; fv[4 * q + 2] = v4.z; fv[4 * q + 3] = v4.w;
         }
         float a = 0.f;
-        if (axis == 0) {
 #pragma unroll
-          for (int f = 0; f < 12; ++f) a += fv[f] * w1u[f];
-        } else {
-#pragma unroll
-          for (int f = 0; f < 12; ++f) a += fv[f] * w1v[f];
-        }
-        UV[(axis * 64 + jh) * SP + k] = axis == 0 ? cj + a : a;
-      }
+        for (int f = 0; f < 12; ++f) a += fv[f] * w[f];
+        return a;
+      };
+      for (int k = t >> 6; k < S; k += 4) UV[jh * SP + k] = cj + row_part(k, w1u);
+      for (int k = t >> 6; k < S; k += 4) UV[(64 + jh) * SP + k] = row_part(S + k, w1v);
     }
     __syncthreads();
     // taps: the waves take 16-tap tiles in turn, two at a time (tiles tb and
@@ -561,8 +560,9 @@ __device__ __forceinline__ void grid_mlp_body(const Record* __restrict__ rec, co
       for (int c = 0; c < 2; ++c) {
         tap[c] = tb + 64 * c + (lane & 15);
         live[c] = tap[c] < n_taps;
-        ku[c] = live[c] ? tap[c] % S : 0;
-        kv[c] = live[c] ? tap[c] / S : 0;
+        const int qv = (int)__umulhi((uint32_t)tap[c], magic_s);   // tap / S (tap < 2^12)
+        ku[c] = live[c] ? tap[c] - qv * S : 0;
+        kv[c] = live[c] ? qv : 0;
         const float* U = UV + ku[c];
         const float* V = UV + 64 * SP + kv[c];
 #pragma unroll
