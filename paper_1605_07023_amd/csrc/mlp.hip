@@ -407,9 +407,11 @@ __device__ __forceinline__ void layer_lds_bias(const h8 (&w)[4][2], const float*
   out[1] = __builtin_bit_cast(h8, words[1]);
 }
 
-// pitch of the transposed layer-1 parts for the window of C x 16 cells: at
-// least its largest support (16, 32, 56), and 4 mod 8
-__host__ __device__ constexpr int mlp_pitch(int c) { return c == 2 ? 20 : c == 3 ? 36 : 60; }
+// row pitch (floats) of the layer-1 parts, [axis][k][64 units] with 4 floats
+// of padding: the 16 lanes of a tap tile read 16 consecutive k at the same
+// units, 272 bytes apart, so each lane's 16-byte read lands on its own 4 of
+// the 64 banks
+constexpr int kUVP = 68;
 
 // layer_lds_bias on two independent tiles with the same weights, their
 // products interleaved
@@ -446,14 +448,11 @@ __device__ __forceinline__ void grid_mlp_body(const Record* __restrict__ rec, co
   const int S = d.S, O = d.O;
   float* W1e = smg;                        // [12][64] rows 0..11 of W1 (w features)
   float* F = W1e + 12 * 64;                // [2][S][12] offset features, 0 = u, 1 = v
-  // per-tap layer-1 parts stored transposed, [2][64][SP]: the 16 lanes of a tile
-  // read 16 consecutive k of one f, and the lane groups' f offsets (4 apart) land
-  // 16 banks apart (SP = 4 mod 8), so those reads are free of bank conflicts;
-  // SP is the window's largest support rounded so, a compile-time pitch, so
-  // every read's offset is an immediate of the LDS instruction
-  constexpr int SP = mlp_pitch(C);
+  // per-tap layer-1 parts, tap-major: UV[axis][k][unit] with row pitch kUVP, so
+  // that a lane's four runs of 4 consecutive units (the K layout of kidx) are
+  // four aligned 16-byte reads
   float* UV = F + 2 * S * 12;
-  float* E = UV + 2 * 64 * SP;             // [64] the visibility's w features (12 used)
+  float* E = UV + 2 * S * kUVP;            // [64] the visibility's w features (12 used)
   float* zero = E + 64;                    // [2][S] 1 where the offset is outside the support
   float2* taps = reinterpret_cast<float2*>(zero + 2 * S);   // [S * S] (2 S is even: 8-byte aligned)
   float* bias = reinterpret_cast<float*>(taps + S * S);    // [2][64] b2, b3 (S * S * 8 bytes: 16-byte aligned)
@@ -545,8 +544,8 @@ __device__ __forceinline__ void grid_mlp_body(const Record* __restrict__ rec, co
         for (int f = 0; f < 12; ++f) a += fv[f] * w[f];
         return a;
       };
-      for (int k = t >> 6; k < S; k += 4) UV[jh * SP + k] = cj + row_part(k, w1u);
-      for (int k = t >> 6; k < S; k += 4) UV[(64 + jh) * SP + k] = row_part(S + k, w1v);
+      for (int k = t >> 6; k < S; k += 4) UV[k * kUVP + jh] = cj + row_part(k, w1u);
+      for (int k = t >> 6; k < S; k += 4) UV[(S + k) * kUVP + jh] = row_part(S + k, w1v);
     }
     __syncthreads();
     // taps: the waves take 16-tap tiles in turn, two at a time (tiles tb and
@@ -563,15 +562,19 @@ __device__ __forceinline__ void grid_mlp_body(const Record* __restrict__ rec, co
         const int qv = (int)__umulhi((uint32_t)tap[c], magic_s);   // tap / S (tap < 2^12)
         ku[c] = live[c] ? tap[c] - qv * S : 0;
         kv[c] = live[c] ? qv : 0;
-        const float* U = UV + ku[c];
-        const float* V = UV + 64 * SP + kv[c];
+        const float* U = UV + ku[c] * kUVP;
+        const float* V = UV + (S + kv[c]) * kUVP;
 #pragma unroll
         for (int kk = 0; kk < 2; ++kk) {
           u4 words;
 #pragma unroll
-          for (int qq = 0; qq < 8; qq += 2) {
-            const int f = kidx(kk, lane >> 4, qq);          // f + 1 is element qq + 1's
-            words[qq >> 1] = relu_h2(f2v{U[f * SP] + V[f * SP], U[(f + 1) * SP] + V[(f + 1) * SP]});
+          for (int half = 0; half < 2; ++half) {
+            // elements 4 half .. 4 half + 3 are units kidx(kk, g, 4 half) + 0..3
+            const int f0 = kidx(kk, lane >> 4, 4 * half);
+            const float4 u = *reinterpret_cast<const float4*>(U + f0);
+            const float4 v = *reinterpret_cast<const float4*>(V + f0);
+            words[2 * half] = relu_h2(f2v{u.x + v.x, u.y + v.y});
+            words[2 * half + 1] = relu_h2(f2v{u.z + v.z, u.w + v.w});
           }
           h1[c][kk] = __builtin_bit_cast(h8, words);
         }
@@ -656,9 +659,8 @@ grid_mlp_kernel_w64(const Record* __restrict__ rec, const float2* __restrict__ w
   grid_mlp_body<P, 4>(rec, wvis, segs, n_segs_p, blob, grid, d);
 }
 
-size_t grid_mlp_lds(int S, int window) {
-  const size_t sp = (size_t)mlp_pitch(window / 16);
-  return sizeof(float) * (12 * 64 + 2 * (size_t)S * 12 + 2 * 64 * sp + 64 + 2 * (size_t)S) +
+size_t grid_mlp_lds(int S) {
+  return sizeof(float) * (12 * 64 + 2 * (size_t)S * 12 + 2 * (size_t)S * kUVP + 64 + 2 * (size_t)S) +
          sizeof(float2) * (size_t)S * S + sizeof(float) * 2 * kHid;
 }
 
@@ -678,9 +680,7 @@ gr_status launch_grid_mlp(const void* bins, const BinLayout& L, int n_pol, const
   const int window = L.tile + k.support;             // 32, 48 or 64: the support's window
   if (window != 32 && window != 48 && window != 64)
     return fail(GR_EINVAL, "gr_grid_binned (network taps): binning tile does not match a 32, 48 or 64-cell window");
-  if (k.support > mlp_pitch(window / 16))
-    return fail(GR_EINVAL, "gr_grid_binned (network taps): support larger than its window's layer-1 pitch");
-  const size_t lds = grid_mlp_lds(k.support, window);
+  const size_t lds = grid_mlp_lds(k.support);
   using Fn = void (*)(const Record*, const float2*, const int4*, const int32_t*, const float*, float2*, MlpGridDev);
   Fn fn;
   if (n_pol == 4) fn = window == 32 ? grid_mlp_kernel<4, 2> : window == 48 ? grid_mlp_kernel<4, 3> : grid_mlp_kernel_w64<4>;
