@@ -69,11 +69,6 @@ constexpr int kBatch = 256;        // visibilities staged per batch (block forms
 constexpr int kBatchWindow = 64;   // window of the batch gridder (batches bin for it)
 constexpr int kWaveBatch = 64;     // visibilities staged per batch (wave form)
 
-// LDS bytes of one wave's staging slice: staged rows, visibilities, pair masks
-__host__ __device__ constexpr size_t wave_slice_bytes(int n_pol) {
-  return (size_t)kWaveBatch * (sizeof(int4) + (size_t)n_pol * sizeof(float2)) + (kWaveBatch / 2) * sizeof(uint32_t);
-}
-
 template <bool CPLX>
 using TapT = typename std::conditional<CPLX, float2, float>::type;
 
@@ -374,6 +369,265 @@ __device__ __forceinline__ void wave_batch(const int4* __restrict__ b_inf, const
   }
 }
 
+// ---- wave form with a gapped tap table -------------------------------------
+// The wave form's table holds every row of S taps followed by WR - S zero
+// entries, after a lead of WR - S zeros: entry e = lead + row * WR + t for tap t
+// of a row.  A window-relative tap index lies in [-(WR - S - 1), WR - 1] (the
+// footprint origin is in the tile, WR - S cells, and the operand columns or rows
+// in the window), so every operand read of a row lands on its taps or on the
+// zeros around them: the address is the visibility's row start plus lane and
+// group constants, with no clamp (the constants go into the LDS instruction's
+// offset field).  Entries of complex taps are ES = 12 bytes, the triple
+// (-Im, Re, Im), where the table fits in LDS with that many wave slices, else
+// ES = 8 bytes (Re, Im), when the B operand of one lane class takes a sign flip
+// and the A operand two lane-constant factors; real taps are 4 bytes.
+template <bool CPLX, bool TRI>
+constexpr int gap_es() { return CPLX ? (TRI ? 12 : 8) : 4; }
+
+template <bool CPLX, bool TRI, int WR>
+__device__ __forceinline__ void stage_taps_gap(float* __restrict__ lds, const void* __restrict__ taps,
+                                               const MfmaDev& d) {
+  const int S = d.S, lead = WR - S;
+  const int n_elem = lead + d.n_rows_tab * WR;
+  for (int e = threadIdx.x; e < n_elem; e += blockDim.x) {
+    const int q = e - lead;
+    const int row = q >= 0 ? q / WR : 0;
+    const int t = q - row * WR;
+    const bool in = q >= 0 && t < S;
+    const int64_t src = (int64_t)row * S + (in ? t : 0);
+    if constexpr (CPLX) {
+      const float re = in ? load_tap32(taps, 2 * src, d.tap_dtype) : 0.f;
+      const float im = in ? load_tap32(taps, 2 * src + 1, d.tap_dtype) : 0.f;
+      if constexpr (TRI) {
+        lds[3 * e] = -im;
+        lds[3 * e + 1] = re;
+        lds[3 * e + 2] = im;
+      } else {
+        lds[2 * e] = re;
+        lds[2 * e + 1] = im;
+      }
+    } else {
+      lds[e] = in ? load_tap32(taps, src, d.tap_dtype) : 0.f;
+    }
+  }
+}
+
+// One lane's visibility of a wave-form batch as read from the binned stream.
+template <int P>
+struct WaveIn {
+  Record r;
+  float2 w[P];
+};
+
+// Read up to 64 visibilities (one per lane, lanes < n live) of a segment batch.
+template <int P>
+__device__ __forceinline__ void load_wave(const Record* __restrict__ rec, const float2* __restrict__ wvis,
+                                          int64_t first, int n, WaveIn<P>& in) {
+  const int lane = threadIdx.x & 63;
+  const bool live = lane < n;
+  in.r = live ? rec[first + lane] : Record{0, 0};
+  if constexpr (P == 4) {
+    const float4* src = reinterpret_cast<const float4*>(wvis + (first + (live ? lane : 0)) * 4);
+    const float4 a = live ? src[0] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 b = live ? src[1] : make_float4(0.f, 0.f, 0.f, 0.f);
+    in.w[0] = make_float2(a.x, a.y); in.w[1] = make_float2(a.z, a.w);
+    in.w[2] = make_float2(b.x, b.y); in.w[3] = make_float2(b.z, b.w);
+  } else {
+    in.w[0] = live ? wvis[first + lane] : make_float2(0.f, 0.f);
+  }
+}
+
+// Staged pair records of the wave form.  Per pair: for each of its two
+// visibilities {B start, A start, pair mask}, the LDS byte addresses of its
+// G^u and G^v rows minus ES times its window-relative x0 or y0, and the mask of
+// the row groups (bits 0..15) and column groups (bits 16..23) of the window
+// that either footprint touches; then the visibilities, P per visibility, as
+// (Re, Im) (triple table) or as (-Im, Re, Im) (pair table and real taps: lane
+// class comp reads the two values at comp * 4, which gives component comp of
+// G^v V with the same two multiplies as with triple entries, and component comp
+// of V as the second value).  A wave's slice holds the 32
+// records of a batch.
+template <int P, bool TRI>
+__host__ __device__ constexpr int gap_vis_bytes() { return TRI ? 8 : 12; }
+template <int P, bool TRI>
+__host__ __device__ constexpr int gap_rec_bytes() { return 24 + 2 * P * gap_vis_bytes<P, TRI>(); }
+__host__ __device__ constexpr size_t gap_slice_bytes(int n_pol, bool tri) {
+  return (size_t)(kWaveBatch / 2) *
+         (n_pol == 4 ? (tri ? gap_rec_bytes<4, true>() : gap_rec_bytes<4, false>())
+                     : (tri ? gap_rec_bytes<1, true>() : gap_rec_bytes<1, false>()));
+}
+struct __attribute__((aligned(4))) Inf3 {
+  uint32_t u, v, box;
+};
+typedef __attribute__((address_space(3))) const Inf3 lds_inf3;
+
+// Stage a batch read by load_wave (lanes < n live) as pair records in pairing
+// order (the bitonic Morton sort of pair_rank).  Slot `pad` (>= 0 for an odd
+// batch) takes a copy of the last visibility's rows with zero visibility.
+// Called by all 64 lanes of a wave.
+template <int P, bool CPLX, bool TRI, int WR>
+__device__ __forceinline__ void stage_wave_gap(const WaveIn<P>& in, int n, int win_x0, int win_y0,
+                                               const MfmaDev& d, uint32_t tab_base, unsigned char* __restrict__ slice,
+                                               int pad) {
+  constexpr int RG = 16 / P;
+  constexpr int ES = gap_es<CPLX, TRI>();
+  constexpr int RB = gap_rec_bytes<P, TRI>();
+  constexpr int VS = gap_vis_bytes<P, TRI>();
+  const int lane = threadIdx.x & 63;
+  const bool live = lane < n;
+  const Record r = in.r;
+  const int xr = rec_x0(r) - win_x0, yr = rec_y0(r) - win_y0;
+  uint32_t sk = live ? (((spread6((uint32_t)xr) | (spread6((uint32_t)yr) << 1)) << 6) | (uint32_t)lane)
+                     : ((1u << 20) | (uint32_t)lane);
+#pragma unroll
+  for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const uint32_t other = (uint32_t)__shfl_xor((int)sk, j);
+      const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
+      sk = keep_min ? min(sk, other) : max(sk, other);
+    }
+  }
+  // lane i holds the i-th key: its visibility's rank goes back to the owner, its
+  // footprint origin comes to lane i, and lane i^1 holds the pair partner's
+  const int src_lane = (int)(sk & 63u);
+  const int rank = __builtin_amdgcn_ds_permute(src_lane << 2, lane);
+  const int xy_own = xr | (yr << 8);
+  const int xy = __builtin_amdgcn_ds_bpermute(src_lane << 2, xy_own);
+  const int xy_partner = __shfl_xor(xy, 1);
+  // the pair mask, formed by the even lane of each sorted pair and sent back to
+  // the owners of both members
+  uint32_t box = 0u;
+  {
+    const int xb = (lane + 1 < n) ? xy_partner : xy;
+    const int xa_ = xy & 0xff, ya_ = xy >> 8, xb_ = xb & 0xff, yb_ = xb >> 8;
+    const int g_lo = min(ya_, yb_) / RG, g_hi = (max(ya_, yb_) + d.S - 1) / RG;
+    const int c_lo = min(xa_, xb_) >> 3, c_hi = (max(xa_, xb_) + d.S - 1) >> 3;
+    const uint32_t rbits = ((2u << g_hi) - 1u) & ~((1u << g_lo) - 1u);
+    const uint32_t cbits = ((2u << c_hi) - 1u) & ~((1u << c_lo) - 1u);
+    box = rbits | (cbits << 16);
+  }
+  const uint32_t box_even = (uint32_t)__shfl(box, rank & ~1);    // the mask of the owner's pair
+  if (live) {
+    const int lead = WR - d.S;
+    const uint32_t bu = tab_base + (uint32_t)((lead + (rec_plane(r) * d.O + rec_sx(r)) * WR - xr) * ES);
+    const uint32_t av = tab_base + (uint32_t)((lead + (rec_plane(r) * d.O + rec_sy(r)) * WR - yr) * ES);
+    unsigned char* rec = slice + (rank >> 1) * RB;
+    uint32_t* inf = reinterpret_cast<uint32_t*>(rec + (rank & 1) * 12);
+    inf[0] = bu; inf[1] = av; inf[2] = box_even;
+    if (pad >= 0 && rank == n - 1) {                  // n - 1 is even here: slot n is its partner
+      inf[3] = bu; inf[4] = av; inf[5] = box_even;
+    }
+    float* vis = reinterpret_cast<float*>(rec + 24 + (rank & 1) * P * VS);
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      if constexpr (TRI) {
+        vis[2 * p] = in.w[p].x;
+        vis[2 * p + 1] = in.w[p].y;
+      } else {
+        vis[3 * p] = -in.w[p].y;
+        vis[3 * p + 1] = in.w[p].x;
+        vis[3 * p + 2] = in.w[p].y;
+      }
+    }
+  }
+  if (pad >= 0 && lane < P * VS / 4)
+    reinterpret_cast<float*>(slice + (pad >> 1) * RB + 24 + P * VS)[lane] = 0.f;
+}
+
+// The work of one wave of the wave form on one staged batch (gapped table): row
+// groups part + j * PARTS (j < NG) and all WCG column groups of the window.
+template <int P, bool CPLX, bool TRI, int WCG, int NG, int PARTS>
+__device__ __forceinline__ void wave_batch_gap(const unsigned char* __restrict__ slice, int nb, int part,
+                                               f4 (&acc)[NG][WCG]) {
+  constexpr int RG = 16 / P;
+  constexpr int ES = gap_es<CPLX, TRI>();
+  constexpr int RB = gap_rec_bytes<P, TRI>();
+  constexpr int VS = gap_vis_bytes<P, TRI>();
+  const int lane = threadIdx.x & 63;
+  const int kk = lane >> 4;                          // K index: (v, re|im)
+  const int v = kk >> 1, comp = kk & 1;
+  const int m = lane & 15;                           // A row / B column
+  const int ar = (P == 4) ? (m >> 2) : m;
+  const int ap = (P == 4) ? (m & 3) : 0;
+  const int bx = m >> 1, bcomp = m & 1;
+  // B: (comp, bcomp) = (0,0) Re g, (0,1) Im g, (1,0) -Im g, (1,1) Re g
+  uint32_t off_b = (uint32_t)(bx * ES);
+  uint32_t sgn_b = 0u;
+  float bm = 1.f;
+  if constexpr (CPLX && TRI) off_b += (comp == 1 && bcomp == 0) ? 0u : (comp == 0 && bcomp == 1) ? 8u : 4u;
+  if constexpr (CPLX && !TRI) {
+    off_b += comp == bcomp ? 0u : 4u;
+    sgn_b = (comp == 1 && bcomp == 0) ? 0x80000000u : 0u;
+  }
+  if constexpr (!CPLX) bm = comp == bcomp ? 1.f : 0.f;
+  // A: component comp of G^v V for row part * RG + ar of the window
+  const uint32_t off_a = (uint32_t)((part * RG + ar) * ES) + ((CPLX && TRI) ? (uint32_t)(comp * 4) : 0u);
+  // this lane's fields of a pair record
+  const uint32_t base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const unsigned char*)slice;
+  const uint32_t l_inf = base + (uint32_t)(v * 12);
+  const uint32_t l_vis = base + (uint32_t)(24 + (v * P + ap) * VS + (TRI ? 0 : comp * 4));
+  auto pair = [&](uint32_t o) {
+    const lds_inf3* ip = (lds_inf3*)(uintptr_t)(l_inf + o);
+    const Inf3 inf{ip->u, ip->v, ip->box};
+    const Pair4 vv = lds_read2(l_vis + o);
+    const uint32_t box = __builtin_amdgcn_readfirstlane(inf.box);
+    float bfr[WCG];
+    {
+      const uint32_t b = inf.u + off_b;
+#pragma unroll
+      for (int c = 0; c < WCG; ++c) bfr[c] = lds_read(b + (uint32_t)(c * 8 * ES));
+    }
+    Pair4 at[NG];
+    float as[NG];
+    {
+      const uint32_t a = inf.v + off_a;
+#pragma unroll
+      for (int j = 0; j < NG; ++j) {
+        const uint32_t aj = a + (uint32_t)(j * PARTS * RG * ES);
+        if constexpr (CPLX) at[j] = lds_read2(aj);
+        else as[j] = lds_read(aj);
+      }
+    }
+    if constexpr (CPLX && !TRI) {
+#pragma unroll
+      for (int c = 0; c < WCG; ++c) bfr[c] = __uint_as_float(__float_as_uint(bfr[c]) ^ sgn_b);
+    }
+    if constexpr (!CPLX) {
+#pragma unroll
+      for (int c = 0; c < WCG; ++c) bfr[c] *= bm;
+    }
+    // component comp of G^v V: with triple taps the lane read (-Im, Re) or (Re, Im)
+    // of the tap and (Re, Im) of V; with pair taps (Re, Im) of the tap and (-Im, Re)
+    // or (Re, Im) of V
+    float afr[NG];
+    if constexpr (CPLX) {
+#pragma unroll
+      for (int j = 0; j < NG; ++j) afr[j] = at[j].a * vv.b + at[j].b * vv.a;
+    } else {
+#pragma unroll
+      for (int j = 0; j < NG; ++j) afr[j] = as[j] * vv.b;      // real taps: vv.b is component comp of V
+    }
+    const uint32_t rb = box >> part, cm = box >> 16;
+#pragma unroll
+    for (int j = 0; j < NG; ++j) {
+      if (__builtin_expect((rb >> (j * PARTS)) & 1u, 1)) {
+#pragma unroll
+        for (int c = 0; c < WCG; ++c) {
+          if (__builtin_expect((cm >> c) & 1u, 1))
+            acc[j][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[j], bfr[c], acc[j][c], 0, 0, 0);
+        }
+      }
+    }
+  };
+  // two pairs per iteration, the second at an immediate offset
+  for (int q = 0; q < nb; q += 4) {
+    const uint32_t o = (uint32_t)(q >> 1) * RB;
+    pair(o);
+    if (q + 2 < nb) pair(o + RB);
+  }
+}
+
 // The work of one wave on one batch of a segment: the window rows of the NG
 // row groups whose first rows are row0 + j * GSTRIDE (j < NG), all WCG column
 // groups of the window at columns win_x0 + 8 c.  b_inf / b_vis hold nb
@@ -593,8 +847,9 @@ grid_mfma_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvis
   }
 }
 
-// Wave form (see the file header).  PARTS = (WR / RG) / NG items per segment.
-template <int P, bool CPLX, int WR, int WCG, int NG, int THREADS>
+// Wave form (see the file header).  PARTS = (WR / RG) / NG items per segment;
+// TRI: triple table entries (complex taps).
+template <int P, bool CPLX, int WR, int WCG, int NG, int THREADS, bool TRI>
 __global__ void __launch_bounds__(THREADS)
 grid_mfma_waves(const Record* __restrict__ rec, const float2* __restrict__ wvis,
                 const int4* __restrict__ segs, const int32_t* __restrict__ n_segs_p,
@@ -602,15 +857,14 @@ grid_mfma_waves(const Record* __restrict__ rec, const float2* __restrict__ wvis,
                 float2* __restrict__ grid, MfmaDev d, uint32_t tap_bytes) {
   constexpr int RG = 16 / P;
   constexpr int PARTS = WR / RG / NG;
+  constexpr int ES = gap_es<CPLX, TRI>();
   static_assert(PARTS * NG * RG == WR, "window rows must split into parts of NG row groups");
   static_assert(WR / RG <= 16 && WCG <= 8, "pair masks hold 16 row groups and 8 column groups");
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  int4* b_inf = reinterpret_cast<int4*>(lds_raw + tap_bytes + (size_t)wave * wave_slice_bytes(P));
-  float2* b_vis = reinterpret_cast<float2*>(b_inf + kWaveBatch);
-  uint32_t* b_box = reinterpret_cast<uint32_t*>(b_vis + kWaveBatch * P);
+  unsigned char* slice = lds_raw + tap_bytes + (size_t)wave * gap_slice_bytes(P, TRI);
   const uint32_t tab_base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned char*)lds_raw;
-  stage_taps_wave<CPLX>(reinterpret_cast<float*>(lds_raw), taps, d);
+  stage_taps_gap<CPLX, TRI, WR>(reinterpret_cast<float*>(lds_raw), taps, d);
   __syncthreads();                                    // the only block barrier
   const int n_items = *n_segs_p * PARTS;
   for (;;) {
@@ -631,14 +885,15 @@ grid_mfma_waves(const Record* __restrict__ rec, const float2* __restrict__ wvis,
       for (int c = 0; c < WCG; ++c) acc[j][c] = f4{0.f, 0.f, 0.f, 0.f};
     for (int b0 = 0; b0 < len; b0 += kWaveBatch) {
       const int nb = min(kWaveBatch, len - b0);
+      WaveIn<P> in;
+      load_wave<P>(rec, wvis, (int64_t)begin + b0, nb, in);
       // the wave's own slice: LDS operations of one wave execute in order, so
       // only the compiler must be kept from moving accesses across these points
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       // an odd batch (nb <= 63 here) is padded in slot nb
-      stage_wave<P, CPLX>(rec, wvis, (int64_t)begin + b0, nb, win_x0, win_y0, d, tab_base, b_inf, b_vis, b_box,
-                          (nb & 1) ? nb : -1);
+      stage_wave_gap<P, CPLX, TRI, WR>(in, nb, win_x0, win_y0, d, tab_base, slice, (nb & 1) ? nb : -1);
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      wave_batch<P, CPLX, WCG, NG, PARTS>(b_inf, b_vis, b_box, nb, part, d.S, acc);
+      wave_batch_gap<P, CPLX, TRI, WCG, NG, PARTS>(slice, nb, part, acc);
     }
     flush_window<P, WCG, NG, PARTS * RG>(acc, row0, win_x0, grid, d);
   }
@@ -714,7 +969,9 @@ using WaveFn = void (*)(const Record*, const float2*, const int4*, const int32_t
 // Wave-form launch shape: threads per block (one block per CU) from the
 // accumulator registers of a wave, NG x WCG x 4: four waves per SIMD up to 72,
 // three up to 128, else two.
-constexpr int wave_threads(int ng, int wcg) { return ng * wcg * 4 <= 72 ? 1024 : ng * wcg * 4 <= 128 ? 768 : 512; }
+constexpr int wave_threads(int ng, int wcg) {
+  return ng * wcg * 4 <= 72 ? 1024 : ng * wcg * 4 <= 128 ? 768 : ng * wcg * 4 <= 168 ? 512 : 256;
+}
 using PersistFn = void (*)(const BatchInst*, const int32_t*, int, const int32_t*, int32_t*);
 
 // window edge (cells) for a support: footprints of a tile of edge WR - S fit it
@@ -762,51 +1019,64 @@ struct WaveCfg {
   int threads, ng;
 };
 
-template <int P, bool CPLX, int WR, int WCG, int NG>
+template <int P, bool CPLX, int WR, int WCG, int NG, bool TRI>
 WaveCfg wave_cfg() {
-  return WaveCfg{grid_mfma_waves<P, CPLX, WR, WCG, NG, wave_threads(NG, WCG)>, wave_threads(NG, WCG), NG};
+  return WaveCfg{grid_mfma_waves<P, CPLX, WR, WCG, NG, wave_threads(NG, WCG), TRI>, wave_threads(NG, WCG), NG};
 }
 
 int default_ng(int n_pol, int wr) { return n_pol == 4 ? (wr == 48 ? 3 : wr == 32 ? 8 : 2) : 1; }
 
 // ng <= 0: the default; an NG with no instance: fn = nullptr
-template <int P, bool CPLX>
+template <int P, bool CPLX, bool TRI>
 WaveCfg wave_fn(int wr, int ng) {
   if (ng <= 0) ng = default_ng(P, wr);
   if constexpr (P == 4) {
     if (wr == 32) {
-      if (ng == 2) return wave_cfg<4, CPLX, 32, 4, 2>();
-      if (ng == 4) return wave_cfg<4, CPLX, 32, 4, 4>();
-      if (ng == 8) return wave_cfg<4, CPLX, 32, 4, 8>();
+      if (ng == 2) return wave_cfg<4, CPLX, 32, 4, 2, TRI>();
+      if (ng == 4) return wave_cfg<4, CPLX, 32, 4, 4, TRI>();
+      if (ng == 8) return wave_cfg<4, CPLX, 32, 4, 8, TRI>();
     } else if (wr == 48) {
-      if (ng == 2) return wave_cfg<4, CPLX, 48, 6, 2>();
-      if (ng == 3) return wave_cfg<4, CPLX, 48, 6, 3>();
-      if (ng == 4) return wave_cfg<4, CPLX, 48, 6, 4>();
-      if (ng == 6) return wave_cfg<4, CPLX, 48, 6, 6>();
+      if (ng == 2) return wave_cfg<4, CPLX, 48, 6, 2, TRI>();
+      if (ng == 3) return wave_cfg<4, CPLX, 48, 6, 3, TRI>();
+      if (ng == 4) return wave_cfg<4, CPLX, 48, 6, 4, TRI>();
+      if (ng == 6) return wave_cfg<4, CPLX, 48, 6, 6, TRI>();
     } else {
-      if (ng == 2) return wave_cfg<4, CPLX, 64, 8, 2>();
-      if (ng == 4) return wave_cfg<4, CPLX, 64, 8, 4>();
+      if (ng == 2) return wave_cfg<4, CPLX, 64, 8, 2, TRI>();
+      if (ng == 4) return wave_cfg<4, CPLX, 64, 8, 4, TRI>();
     }
   } else {
     if (wr == 32) {
-      if (ng == 1) return wave_cfg<1, CPLX, 32, 4, 1>();
-      if (ng == 2) return wave_cfg<1, CPLX, 32, 4, 2>();
+      if (ng == 1) return wave_cfg<1, CPLX, 32, 4, 1, TRI>();
+      if (ng == 2) return wave_cfg<1, CPLX, 32, 4, 2, TRI>();
     } else if (wr == 48) {
-      if (ng == 1) return wave_cfg<1, CPLX, 48, 6, 1>();
-      if (ng == 3) return wave_cfg<1, CPLX, 48, 6, 3>();
+      if (ng == 1) return wave_cfg<1, CPLX, 48, 6, 1, TRI>();
+      if (ng == 3) return wave_cfg<1, CPLX, 48, 6, 3, TRI>();
     } else {
-      if (ng == 1) return wave_cfg<1, CPLX, 64, 8, 1>();
-      if (ng == 2) return wave_cfg<1, CPLX, 64, 8, 2>();
-      if (ng == 4) return wave_cfg<1, CPLX, 64, 8, 4>();
+      if (ng == 1) return wave_cfg<1, CPLX, 64, 8, 1, TRI>();
+      if (ng == 2) return wave_cfg<1, CPLX, 64, 8, 2, TRI>();
+      if (ng == 4) return wave_cfg<1, CPLX, 64, 8, 4, TRI>();
     }
   }
   return WaveCfg{nullptr, 0, ng};
 }
 
+WaveCfg wave_fn_for(int n_pol, bool cplx, bool tri, int wr, int ng) {
+  if (n_pol == 4) return !cplx ? wave_fn<4, false, false>(wr, ng) : tri ? wave_fn<4, true, true>(wr, ng)
+                                                                          : wave_fn<4, true, false>(wr, ng);
+  return !cplx ? wave_fn<1, false, false>(wr, ng) : tri ? wave_fn<1, true, true>(wr, ng)
+                                                        : wave_fn<1, true, false>(wr, ng);
+}
+
+// LDS bytes of the wave form's gapped table (triple, pair or real entries)
+size_t gap_tab_bytes(const gr_kernel& k, int wr, bool tri) {
+  const size_t es = k.taps_complex ? (tri ? 12 : 8) : 4;
+  return align256(((size_t)(wr - k.support) + (size_t)k.n_planes * k.oversample * wr) * es);
+}
+
 int wave_parts(int n_pol, int wr, int ng) { return wr / (16 / n_pol) / ng; }
 
 // wave = true: the wave form's (-Im, Re, Im) entries; false: the block forms' (Re, Im)
-size_t tap_lds_bytes(const gr_kernel& k, bool wave = false) {
+size_t tap_lds_bytes(const gr_kernel& k, bool wave) {
   const size_t per = k.taps_complex ? (wave ? 12 : 8) : 4;
   return align256((size_t)k.n_planes * k.oversample * (k.support + 2) * per);
 }
@@ -857,13 +1127,18 @@ gr_status launch_mfma(const void* bins, const BinLayout& L, int n_pol, const gr_
   d.n_blocks = (uint32_t)nb;
   const int wr = window_of(k.support);
   if (L.tile + k.support > wr) return fail(GR_EINVAL, "binning tile does not fit the gridder window");
-  // wave form when the table leaves room for the wave slices
-  WaveCfg wc;
-  if (n_pol == 4) wc = k.taps_complex ? wave_fn<4, true>(wr, ng) : wave_fn<4, false>(wr, ng);
-  else wc = k.taps_complex ? wave_fn<1, true>(wr, ng) : wave_fn<1, false>(wr, ng);
+  // wave form when the table leaves room for the wave slices: triple entries
+  // when they fit, else (Re, Im) pairs
+  bool wtri = k.taps_complex != 0;
+  WaveCfg wc = wave_fn_for(n_pol, k.taps_complex != 0, wtri, wr, ng);
   if (wc.fn == nullptr)
     return fail(GR_EUNSUPPORTED, "tuning: no MFMA gridder with this many row groups per wave for the window");
-  const size_t wave_lds = tap_lds_bytes(k, true) + (size_t)(wc.threads / 64) * wave_slice_bytes(n_pol);
+  size_t wave_lds = gap_tab_bytes(k, wr, wtri) + (size_t)(wc.threads / 64) * gap_slice_bytes(n_pol, wtri);
+  if (wtri && wave_lds > 160 * 1024) {
+    wtri = false;
+    wc = wave_fn_for(n_pol, true, false, wr, ng);
+    wave_lds = gap_tab_bytes(k, wr, false) + (size_t)(wc.threads / 64) * gap_slice_bytes(n_pol, wtri);
+  }
   if (wave_lds <= 160 * 1024) {
     if ((st = ensure_lds_limit(reinterpret_cast<const void*>(wc.fn), wave_lds, "gr_grid_binned")) != GR_OK)
       return st;
@@ -874,7 +1149,7 @@ gr_status launch_mfma(const void* bins, const BinLayout& L, int n_pol, const gr_
     const int waves = wc.threads / 64;
     const int blocks = (int)std::min<int64_t>((int64_t)device_cus(), (items + waves - 1) / waves);
     hipLaunchKernelGGL(wc.fn, dim3((unsigned)blocks), dim3(wc.threads), wave_lds, stream, rec, wv, segs,
-                       nsegs, counter, k.taps, grid, d, (uint32_t)tap_lds_bytes(k, true));
+                       nsegs, counter, k.taps, grid, d, (uint32_t)gap_tab_bytes(k, wr, wtri));
     return check_launch("gr_grid_binned (mfma waves)");
   }
   // block form: triple entries when they fit, else (Re, Im) pairs
