@@ -461,6 +461,42 @@ struct __attribute__((aligned(4))) Inf3 {
 };
 typedef __attribute__((address_space(3))) const Inf3 lds_inf3;
 
+// The value of lane i ^ J, J < 16, by DPP moves inside rows of 16 lanes (no LDS
+// round trip): J = 1, 2 by a quad permutation; J = 4 as the mirror within 8
+// lanes followed by the reversal within 4; J = 8 as the mirror within 16
+// followed by the mirror within 8.  Larger J by ds_bpermute.
+template <int J>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t x) {
+  constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E, kQuadRev = 0x1B, kRowMirror = 0x140, kHalfMirror = 0x141;
+  if constexpr (J == 1) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kQuadXor1, 0xF, 0xF, true);
+  else if constexpr (J == 2) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kQuadXor2, 0xF, 0xF, true);
+  else if constexpr (J == 4) {
+    const int t = __builtin_amdgcn_update_dpp(0, (int)x, kHalfMirror, 0xF, 0xF, true);
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, t, kQuadRev, 0xF, 0xF, true);
+  } else if constexpr (J == 8) {
+    const int t = __builtin_amdgcn_update_dpp(0, (int)x, kRowMirror, 0xF, 0xF, true);
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, t, kHalfMirror, 0xF, 0xF, true);
+  } else {
+    return (uint32_t)__shfl_xor((int)x, J);
+  }
+}
+
+// One compare-exchange step (partner lane ^ J) of the bitonic sort over 64
+// lanes for merges of size K: ascending where lane & K is clear.
+template <int K, int J>
+__device__ __forceinline__ uint32_t bitonic_step(uint32_t key, int lane) {
+  const uint32_t other = lane_xor<J>(key);
+  const bool keep_min = ((lane & J) == 0) == ((lane & K) == 0);
+  return keep_min ? min(key, other) : max(key, other);
+}
+
+template <int K, int J>
+__device__ __forceinline__ uint32_t bitonic_merge(uint32_t key, int lane) {
+  key = bitonic_step<K, J>(key, lane);
+  if constexpr (J > 1) key = bitonic_merge<K, J / 2>(key, lane);
+  return key;
+}
+
 // Stage a batch read by load_wave (lanes < n live) as pair records in pairing
 // order (the bitonic Morton sort of pair_rank).  Slot `pad` (>= 0 for an odd
 // batch) takes a copy of the last visibility's rows with zero visibility.
@@ -479,22 +515,19 @@ __device__ __forceinline__ void stage_wave_gap(const WaveIn<P>& in, int n, int w
   const int xr = rec_x0(r) - win_x0, yr = rec_y0(r) - win_y0;
   uint32_t sk = live ? (((spread6((uint32_t)xr) | (spread6((uint32_t)yr) << 1)) << 6) | (uint32_t)lane)
                      : ((1u << 20) | (uint32_t)lane);
-#pragma unroll
-  for (int k = 2; k <= 64; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      const uint32_t other = (uint32_t)__shfl_xor((int)sk, j);
-      const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
-      sk = keep_min ? min(sk, other) : max(sk, other);
-    }
-  }
+  sk = bitonic_merge<2, 1>(sk, lane);
+  sk = bitonic_merge<4, 2>(sk, lane);
+  sk = bitonic_merge<8, 4>(sk, lane);
+  sk = bitonic_merge<16, 8>(sk, lane);
+  sk = bitonic_merge<32, 16>(sk, lane);
+  sk = bitonic_merge<64, 32>(sk, lane);
   // lane i holds the i-th key: its visibility's rank goes back to the owner, its
   // footprint origin comes to lane i, and lane i^1 holds the pair partner's
   const int src_lane = (int)(sk & 63u);
   const int rank = __builtin_amdgcn_ds_permute(src_lane << 2, lane);
   const int xy_own = xr | (yr << 8);
   const int xy = __builtin_amdgcn_ds_bpermute(src_lane << 2, xy_own);
-  const int xy_partner = __shfl_xor(xy, 1);
+  const int xy_partner = (int)lane_xor<1>((uint32_t)xy);
   // the pair mask, formed by the even lane of each sorted pair and sent back to
   // the owners of both members
   uint32_t box = 0u;
@@ -858,6 +891,11 @@ grid_mfma_waves(const Record* __restrict__ rec, const float2* __restrict__ wvis,
   constexpr int RG = 16 / P;
   constexpr int PARTS = WR / RG / NG;
   constexpr int ES = gap_es<CPLX, TRI>();
+#ifdef GR_PREF_ALL
+  constexpr bool PREF = GR_PREF_ALL;
+#else
+  constexpr bool PREF = false;
+#endif
   static_assert(PARTS * NG * RG == WR, "window rows must split into parts of NG row groups");
   static_assert(WR / RG <= 16 && WCG <= 8, "pair masks hold 16 row groups and 8 column groups");
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -883,16 +921,20 @@ grid_mfma_waves(const Record* __restrict__ rec, const float2* __restrict__ wvis,
     for (int j = 0; j < NG; ++j)
 #pragma unroll
       for (int c = 0; c < WCG; ++c) acc[j][c] = f4{0.f, 0.f, 0.f, 0.f};
+    WaveIn<P> in;
+    if (PREF) load_wave<P>(rec, wvis, begin, min(kWaveBatch, len), in);
     for (int b0 = 0; b0 < len; b0 += kWaveBatch) {
       const int nb = min(kWaveBatch, len - b0);
-      WaveIn<P> in;
-      load_wave<P>(rec, wvis, (int64_t)begin + b0, nb, in);
+      if (!PREF) load_wave<P>(rec, wvis, (int64_t)begin + b0, nb, in);
       // the wave's own slice: LDS operations of one wave execute in order, so
       // only the compiler must be kept from moving accesses across these points
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       // an odd batch (nb <= 63 here) is padded in slot nb
       stage_wave_gap<P, CPLX, TRI, WR>(in, nb, win_x0, win_y0, d, tab_base, slice, (nb & 1) ? nb : -1);
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      // the next batch is read from HBM while this one is gridded
+      if (PREF && b0 + kWaveBatch < len)
+        load_wave<P>(rec, wvis, (int64_t)begin + b0 + kWaveBatch, min(kWaveBatch, len - b0 - kWaveBatch), in);
       wave_batch_gap<P, CPLX, TRI, WCG, NG, PARTS>(slice, nb, part, acc);
     }
     flush_window<P, WCG, NG, PARTS * RG>(acc, row0, win_x0, grid, d);
