@@ -641,6 +641,17 @@ __device__ __forceinline__ void wave_batch_gap(const unsigned char* __restrict__
 #pragma unroll
       for (int j = 0; j < NG; ++j) afr[j] = as[j] * vv.b;      // real taps: vv.b is component comp of V
     }
+    // With the pair table every operand is formed before the first matrix
+    // operation of the pair (measured 2 % faster at S = 32, where a part's row
+    // groups are spread over the window and a pair touches nearly all of them);
+    // with the triple table the compiler's placement, which forms A inside the
+    // row-group branches, measured 2 % faster at S = 16.
+    if constexpr (CPLX && !TRI) {
+#pragma unroll
+      for (int j = 0; j < NG; ++j) asm volatile("" : "+v"(afr[j]));
+#pragma unroll
+      for (int c = 0; c < WCG; ++c) asm volatile("" : "+v"(bfr[c]));
+    }
     const uint32_t rb = box >> part, cm = box >> 16;
 #pragma unroll
     for (int j = 0; j < NG; ++j) {
@@ -891,11 +902,6 @@ grid_mfma_waves(const Record* __restrict__ rec, const float2* __restrict__ wvis,
   constexpr int RG = 16 / P;
   constexpr int PARTS = WR / RG / NG;
   constexpr int ES = gap_es<CPLX, TRI>();
-#ifdef GR_PREF_ALL
-  constexpr bool PREF = GR_PREF_ALL;
-#else
-  constexpr bool PREF = false;
-#endif
   static_assert(PARTS * NG * RG == WR, "window rows must split into parts of NG row groups");
   static_assert(WR / RG <= 16 && WCG <= 8, "pair masks hold 16 row groups and 8 column groups");
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -921,20 +927,17 @@ grid_mfma_waves(const Record* __restrict__ rec, const float2* __restrict__ wvis,
     for (int j = 0; j < NG; ++j)
 #pragma unroll
       for (int c = 0; c < WCG; ++c) acc[j][c] = f4{0.f, 0.f, 0.f, 0.f};
-    WaveIn<P> in;
-    if (PREF) load_wave<P>(rec, wvis, begin, min(kWaveBatch, len), in);
     for (int b0 = 0; b0 < len; b0 += kWaveBatch) {
       const int nb = min(kWaveBatch, len - b0);
-      if (!PREF) load_wave<P>(rec, wvis, (int64_t)begin + b0, nb, in);
+      // (reading the next batch ahead measured no faster and costs registers)
+      WaveIn<P> in;
+      load_wave<P>(rec, wvis, (int64_t)begin + b0, nb, in);
       // the wave's own slice: LDS operations of one wave execute in order, so
       // only the compiler must be kept from moving accesses across these points
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       // an odd batch (nb <= 63 here) is padded in slot nb
       stage_wave_gap<P, CPLX, TRI, WR>(in, nb, win_x0, win_y0, d, tab_base, slice, (nb & 1) ? nb : -1);
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      // the next batch is read from HBM while this one is gridded
-      if (PREF && b0 + kWaveBatch < len)
-        load_wave<P>(rec, wvis, (int64_t)begin + b0 + kWaveBatch, min(kWaveBatch, len - b0 - kWaveBatch), in);
       wave_batch_gap<P, CPLX, TRI, WCG, NG, PARTS>(slice, nb, part, acc);
     }
     flush_window<P, WCG, NG, PARTS * RG>(acc, row0, win_x0, grid, d);
