@@ -154,19 +154,27 @@ degrid_kernel(const Record* __restrict__ rec, const int32_t* __restrict__ idx, c
       const int c_hi = __builtin_amdgcn_readfirstlane((xhi + S - 1) >> 1);
       const uint64_t cmask = ((2ull << c_hi) - 1ull) & ~((1ull << c_lo) - 1ull);
       // B: visibility v's G^u tap at cell 8c + 2s + xk, as the (bcomp, comp) entry of the complex product
+      // (bcomp, comp) = (0,0) and (1,1): Re t; (0,1): Im t; (1,0): -Im t, one read of the
+      // entry's component and a lane-constant sign
+      const float* tabf = reinterpret_cast<const float*>(tab);
+      const int bsel = bcomp == comp ? 0 : 1;
+      const uint32_t bsgn = (bcomp == 1 && comp == 0) ? 0x80000000u : 0u;
       float bfr[WCG][4];
 #pragma unroll
       for (int c = 0; c < WCG; ++c) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           if (!((cmask >> (4 * c + s)) & 1ull)) continue;   // uniform; the value is not used
-          const float2 t = tab[rowu + tap_slot(8 * c + 2 * s + xk - xr, S)];
-          bfr[c][s] = bcomp == comp ? t.x : (bcomp ? -t.y : t.y);
+          const float t = tabf[2 * (rowu + tap_slot(8 * c + 2 * s + xk - xr, S)) + bsel];
+          bfr[c][s] = __uint_as_float(__float_as_uint(t) ^ bsgn);
         }
       }
-      float vacc[P == 4 ? 4 : 1];
+      // stage 2 sums, per lane: pr = sum Re(t) Z_own, pi = sum Im(t) Z_own over its rows; the
+      // complex product takes the partner lane's pi once, after the last row group
+      constexpr int NA = P == 4 ? 4 : 1;
+      float pr[NA], pi[NA];
 #pragma unroll
-      for (int i = 0; i < (P == 4 ? 4 : 1); ++i) vacc[i] = 0.f;
+      for (int i = 0; i < NA; ++i) pr[i] = pi[i] = 0.f;
       // wave-uniform mask of the row groups in the batch's footprints
       const uint32_t rmask = ((2u << g_hi) - 1u) & ~((1u << g_lo) - 1u);
 #pragma unroll
@@ -192,21 +200,22 @@ degrid_kernel(const Record* __restrict__ rec, const int32_t* __restrict__ idx, c
         // stage 2: D row 4k + i of this lane is (row k, pol i) at P = 4, row 4k + i at P = 1
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const float zown = z[i];
-          // the other component of Z sits in the neighbouring lane: a DPP quad permutation (1, 0, 3, 2)
-          const float zpart =
-              __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(zown), 0xB1, 0xF, 0xF, true));
           const int row = j * RG + ((P == 4) ? k : 4 * k + i);
           const float2 tv = tab[rowv + tap_slot(row - yr, S)];
-          const float t_im = comp ? tv.y : -tv.y;
-          float& va = vacc[(P == 4) ? i : 0];
-          va = fmaf(tv.x, zown, va);
-          va = fmaf(t_im, zpart, va);
+          pr[(P == 4) ? i : 0] = fmaf(tv.x, z[i], pr[(P == 4) ? i : 0]);
+          pi[(P == 4) ? i : 0] = fmaf(tv.y, z[i], pi[(P == 4) ? i : 0]);
         }
       }
-      // add the partial sums of the 4 row lanes; lanes 0..15 write (visibility, component)
+      // the complex product: component 0 is sum Re(t) Z_re - Im(t) Z_im, component 1 is
+      // sum Re(t) Z_im + Im(t) Z_re; Z's other component sits in the neighbouring lane
+      // (DPP quad permutation (1, 0, 3, 2)).  Then the partial sums of the 4 row lanes are
+      // added; lanes 0..15 write (visibility, component).
+      float vacc[NA];
 #pragma unroll
-      for (int i = 0; i < (P == 4 ? 4 : 1); ++i) {
+      for (int i = 0; i < NA; ++i) {
+        const float pi_partner =
+            __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(pi[i]), 0xB1, 0xF, 0xF, true));
+        vacc[i] = comp ? pr[i] + pi_partner : pr[i] - pi_partner;
         vacc[i] += __shfl_xor(vacc[i], 16);
         vacc[i] += __shfl_xor(vacc[i], 32);
       }
