@@ -109,30 +109,70 @@ degrid_kernel(const Record* __restrict__ rec, const int32_t* __restrict__ idx, c
   const int S = d.S;
   const int n_items = *n_segs_p;
 
+  // The next segment's window is read from HBM into registers while the current
+  // one is degridded (each thread its share, issued after its wave's last record
+  // read of the segment, so that no record read waits for it); the 64-cell window
+  // at P = 4 would need 32 more registers and loads its window after the barrier.
+  constexpr int WE = WR * P * WR;                                        // window values
+  constexpr int PER = (WE + kDegridThreads - 1) / kDegridThreads;        // per thread
+  constexpr bool PF = PER <= 9;
+  float2 nxt[PF ? PER : 1];
+  auto fetch = [&](int sgi) {
+    const int4 q = segs[sgi];
+    const int wx0 = (q.z % d.n_tx) * d.tile, wy0 = (q.z / d.n_tx) * d.tile;
+#pragma unroll
+    for (int u = 0; u < (PF ? PER : 1); ++u) {
+      const int e = threadIdx.x + u * kDegridThreads;
+      const int x = e % WR, t = e / WR, p = t % P, row = t / P;
+      const int gy = wy0 + row, gx = wx0 + x;
+      nxt[u] = (e < WE && gy < d.H && gx < d.W) ? grid[((int64_t)p * d.H + gy) * d.W + gx] : make_float2(0.f, 0.f);
+    }
+  };
+  __syncthreads();                                   // the table is staged
+  if (threadIdx.x == 0) s_seg = atomicAdd(counter, 1);
+  __syncthreads();
+  int seg = s_seg;
+  if (PF && seg < n_items) fetch(seg);
   for (;;) {
-    __syncthreads();                                 // previous window consumed (and the table staged)
-    if (threadIdx.x == 0) s_seg = atomicAdd(counter, 1);
-    __syncthreads();
-    const int seg = s_seg;
     if (seg >= n_items) break;                       // uniform for the block
+    __syncthreads();                                 // previous window consumed
     const int4 sg = segs[seg];
     const int begin = sg.x, len = sg.y, tile_id = sg.z;
     const int win_x0 = (tile_id % d.n_tx) * d.tile;
     const int win_y0 = (tile_id / d.n_tx) * d.tile;
     // the window, all polarisations; cells past the grid edge read as zero
-    for (int e = threadIdx.x; e < WR * P * WR; e += blockDim.x) {
-      const int x = e % WR, t = e / WR, p = t % P, row = t / P;
-      const int gy = win_y0 + row, gx = win_x0 + x;
-      float2 g = make_float2(0.f, 0.f);
-      if (gy < d.H && gx < d.W) g = grid[((int64_t)p * d.H + gy) * d.W + gx];
-      *reinterpret_cast<float2*>(win + (row * P + p) * LS + 2 * x) = g;
+    if constexpr (PF) {
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int e = threadIdx.x + u * kDegridThreads;
+        if (e < WE) {
+          const int x = e % WR, t = e / WR, p = t % P, row = t / P;
+          *reinterpret_cast<float2*>(win + (row * P + p) * LS + 2 * x) = nxt[u];
+        }
+      }
+    } else {
+      for (int e = threadIdx.x; e < WE; e += blockDim.x) {
+        const int x = e % WR, t = e / WR, p = t % P, row = t / P;
+        const int gy = win_y0 + row, gx = win_x0 + x;
+        float2 g = make_float2(0.f, 0.f);
+        if (gy < d.H && gx < d.W) g = grid[((int64_t)p * d.H + gy) * d.W + gx];
+        *reinterpret_cast<float2*>(win + (row * P + p) * LS + 2 * x) = g;
+      }
     }
-    __syncthreads();
+    if (threadIdx.x == 0) s_seg = atomicAdd(counter, 1);
+    __syncthreads();                                 // window complete, next segment claimed
+    const int seg_next = s_seg;
+    bool fetched = !PF || seg_next >= n_items;
 
     for (int b0 = wave * kVisPerBatch; b0 < len; b0 += n_waves * kVisPerBatch) {
       const int nb = min(kVisPerBatch, len - b0);
       const bool live = v < nb;
       const Record r = rec[begin + b0 + (live ? v : 0)];
+      const int64_t n_out = idx[begin + b0 + (live ? v : 0)];
+      if (!fetched && b0 + n_waves * kVisPerBatch >= len) {   // this wave's last batch of the segment
+        fetch(seg_next);
+        fetched = true;
+      }
       const int xr = rec_x0(r) - win_x0, yr = rec_y0(r) - win_y0;
       // a missing visibility reads the zero row: its B values and G^v taps are 0
       const int zero_row = d.n_rows_tab * (S + 2);
@@ -220,12 +260,13 @@ degrid_kernel(const Record* __restrict__ rec, const int32_t* __restrict__ idx, c
         vacc[i] += __shfl_xor(vacc[i], 32);
       }
       if (k == 0 && live) {
-        const int64_t n = idx[begin + b0 + v];
-        float* out = reinterpret_cast<float*>(vis_out) + n * P * 2 + comp;
+        float* out = reinterpret_cast<float*>(vis_out) + n_out * P * 2 + comp;
 #pragma unroll
         for (int i = 0; i < (P == 4 ? 4 : 1); ++i) out[2 * i] = vacc[i];
       }
     }
+    if (!fetched) fetch(seg_next);                   // a wave with no batch in this segment
+    seg = seg_next;
   }
 }
 
