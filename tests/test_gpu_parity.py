@@ -154,14 +154,37 @@ def test_grid_points_mfma(R, S, P, seg):
     assert stats.cpu().tolist() == [wl.n_vis - dropped, dropped] and dropped > 0
 
 
-# The single-problem MFMA gridder has three forms, chosen by the LDS its tap
-# table needs (complex W taps, S = 32, O = 8: 408 B per table row as (-Im, Re, Im)
-# triples, 272 B as (Re, Im) pairs; 160 KiB of LDS):
-#   wave form: table + 16 wave slices (P = 4: 3200 B, P = 1: 1664 B each);
-#   block form, triple entries: table + 12,800 B (P = 4) / 6,656 B (P = 1);
+# The single-problem MFMA gridder has four forms, chosen by the LDS its tap
+# table needs (complex W taps, O = 8; 160 KiB of LDS):
+#   wave form, gapped table (rows of W entries, W = 48 at S = 32, 32 at S = 16, plus
+#   a lead of W - S), triple entries (12 B) or (Re, Im) pairs (8 B), + one slice of
+#   32 pair records per wave (16 waves at S = 32, 12 at S = 16; P = 4: 2816 B with
+#   triples, 3840 B with pairs; P = 1: 1280 B / 1536 B);
+#   block form, rows of S + 2 entries, triple: table + 12,800 B (P = 4) / 6,656 B (P = 1);
 #   block form, (Re, Im) pairs: pair table + 12,288 B (P = 4).
-# 40 planes (320 rows) at P = 4 take the triple block form, 60 planes (480 rows)
-# the pair block form, 48 planes (384 rows) at P = 1 the triple block form.
+# At S = 32, 40 planes (320 rows) at P = 4 take the triple block form, 60 planes (480
+# rows) the pair block form, 48 planes (384 rows) at P = 1 the triple block form.
+# Wave form table kinds: at S = 32, P = 4, 5 planes fit triple entries, 32 planes
+# (256 rows, the full-shape table) only pairs; at P = 1, 36 planes (288 rows) take
+# pairs; at S = 16, P = 4, 48 planes (384 rows) take pairs.  Integer visibilities and
+# taps keep every sum exact, so each kind must equal the FP64 oracle bit for bit.
+@pytest.mark.parametrize("S,P,planes,rg", [(32, 4, 5, 0), (32, 4, 32, 0), (32, 4, 32, 4), (32, 1, 36, 0),
+                                           (16, 4, 5, 0), (16, 4, 48, 0), (16, 4, 48, 4)])
+def test_wave_form_table_kinds_bit_exact(R, S, P, planes, rg):
+    _say(f"wave form table kinds, integer inputs, S={S} P={P} planes={planes} row groups={rg}")
+    rng = np.random.default_rng(S * 100 + planes + P)
+    wl = random_point_workload(3000, P, 120, 104, S, 8, seed=planes + S, n_planes=planes, margin=4,
+                               weights=False, kernel="wsep")
+    wl.vis = (rng.integers(-2, 3, (wl.n_vis, P)) + 1j * rng.integers(-2, 3, (wl.n_vis, P))).astype(np.complex64)
+    taps = rng.integers(-1, 2, (planes, 8, S)) + 1j * rng.integers(-1, 2, (planes, 8, S))
+    taps_np = np.stack([taps.real, taps.imag], axis=-1)
+    g = _custom_taps_run(R, wl, taps_np, R.tuning(0, 0, 0, rg, 0, variant=2))
+    ref, dropped = _oracle_grid(wl, taps)
+    assert wl.n_vis - dropped > 2000
+    assert np.abs(ref).max() < 2 ** 20
+    np.testing.assert_array_equal(g.astype(np.complex128), ref)
+
+
 @pytest.mark.parametrize("P,planes,seg", [(4, 40, 0), (4, 40, 77), (4, 60, 0), (1, 48, 9)])
 def test_grid_points_mfma_block_forms(R, P, planes, seg):
     _say(f"grid random points MFMA block forms P={P} planes={planes} seg_len={seg}")
