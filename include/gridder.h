@@ -189,7 +189,11 @@ gr_status gr_preprocess_bin(const double* uvw, const void* vis, int32_t vis_dtyp
  * (1024 threads; 768 for W = 32 with n_pol = 4) whose waves take (segment,
  * row part) work from a counter in the bins workspace and stage their own
  * visibility batches, or, when the table leaves too little LDS for that, one
- * 256-thread block per segment.
+ * 256-thread block per segment.  The first form keeps W - S zero entries after
+ * every table row (and before the first), so that no operand address needs a
+ * clamp: W - S + planes x O x W entries of 12 bytes ((-Im, Re, Im)) where that
+ * fits beside the waves' staging (32 pair records each, 1.3 to 3.8 KiB),
+ * else of 8 bytes ((Re, Im)).
  * The number of row groups one wave accumulates comes from the tuning memo's
  * slot 0 entry for this problem class when that entry is a variant-2 tuning
  * (its wg_v; see gr_tuning), else the default for the window.
