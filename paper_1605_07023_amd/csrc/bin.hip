@@ -434,6 +434,7 @@ BinLayout bin_layout(int64_t n_vis, int n_pol, int support, int height, int widt
   L.off_segs = off;    off += align256(sizeof(int4) * (size_t)L.max_segs);
   L.off_nsegs = off;   off += 256;
   L.off_scan = off;    off += align256(2 * sizeof(int32_t) * (size_t)((L.n_tiles + kScanTiles - 1) / kScanTiles));
+  L.off_perm = off;    off += align256(sizeof(int32_t) * (size_t)n_vis);   // the MFMA gridder's pairing order
   L.bytes = off;
   return L;
 }

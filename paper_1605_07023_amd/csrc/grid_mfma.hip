@@ -32,13 +32,14 @@
 //    stages the tap table once (Section 4 stages the GCF in local memory); its
 //    16 waves then work without block barriers, each taking
 //    (segment, part) items from an atomic counter, where part p of a window is
-//    the row groups p, p + parts, p + 2 parts, ...  Each wave stages its own
-//    batches of 64 visibilities in its own LDS slice, sorted into pairs of
-//    nearby footprints, each visibility as the LDS addresses of its two tap
-//    rows and each pair as the mask of D tiles it touches (decoded once, not
-//    per use).  Its table entries are (-Im, Re, Im) triples, so that every
-//    operand is one read at a lane-constant offset, clamped to the tap row by
-//    one v_med3 on its address.
+//    the row groups p, p + parts, p + 2 parts, ...  A small kernel first
+//    orders each segment by the set of D tiles its footprints touch, so that
+//    consecutive visibilities, which the wave form pairs, touch the same
+//    tiles.  Each wave stages its own batches of 64 visibilities in its own
+//    LDS slice, each visibility as the LDS addresses of its two tap rows and
+//    each pair as the mask of D tiles it touches (decoded once, not per use).
+//    Its table is gapped (zeros around every row of taps, so that operand
+//    reads need no clamp), with (-Im, Re, Im) entries where they fit.
 //  * grid_mfma_kernel: one 256-thread block per segment, its 4 waves sharing
 //    the segment's window rows (the form used when the table leaves too little
 //    LDS for 16 wave slices).
@@ -419,21 +420,23 @@ struct WaveIn {
   float2 w[P];
 };
 
-// Read up to 64 visibilities (one per lane, lanes < n live) of a segment batch.
+// Read up to 64 visibilities (one per lane, lanes < n live) of a segment batch,
+// the entries order[first + lane] of the binned stream.
 template <int P>
 __device__ __forceinline__ void load_wave(const Record* __restrict__ rec, const float2* __restrict__ wvis,
-                                          int64_t first, int n, WaveIn<P>& in) {
+                                          const int32_t* __restrict__ order, int64_t first, int n, WaveIn<P>& in) {
   const int lane = threadIdx.x & 63;
   const bool live = lane < n;
-  in.r = live ? rec[first + lane] : Record{0, 0};
+  const int64_t e = live ? (int64_t)order[first + lane] : 0;
+  in.r = live ? rec[e] : Record{0, 0};
   if constexpr (P == 4) {
-    const float4* src = reinterpret_cast<const float4*>(wvis + (first + (live ? lane : 0)) * 4);
+    const float4* src = reinterpret_cast<const float4*>(wvis + e * 4);
     const float4 a = live ? src[0] : make_float4(0.f, 0.f, 0.f, 0.f);
     const float4 b = live ? src[1] : make_float4(0.f, 0.f, 0.f, 0.f);
     in.w[0] = make_float2(a.x, a.y); in.w[1] = make_float2(a.z, a.w);
     in.w[2] = make_float2(b.x, b.y); in.w[3] = make_float2(b.z, b.w);
   } else {
-    in.w[0] = live ? wvis[first + lane] : make_float2(0.f, 0.f);
+    in.w[0] = live ? wvis[e] : make_float2(0.f, 0.f);
   }
 }
 
@@ -461,46 +464,16 @@ struct __attribute__((aligned(4))) Inf3 {
 };
 typedef __attribute__((address_space(3))) const Inf3 lds_inf3;
 
-// The value of lane i ^ J, J < 16, by DPP moves inside rows of 16 lanes (no LDS
-// round trip): J = 1, 2 by a quad permutation; J = 4 as the mirror within 8
-// lanes followed by the reversal within 4; J = 8 as the mirror within 16
-// followed by the mirror within 8.  Larger J by ds_bpermute.
-template <int J>
-__device__ __forceinline__ uint32_t lane_xor(uint32_t x) {
-  constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E, kQuadRev = 0x1B, kRowMirror = 0x140, kHalfMirror = 0x141;
-  if constexpr (J == 1) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kQuadXor1, 0xF, 0xF, true);
-  else if constexpr (J == 2) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kQuadXor2, 0xF, 0xF, true);
-  else if constexpr (J == 4) {
-    const int t = __builtin_amdgcn_update_dpp(0, (int)x, kHalfMirror, 0xF, 0xF, true);
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, t, kQuadRev, 0xF, 0xF, true);
-  } else if constexpr (J == 8) {
-    const int t = __builtin_amdgcn_update_dpp(0, (int)x, kRowMirror, 0xF, 0xF, true);
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, t, kHalfMirror, 0xF, 0xF, true);
-  } else {
-    return (uint32_t)__shfl_xor((int)x, J);
-  }
+// The value of lane i ^ 1 (a DPP quad permutation, no LDS round trip).
+__device__ __forceinline__ uint32_t lane_xor1(uint32_t x) {
+  constexpr int kQuadXor1 = 0xB1;
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kQuadXor1, 0xF, 0xF, true);
 }
 
-// One compare-exchange step (partner lane ^ J) of the bitonic sort over 64
-// lanes for merges of size K: ascending where lane & K is clear.
-template <int K, int J>
-__device__ __forceinline__ uint32_t bitonic_step(uint32_t key, int lane) {
-  const uint32_t other = lane_xor<J>(key);
-  const bool keep_min = ((lane & J) == 0) == ((lane & K) == 0);
-  return keep_min ? min(key, other) : max(key, other);
-}
-
-template <int K, int J>
-__device__ __forceinline__ uint32_t bitonic_merge(uint32_t key, int lane) {
-  key = bitonic_step<K, J>(key, lane);
-  if constexpr (J > 1) key = bitonic_merge<K, J / 2>(key, lane);
-  return key;
-}
-
-// Stage a batch read by load_wave (lanes < n live) as pair records in pairing
-// order (the bitonic Morton sort of pair_rank).  Slot `pad` (>= 0 for an odd
-// batch) takes a copy of the last visibility's rows with zero visibility.
-// Called by all 64 lanes of a wave.
+// Stage a batch read by load_wave (lanes < n live) as pair records: lanes 2q
+// and 2q + 1 form pair q (the segment's pairing order, order_segments_kernel).
+// Slot `pad` (>= 0 for an odd batch) takes a copy of the last visibility's rows
+// with zero visibility.  Called by all 64 lanes of a wave.
 template <int P, bool CPLX, bool TRI, int WR>
 __device__ __forceinline__ void stage_wave_gap(const WaveIn<P>& in, int n, int win_x0, int win_y0,
                                                const MfmaDev& d, uint32_t tab_base, unsigned char* __restrict__ slice,
@@ -513,23 +486,10 @@ __device__ __forceinline__ void stage_wave_gap(const WaveIn<P>& in, int n, int w
   const bool live = lane < n;
   const Record r = in.r;
   const int xr = rec_x0(r) - win_x0, yr = rec_y0(r) - win_y0;
-  uint32_t sk = live ? (((spread6((uint32_t)xr) | (spread6((uint32_t)yr) << 1)) << 6) | (uint32_t)lane)
-                     : ((1u << 20) | (uint32_t)lane);
-  sk = bitonic_merge<2, 1>(sk, lane);
-  sk = bitonic_merge<4, 2>(sk, lane);
-  sk = bitonic_merge<8, 4>(sk, lane);
-  sk = bitonic_merge<16, 8>(sk, lane);
-  sk = bitonic_merge<32, 16>(sk, lane);
-  sk = bitonic_merge<64, 32>(sk, lane);
-  // lane i holds the i-th key: its visibility's rank goes back to the owner, its
-  // footprint origin comes to lane i, and lane i^1 holds the pair partner's
-  const int src_lane = (int)(sk & 63u);
-  const int rank = __builtin_amdgcn_ds_permute(src_lane << 2, lane);
-  const int xy_own = xr | (yr << 8);
-  const int xy = __builtin_amdgcn_ds_bpermute(src_lane << 2, xy_own);
-  const int xy_partner = (int)lane_xor<1>((uint32_t)xy);
-  // the pair mask, formed by the even lane of each sorted pair and sent back to
-  // the owners of both members
+  const int rank = lane;
+  const int xy = xr | (yr << 8);
+  const int xy_partner = (int)lane_xor1((uint32_t)xy);
+  // the pair mask, formed by the even lane of each pair and shared with the odd one
   uint32_t box = 0u;
   {
     const int xb = (lane + 1 < n) ? xy_partner : xy;
@@ -540,7 +500,8 @@ __device__ __forceinline__ void stage_wave_gap(const WaveIn<P>& in, int n, int w
     const uint32_t cbits = ((2u << c_hi) - 1u) & ~((1u << c_lo) - 1u);
     box = rbits | (cbits << 16);
   }
-  const uint32_t box_even = (uint32_t)__shfl(box, rank & ~1);    // the mask of the owner's pair
+  const uint32_t box_partner = lane_xor1(box);
+  const uint32_t box_even = (lane & 1) ? box_partner : box;
   if (live) {
     const int lead = WR - d.S;
     const uint32_t bu = tab_base + (uint32_t)((lead + (rec_plane(r) * d.O + rec_sx(r)) * WR - xr) * ES);
@@ -896,6 +857,7 @@ grid_mfma_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvis
 template <int P, bool CPLX, int WR, int WCG, int NG, int THREADS, bool TRI>
 __global__ void __launch_bounds__(THREADS)
 grid_mfma_waves(const Record* __restrict__ rec, const float2* __restrict__ wvis,
+                const int32_t* __restrict__ order,
                 const int4* __restrict__ segs, const int32_t* __restrict__ n_segs_p,
                 int32_t* __restrict__ counter, const void* __restrict__ taps,
                 float2* __restrict__ grid, MfmaDev d, uint32_t tap_bytes) {
@@ -931,7 +893,7 @@ grid_mfma_waves(const Record* __restrict__ rec, const float2* __restrict__ wvis,
       const int nb = min(kWaveBatch, len - b0);
       // (reading the next batch ahead measured no faster and costs registers)
       WaveIn<P> in;
-      load_wave<P>(rec, wvis, (int64_t)begin + b0, nb, in);
+      load_wave<P>(rec, wvis, order, (int64_t)begin + b0, nb, in);
       // the wave's own slice: LDS operations of one wave execute in order, so
       // only the compiler must be kept from moving accesses across these points
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -941,6 +903,58 @@ grid_mfma_waves(const Record* __restrict__ rec, const float2* __restrict__ wvis,
       wave_batch_gap<P, CPLX, TRI, WCG, NG, PARTS>(slice, nb, part, acc);
     }
     flush_window<P, WCG, NG, PARTS * RG>(acc, row0, win_x0, grid, d);
+  }
+}
+
+// Pairing order of the wave form: each segment's entries ordered by the D tiles
+// their footprint touches in the window, the class (first row group, first
+// column group, one more row group or not, one more column group or not), so
+// that consecutive entries, which the wave form pairs, mostly touch the same
+// tiles and a pair costs about what one of its visibilities costs.  A counting
+// sort per segment (one block each; the order within a class is arbitrary):
+// order[begin + k] is the k-th entry of segment [begin, begin + len).
+constexpr int kMaxBoxClasses = 128;
+__device__ __forceinline__ int box_class(const Record r, int win_x0, int win_y0, int S, int lg_rg, int nc) {
+  const int xr = rec_x0(r) - win_x0, yr = rec_y0(r) - win_y0;
+  const int rg = 1 << lg_rg;
+  const int dc = (((xr & 7) + S - 1) >> 3) - ((S - 1) >> 3);
+  const int dg = (((yr & (rg - 1)) + S - 1) >> lg_rg) - ((S - 1) >> lg_rg);
+  return (((yr >> lg_rg) * nc + (xr >> 3)) * 2 + dc) * 2 + dg;
+}
+
+__global__ void __launch_bounds__(256)
+order_segments_kernel(const Record* __restrict__ rec, const int4* __restrict__ segs,
+                      const int32_t* __restrict__ n_segs_p, int S, int lg_rg, int tile, int n_tx,
+                      int32_t* __restrict__ order) {
+  __shared__ int s_at[kMaxBoxClasses];
+  const int seg = blockIdx.x;
+  if (seg >= *n_segs_p) return;                       // uniform over the block
+  const int4 sg = segs[seg];
+  const int begin = sg.x, len = sg.y;
+  const int win_x0 = (sg.z % n_tx) * tile, win_y0 = (sg.z / n_tx) * tile;
+  const int nc = ((tile - 1) >> 3) + 1;
+  for (int c = threadIdx.x; c < kMaxBoxClasses; c += blockDim.x) s_at[c] = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < len; i += blockDim.x)
+    atomicAdd(&s_at[box_class(rec[begin + i], win_x0, win_y0, S, lg_rg, nc)], 1);
+  __syncthreads();
+  if (threadIdx.x < 64) {                             // exclusive scan, two classes per lane
+    const int lane = threadIdx.x;
+    const int a = s_at[2 * lane], b = s_at[2 * lane + 1];
+    int incl = a + b;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(incl, o);
+      if (lane >= o) incl += t;
+    }
+    const int excl = incl - a - b;
+    s_at[2 * lane] = excl;
+    s_at[2 * lane + 1] = excl + a;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < len; i += blockDim.x) {
+    const int c = box_class(rec[begin + i], win_x0, win_y0, S, lg_rg, nc);
+    order[begin + atomicAdd(&s_at[c], 1)] = begin + i;
   }
 }
 
@@ -1008,7 +1022,7 @@ __global__ void __launch_bounds__(64) zero_counter(int32_t* c) {
 
 using MfmaFn = void (*)(const Record*, const float2*, const int4*, const int32_t*, const void*,
                         float2*, MfmaDev);
-using WaveFn = void (*)(const Record*, const float2*, const int4*, const int32_t*, int32_t*,
+using WaveFn = void (*)(const Record*, const float2*, const int32_t*, const int4*, const int32_t*, int32_t*,
                         const void*, float2*, MfmaDev, uint32_t);
 
 // Wave-form launch shape: threads per block (one block per CU) from the
@@ -1187,13 +1201,20 @@ gr_status launch_mfma(const void* bins, const BinLayout& L, int n_pol, const gr_
   if (wave_lds <= 160 * 1024) {
     if ((st = ensure_lds_limit(reinterpret_cast<const void*>(wc.fn), wave_lds, "gr_grid_binned")) != GR_OK)
       return st;
-    // the work counter sits after the segment count in the bins workspace
+    // the work counter sits after the segment count in the bins workspace, the
+    // pairing order after the scan scratch
     int32_t* counter = const_cast<int32_t*>(nsegs) + 16;
+    auto* order = reinterpret_cast<int32_t*>(const_cast<char*>(base) + L.off_perm);
+    const int lg_rg = n_pol == 4 ? 2 : 4;
+    const int nc = ((L.tile - 1) >> 3) + 1, ng0 = ((L.tile - 1) >> lg_rg) + 1;
+    if (nc * ng0 * 4 > kMaxBoxClasses) return fail(GR_EUNSUPPORTED, "gr_grid_binned: binning tile too large");
+    order_segments_kernel<<<(unsigned)nb, 256, 0, stream>>>(rec, segs, nsegs, k.support, lg_rg, L.tile, L.n_tx,
+                                                            order);
     zero_counter<<<1, 64, 0, stream>>>(counter);
     const int64_t items = nb * wave_parts(n_pol, wr, wc.ng);
     const int waves = wc.threads / 64;
     const int blocks = (int)std::min<int64_t>((int64_t)device_cus(), (items + waves - 1) / waves);
-    hipLaunchKernelGGL(wc.fn, dim3((unsigned)blocks), dim3(wc.threads), wave_lds, stream, rec, wv, segs,
+    hipLaunchKernelGGL(wc.fn, dim3((unsigned)blocks), dim3(wc.threads), wave_lds, stream, rec, wv, order, segs,
                        nsegs, counter, k.taps, grid, d, (uint32_t)gap_tab_bytes(k, wr, wtri));
     return check_launch("gr_grid_binned (mfma waves)");
   }

@@ -73,7 +73,7 @@ gr_status launch_romein(const Record* rec, const float2* wvis, int64_t n_vis, in
 struct BinLayout {
   int tile, n_tx, n_ty, seg_len;
   int64_t n_tiles, max_segs;
-  size_t off_rec, off_wvis, off_count, off_cursor, off_segs, off_nsegs, off_scan, bytes;
+  size_t off_rec, off_wvis, off_count, off_cursor, off_segs, off_nsegs, off_scan, off_perm, bytes;
 };
 // tile edge T (cells): footprints of a tile fit the MFMA gridder's window of T + S
 // cells (32, 48 or 64), and always the 64-cell window of the other binned gridders
