@@ -138,7 +138,8 @@ gr_status gr_grid_records(const void* records, const void* wvis, int64_t n_vis, 
                           const gr_tuning* tuning, void* stream);
 
 /* Size in bytes of the `bins` buffer of gr_bin / gr_grid_binned (0 if the
- * arguments are invalid).  seg_len <= 0 selects the default (4096). */
+ * arguments are invalid), including 4 bytes per visibility for the pairing
+ * order that gr_grid_binned writes.  seg_len <= 0 selects the default (4096). */
 size_t gr_bin_bytes(int64_t n_vis, int32_t n_pol, int32_t support, int32_t height, int32_t width,
                     int32_t seg_len);
 
@@ -189,7 +190,13 @@ gr_status gr_preprocess_bin(const double* uvw, const void* vis, int32_t vis_dtyp
  * (1024 threads; 768 for W = 32 with n_pol = 4) whose waves take (segment,
  * row part) work from a counter in the bins workspace and stage their own
  * visibility batches, or, when the table leaves too little LDS for that, one
- * 256-thread block per segment.  The first form keeps W - S zero entries after
+ * 256-thread block per segment.  The first form pairs consecutive
+ * visibilities of an order that a small kernel writes into the bins
+ * workspace first: each segment sorted by the D tiles its footprints touch
+ * (first row group, first column group, and whether a footprint reaches one
+ * more of each), so that the two visibilities of a pair mostly touch the same
+ * tiles.  The call therefore writes to bins (the counter and that order);
+ * calls that share one bins buffer must not overlap.  The first form keeps W - S zero entries after
  * every table row (and before the first), so that no operand address needs a
  * clamp: W - S + planes x O x W entries of 12 bytes ((-Im, Re, Im)) where that
  * fits beside the waves' staging (32 pair records each, 1.3 to 3.8 KiB),
@@ -337,7 +344,7 @@ gr_status gr_grid(const double* uvw, const void* vis, int32_t vis_dtype, const f
  * that the library holds on every device it runs on until the process ends
  * (its address is looked up once per device, on the first call there).
  * Calls whose gr_grid_workspace_bytes exceeds it return GR_ENOMEM before
- * anything is enqueued: with n_pol = 4, about 1.3 million visibilities on a
+ * anything is enqueued: with n_pol = 4, about 1.26 million visibilities on a
  * 4096^2 grid.  Nothing is allocated and no allocating routine is called.
  * Every call on one device shares that device's array, and the kernels
  * clear what must start at zero; calls that overlap on one device (other
