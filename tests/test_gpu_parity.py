@@ -307,6 +307,67 @@ def test_bin_is_a_grouping_of_the_valid_stream(R):
         assert np.all(x0[b:b + ln] // T == t % n_tx) and np.all(y0[b:b + ln] // T == t // n_tx)
 
 
+def _box_class(xr, yr, S, rg, tile):
+    """The pairing class of a footprint at (xr, yr) in its window: first row
+    group, first column group of 8, and whether it reaches one more of each."""
+    nc = (tile - 1) // 8 + 1
+    dc = ((xr % 8) + S - 1) // 8 - (S - 1) // 8
+    dg = ((yr % rg) + S - 1) // rg - (S - 1) // rg
+    return (((yr // rg) * nc + xr // 8) * 2 + dc) * 2 + dg
+
+
+@pytest.mark.parametrize("S,P,seg", [(32, 4, 300), (16, 4, 4096), (32, 1, 77), (8, 4, 1000)])
+def test_pairing_order_is_a_class_sort_of_each_segment(R, S, P, seg):
+    """gr_grid_binned's pairing order (the last region of the bins buffer): per
+    segment a permutation of the segment's entries, their D-tile classes
+    non-decreasing (entries of one class may come in any order); and the grid
+    equals the FP64 oracle's."""
+    from paper_1605_07023_amd import binding as B
+    _say(f"pairing order S={S} P={P} seg_len={seg}")
+    rng = np.random.default_rng(S + P + seg)
+    H, W = 200, 168
+    wl = random_point_workload(4000, P, H, W, S, 8, seed=S * 7 + P, n_planes=3, margin=4,
+                               weights=False, kernel="wsep")
+    wl.vis = (rng.integers(-2, 3, (wl.n_vis, P)) + 1j * rng.integers(-2, 3, (wl.n_vis, P))).astype(np.complex64)
+    taps = rng.integers(-1, 2, (3, 8, S)) + 1j * rng.integers(-1, 2, (3, 8, S))
+    t = torch.from_numpy(np.ascontiguousarray(np.stack([taps.real, taps.imag], axis=-1), dtype=np.float32)).to(DEV)
+    dw = R.upload(wl, DEV, taps=t)
+    k = B.make_kernel(t, S, 8, 3, taps_complex=True, w_min=wl.w_min, inv_dw=wl.inv_dw)
+    rec, wv = R.preprocess(dw)
+    N = wl.n_vis
+    nb = B.gr_bin_bytes(N, P, S, H, W, seg)
+    bins = torch.zeros(nb, dtype=torch.uint8, device=DEV)
+    B.gr_bin(rec, wv, N, P, S, H, W, seg, bins, nb)
+    g = torch.zeros((P, H, W), dtype=torch.complex64, device=DEV)
+    B.gr_grid_binned(bins, N, P, k, seg, g, H, W)
+    torch.cuda.synchronize()
+    ref, _ = _oracle_grid(wl, taps)
+    np.testing.assert_array_equal(g.cpu().numpy().astype(np.complex128), ref)
+    raw = bins.cpu().numpy()
+    r_all = raw[:8 * N].view(np.uint64)
+    order = raw[nb - (4 * N + 255) // 256 * 256:][:4 * N].view(np.int32)
+    T = (32 if S <= 16 else 48 if S <= 32 else 64) - S
+    rg = 16 // P
+    n_tx, n_ty = -(-W // T), -(-H // T)
+    off = (8 * N + 255) // 256 * 256 + (8 * P * N + 255) // 256 * 256
+    off += 2 * ((4 * n_tx * n_ty + 255) // 256 * 256)
+    max_segs = n_tx * n_ty + -(-N // seg)
+    segs = raw[off:off + 16 * max_segs].view(np.int32).reshape(-1, 4)
+    n_segs = int(raw[off + (16 * max_segs + 255) // 256 * 256:][:4].view(np.int32)[0])
+    assert n_segs > 1
+    multi = 0
+    for b, ln, tid, _ in segs[:n_segs]:
+        o = order[b:b + ln].astype(np.int64)
+        np.testing.assert_array_equal(np.sort(o), np.arange(b, b + ln))
+        r = r_all[o]
+        xr = (r & np.uint64(0xFFFF)).astype(np.int64) - (tid % n_tx) * T
+        yr = ((r >> np.uint64(16)) & np.uint64(0xFFFF)).astype(np.int64) - (tid // n_tx) * T
+        c = _box_class(xr, yr, S, rg, T)
+        assert np.all(np.diff(c) >= 0)
+        multi += len(np.unique(c)) > 1
+    assert multi > 0
+
+
 @pytest.mark.parametrize("cu,cv", TUNINGS_P4)
 @pytest.mark.parametrize("S", [8, 16])
 def test_grid_points_wkernel_p4(R, cu, cv, S):
