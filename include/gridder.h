@@ -405,7 +405,14 @@ gr_status gr_make_kb_table(double beta, int32_t support, int32_t oversample, int
  * with nu_j = (j + 1/2)/M - 1/2, t the image response of a Kaiser-Bessel
  * window of width support_aa and shape beta, w_hat = w_hat_first + plane *
  * w_hat_step (w in pixel units), M = n_samples (<= 0: 4 S), c normalising the
- * w = 0, s = 0 taps to unit sum, and g = 0 where |d| >= S/2. */
+ * w = 0, s = 0 taps to unit sum, and g = 0 where |d| >= S/2.  When the planes'
+ * w_hat values are symmetric about 0 (w_hat_first + (n_planes - 1) / 2 *
+ * w_hat_step within 1e-12 of their range), plane n_planes - 1 - p holds
+ * exactly the complex conjugates of plane p: the lower plane of each mirror
+ * pair is evaluated at the negated w_hat of its partner (the middle plane of an
+ * odd count at 0), and the samples at nu and -nu are summed together.
+ * gr_grid_binned recognises such tables and reads conjugates from the mirror
+ * plane instead of flipping signs. */
 gr_status gr_make_wkernel_table(int32_t support, int32_t oversample, int32_t n_planes,
                                 double w_hat_first, double w_hat_step, int32_t support_aa,
                                 double beta, int32_t n_samples, int32_t out_dtype, void* out,

@@ -388,14 +388,15 @@ constexpr int gap_es() { return CPLX ? (TRI ? 12 : 8) : 4; }
 template <bool CPLX, bool TRI, int WR>
 __device__ __forceinline__ void stage_taps_gap(float* __restrict__ lds, const void* __restrict__ taps,
                                                const MfmaDev& d) {
-  const int S = d.S, lead = WR - S;
+  const int S = d.S, lead = WR - S, np = d.n_rows_tab / d.O;
   const int n_elem = lead + d.n_rows_tab * WR;
   for (int e = threadIdx.x; e < n_elem; e += blockDim.x) {
     const int q = e - lead;
-    const int row = q >= 0 ? q / WR : 0;
+    const int row = q >= 0 ? q / WR : 0;              // LDS row s * n_planes + plane
     const int t = q - row * WR;
     const bool in = q >= 0 && t < S;
-    const int64_t src = (int64_t)row * S + (in ? t : 0);
+    const int src_row = (row % np) * d.O + row / np;  // table row plane * O + s
+    const int64_t src = (int64_t)src_row * S + (in ? t : 0);
     if constexpr (CPLX) {
       const float re = in ? load_tap32(taps, 2 * src, d.tap_dtype) : 0.f;
       const float im = in ? load_tap32(taps, 2 * src + 1, d.tap_dtype) : 0.f;
@@ -440,29 +441,48 @@ __device__ __forceinline__ void load_wave(const Record* __restrict__ rec, const 
   }
 }
 
-// Staged pair records of the wave form.  Per pair: for each of its two
-// visibilities {B start, A start, pair mask}, the LDS byte addresses of its
-// G^u and G^v rows minus ES times its window-relative x0 or y0, and the mask of
-// the row groups (bits 0..15) and column groups (bits 16..23) of the window
-// that either footprint touches; then the visibilities, P per visibility, as
-// (Re, Im) (triple table) or as (-Im, Re, Im) (pair table and real taps: lane
-// class comp reads the two values at comp * 4, which gives component comp of
-// G^v V with the same two multiplies as with triple entries, and component comp
-// of V as the second value).  A wave's slice holds the 32
-// records of a batch.
+// Staged pair records of the wave form.  Per pair a 28-byte header: for each of
+// its two visibilities {B start, A start}, the LDS byte addresses of its G^u
+// and G^v rows minus ES times its window-relative x0 or y0; then the two B
+// starts of the rows of the mirror plane (n_planes - 1 - plane, used when the
+// table's planes are conjugate pairs, as those of a W kernel sampled at w
+// values symmetric about 0 are); then the mask of the row groups (bits 0..15)
+// and column groups (bits 16..23) of the window that either footprint touches.
+// Then the visibilities, P per visibility, as (Re, Im) (triple table) or as
+// (-Im, Re, Im) (pair table and real taps: lane class comp reads the two values
+// at comp * 4, which gives component comp of G^v V with the same two multiplies
+// as with triple entries, and component comp of V as the second value).  A
+// wave's slice holds the 32 records of a batch.
+constexpr int kGapHdr = 28;
 template <int P, bool TRI>
 __host__ __device__ constexpr int gap_vis_bytes() { return TRI ? 8 : 12; }
 template <int P, bool TRI>
-__host__ __device__ constexpr int gap_rec_bytes() { return 24 + 2 * P * gap_vis_bytes<P, TRI>(); }
+__host__ __device__ constexpr int gap_rec_bytes() { return kGapHdr + 2 * P * gap_vis_bytes<P, TRI>(); }
 __host__ __device__ constexpr size_t gap_slice_bytes(int n_pol, bool tri) {
   return (size_t)(kWaveBatch / 2) *
          (n_pol == 4 ? (tri ? gap_rec_bytes<4, true>() : gap_rec_bytes<4, false>())
                      : (tri ? gap_rec_bytes<1, true>() : gap_rec_bytes<1, false>()));
 }
-struct __attribute__((aligned(4))) Inf3 {
-  uint32_t u, v, box;
-};
-typedef __attribute__((address_space(3))) const Inf3 lds_inf3;
+typedef __attribute__((address_space(3))) const uint32_t lds_u32;
+__device__ __forceinline__ uint32_t lds_read_u32(uint32_t addr) { return *(lds_u32*)(uintptr_t)addr; }
+
+// Whether every plane of the staged gapped table (complex entries, (Re, Im)
+// pairs) holds the complex conjugates of the taps of the mirror plane
+// n_planes - 1 - plane, compared exactly.  Called by every thread of the block
+// after the table is staged; the result is the same in every thread.
+template <int WR>
+__device__ bool planes_conjugate(const float* __restrict__ tab, const MfmaDev& d) {
+  const int S = d.S, O = d.O, lead = WR - S, np = d.n_rows_tab / O;
+  const int n = d.n_rows_tab * S;
+  int bad = 0;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int row = e / S, t = e - row * S;          // LDS row s * np + p
+    const int s = row / np, p = row - s * np;
+    const int a = lead + row * WR + t, b = lead + (s * np + np - 1 - p) * WR + t;
+    bad |= !(tab[2 * a] == tab[2 * b] && tab[2 * a + 1] == -tab[2 * b + 1]);
+  }
+  return __syncthreads_or(bad) == 0;
+}
 
 // The value of lane i ^ 1 (a DPP quad permutation, no LDS round trip).
 __device__ __forceinline__ uint32_t lane_xor1(uint32_t x) {
@@ -473,8 +493,9 @@ __device__ __forceinline__ uint32_t lane_xor1(uint32_t x) {
 // Stage a batch read by load_wave (lanes < n live) as pair records: lanes 2q
 // and 2q + 1 form pair q (the segment's pairing order, order_segments_kernel).
 // Slot `pad` (>= 0 for an odd batch) takes a copy of the last visibility's rows
-// with zero visibility.  Called by all 64 lanes of a wave.
-template <int P, bool CPLX, bool TRI, int WR>
+// with zero visibility.  MIRROR: also the B starts of the mirror plane's rows.
+// Called by all 64 lanes of a wave.
+template <int P, bool CPLX, bool TRI, int WR, bool MIRROR>
 __device__ __forceinline__ void stage_wave_gap(const WaveIn<P>& in, int n, int win_x0, int win_y0,
                                                const MfmaDev& d, uint32_t tab_base, unsigned char* __restrict__ slice,
                                                int pad) {
@@ -504,15 +525,28 @@ __device__ __forceinline__ void stage_wave_gap(const WaveIn<P>& in, int n, int w
   const uint32_t box_even = (lane & 1) ? box_partner : box;
   if (live) {
     const int lead = WR - d.S;
-    const uint32_t bu = tab_base + (uint32_t)((lead + (rec_plane(r) * d.O + rec_sx(r)) * WR - xr) * ES);
-    const uint32_t av = tab_base + (uint32_t)((lead + (rec_plane(r) * d.O + rec_sy(r)) * WR - yr) * ES);
+    const int plane = rec_plane(r), np = d.n_rows_tab / d.O;
+    const uint32_t bu = tab_base + (uint32_t)((lead + (rec_sx(r) * np + plane) * WR - xr) * ES);
+    const uint32_t av = tab_base + (uint32_t)((lead + (rec_sy(r) * np + plane) * WR - yr) * ES);
     unsigned char* rec = slice + (rank >> 1) * RB;
-    uint32_t* inf = reinterpret_cast<uint32_t*>(rec + (rank & 1) * 12);
-    inf[0] = bu; inf[1] = av; inf[2] = box_even;
-    if (pad >= 0 && rank == n - 1) {                  // n - 1 is even here: slot n is its partner
-      inf[3] = bu; inf[4] = av; inf[5] = box_even;
+    uint32_t* hdr = reinterpret_cast<uint32_t*>(rec);
+    const int v = rank & 1;
+    hdr[2 * v] = bu;
+    hdr[2 * v + 1] = av;
+    uint32_t bm = 0u;
+    if constexpr (MIRROR) {
+      // the row of plane np - 1 - plane lies np - 1 - 2 plane rows away: an odd
+      // number for an even plane count, which puts it in the other half of the
+      // LDS banks (a row is WR * ES / 4 = 32 mod 64 words long)
+      bm = bu + (uint32_t)((np - 1 - 2 * plane) * WR * ES);
+      hdr[4 + v] = bm;
     }
-    float* vis = reinterpret_cast<float*>(rec + 24 + (rank & 1) * P * VS);
+    if (v == 0) hdr[6] = box_even;
+    if (pad >= 0 && rank == n - 1) {                  // n - 1 is even here: slot n is its partner
+      hdr[2] = bu; hdr[3] = av;
+      if constexpr (MIRROR) hdr[5] = bm;
+    }
+    float* vis = reinterpret_cast<float*>(rec + kGapHdr + v * P * VS);
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       if constexpr (TRI) {
@@ -526,12 +560,14 @@ __device__ __forceinline__ void stage_wave_gap(const WaveIn<P>& in, int n, int w
     }
   }
   if (pad >= 0 && lane < P * VS / 4)
-    reinterpret_cast<float*>(slice + (pad >> 1) * RB + 24 + P * VS)[lane] = 0.f;
+    reinterpret_cast<float*>(slice + (pad >> 1) * RB + kGapHdr + P * VS)[lane] = 0.f;
 }
 
 // The work of one wave of the wave form on one staged batch (gapped table): row
 // groups part + j * PARTS (j < NG) and all WCG column groups of the window.
-template <int P, bool CPLX, bool TRI, int WCG, int NG, int PARTS>
+// MIRROR (pair table whose planes are conjugate pairs): the lanes that need
+// -Im g read Im of the mirror plane's row instead of flipping a sign.
+template <int P, bool CPLX, bool TRI, int WCG, int NG, int PARTS, bool MIRROR>
 __device__ __forceinline__ void wave_batch_gap(const unsigned char* __restrict__ slice, int nb, int part,
                                                f4 (&acc)[NG][WCG]) {
   constexpr int RG = 16 / P;
@@ -552,30 +588,33 @@ __device__ __forceinline__ void wave_batch_gap(const unsigned char* __restrict__
   if constexpr (CPLX && TRI) off_b += (comp == 1 && bcomp == 0) ? 0u : (comp == 0 && bcomp == 1) ? 8u : 4u;
   if constexpr (CPLX && !TRI) {
     off_b += comp == bcomp ? 0u : 4u;
-    sgn_b = (comp == 1 && bcomp == 0) ? 0x80000000u : 0u;
+    if constexpr (!MIRROR) sgn_b = (comp == 1 && bcomp == 0) ? 0x80000000u : 0u;
   }
   if constexpr (!CPLX) bm = comp == bcomp ? 1.f : 0.f;
   // A: component comp of G^v V for row part * RG + ar of the window
   const uint32_t off_a = (uint32_t)((part * RG + ar) * ES) + ((CPLX && TRI) ? (uint32_t)(comp * 4) : 0u);
   // this lane's fields of a pair record
   const uint32_t base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const unsigned char*)slice;
-  const uint32_t l_inf = base + (uint32_t)(v * 12);
-  const uint32_t l_vis = base + (uint32_t)(24 + (v * P + ap) * VS + (TRI ? 0 : comp * 4));
+  const bool from_mirror = MIRROR && comp == 1 && bcomp == 0;
+  const uint32_t l_b = base + (uint32_t)(from_mirror ? 16 + 4 * v : 8 * v);
+  const uint32_t l_a = base + (uint32_t)(8 * v + 4);
+  const uint32_t l_box = base + 24u;
+  const uint32_t l_vis = base + (uint32_t)(kGapHdr + (v * P + ap) * VS + (TRI ? 0 : comp * 4));
   auto pair = [&](uint32_t o) {
-    const lds_inf3* ip = (lds_inf3*)(uintptr_t)(l_inf + o);
-    const Inf3 inf{ip->u, ip->v, ip->box};
+    const uint32_t row_u = lds_read_u32(l_b + o);
+    const uint32_t row_v = lds_read_u32(l_a + o);
+    const uint32_t box = __builtin_amdgcn_readfirstlane(lds_read_u32(l_box + o));
     const Pair4 vv = lds_read2(l_vis + o);
-    const uint32_t box = __builtin_amdgcn_readfirstlane(inf.box);
     float bfr[WCG];
     {
-      const uint32_t b = inf.u + off_b;
+      const uint32_t b = row_u + off_b;
 #pragma unroll
       for (int c = 0; c < WCG; ++c) bfr[c] = lds_read(b + (uint32_t)(c * 8 * ES));
     }
     Pair4 at[NG];
     float as[NG];
     {
-      const uint32_t a = inf.v + off_a;
+      const uint32_t a = row_v + off_a;
 #pragma unroll
       for (int j = 0; j < NG; ++j) {
         const uint32_t aj = a + (uint32_t)(j * PARTS * RG * ES);
@@ -583,7 +622,9 @@ __device__ __forceinline__ void wave_batch_gap(const unsigned char* __restrict__
         else as[j] = lds_read(aj);
       }
     }
-    if constexpr (CPLX && !TRI) {
+    // every operand read of the pair is issued before any is used
+    if constexpr (MIRROR) __builtin_amdgcn_sched_barrier(0);
+    if constexpr (CPLX && !TRI && !MIRROR) {
 #pragma unroll
       for (int c = 0; c < WCG; ++c) bfr[c] = __uint_as_float(__float_as_uint(bfr[c]) ^ sgn_b);
     }
@@ -852,27 +893,16 @@ grid_mfma_kernel(const Record* __restrict__ rec, const float2* __restrict__ wvis
   }
 }
 
-// Wave form (see the file header).  PARTS = (WR / RG) / NG items per segment;
-// TRI: triple table entries (complex taps).
-template <int P, bool CPLX, int WR, int WCG, int NG, int THREADS, bool TRI>
-__global__ void __launch_bounds__(THREADS)
-grid_mfma_waves(const Record* __restrict__ rec, const float2* __restrict__ wvis,
-                const int32_t* __restrict__ order,
-                const int4* __restrict__ segs, const int32_t* __restrict__ n_segs_p,
-                int32_t* __restrict__ counter, const void* __restrict__ taps,
-                float2* __restrict__ grid, MfmaDev d, uint32_t tap_bytes) {
+// The item loop of the wave form: (segment, part) items from the atomic counter
+// until they run out.
+template <int P, bool CPLX, int WR, int WCG, int NG, bool TRI, bool MIRROR>
+__device__ __forceinline__ void wave_items(const Record* __restrict__ rec, const float2* __restrict__ wvis,
+                                           const int32_t* __restrict__ order, const int4* __restrict__ segs,
+                                           int n_items, int32_t* __restrict__ counter, float2* __restrict__ grid,
+                                           const MfmaDev& d, uint32_t tab_base, unsigned char* __restrict__ slice) {
   constexpr int RG = 16 / P;
   constexpr int PARTS = WR / RG / NG;
-  constexpr int ES = gap_es<CPLX, TRI>();
-  static_assert(PARTS * NG * RG == WR, "window rows must split into parts of NG row groups");
-  static_assert(WR / RG <= 16 && WCG <= 8, "pair masks hold 16 row groups and 8 column groups");
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  unsigned char* slice = lds_raw + tap_bytes + (size_t)wave * gap_slice_bytes(P, TRI);
-  const uint32_t tab_base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned char*)lds_raw;
-  stage_taps_gap<CPLX, TRI, WR>(reinterpret_cast<float*>(lds_raw), taps, d);
-  __syncthreads();                                    // the only block barrier
-  const int n_items = *n_segs_p * PARTS;
+  const int lane = threadIdx.x & 63;
   for (;;) {
     int item = 0;
     if (lane == 0) item = atomicAdd(counter, 1);
@@ -898,12 +928,43 @@ grid_mfma_waves(const Record* __restrict__ rec, const float2* __restrict__ wvis,
       // only the compiler must be kept from moving accesses across these points
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       // an odd batch (nb <= 63 here) is padded in slot nb
-      stage_wave_gap<P, CPLX, TRI, WR>(in, nb, win_x0, win_y0, d, tab_base, slice, (nb & 1) ? nb : -1);
+      stage_wave_gap<P, CPLX, TRI, WR, MIRROR>(in, nb, win_x0, win_y0, d, tab_base, slice, (nb & 1) ? nb : -1);
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      wave_batch_gap<P, CPLX, TRI, WCG, NG, PARTS>(slice, nb, part, acc);
+      wave_batch_gap<P, CPLX, TRI, WCG, NG, PARTS, MIRROR>(slice, nb, part, acc);
     }
     flush_window<P, WCG, NG, PARTS * RG>(acc, row0, win_x0, grid, d);
   }
+}
+
+// Wave form (see the file header).  PARTS = (WR / RG) / NG items per segment;
+// TRI: triple table entries (complex taps).  With the pair table, a table whose
+// planes are conjugate pairs takes the mirror-plane loop (no sign flips).
+template <int P, bool CPLX, int WR, int WCG, int NG, int THREADS, bool TRI>
+__global__ void __launch_bounds__(THREADS)
+grid_mfma_waves(const Record* __restrict__ rec, const float2* __restrict__ wvis,
+                const int32_t* __restrict__ order,
+                const int4* __restrict__ segs, const int32_t* __restrict__ n_segs_p,
+                int32_t* __restrict__ counter, const void* __restrict__ taps,
+                float2* __restrict__ grid, MfmaDev d, uint32_t tap_bytes) {
+  constexpr int RG = 16 / P;
+  constexpr int PARTS = WR / RG / NG;
+  static_assert(PARTS * NG * RG == WR, "window rows must split into parts of NG row groups");
+  static_assert(WR / RG <= 16 && WCG <= 8, "pair masks hold 16 row groups and 8 column groups");
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int wave = threadIdx.x >> 6;
+  unsigned char* slice = lds_raw + tap_bytes + (size_t)wave * gap_slice_bytes(P, TRI);
+  const uint32_t tab_base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned char*)lds_raw;
+  stage_taps_gap<CPLX, TRI, WR>(reinterpret_cast<float*>(lds_raw), taps, d);
+  __syncthreads();                                    // the only block barriers: here and in planes_conjugate
+  const int n_items = *n_segs_p * PARTS;
+  if constexpr (CPLX && !TRI) {
+    if (planes_conjugate<WR>(reinterpret_cast<const float*>(lds_raw), d)) {
+      wave_items<P, CPLX, WR, WCG, NG, TRI, true>(rec, wvis, order, segs, n_items, counter, grid, d, tab_base,
+                                                  slice);
+      return;
+    }
+  }
+  wave_items<P, CPLX, WR, WCG, NG, TRI, false>(rec, wvis, order, segs, n_items, counter, grid, d, tab_base, slice);
 }
 
 // Pairing order of the wave form: each segment's entries ordered by the D tiles

@@ -96,18 +96,35 @@ wkernel_table_kernel(int S, int O, int n_planes, double wh0, double whs, int aa,
     __syncthreads();
   }
   const double c = 1.0 / red[0];
-  const double wh = wh0 + (double)plane * whs;
+  double wh = wh0 + (double)plane * whs;
+  if (n_planes > 1) {
+    // planes at w values symmetric about 0 get exactly conjugate taps: the lower
+    // plane of a mirror pair takes the exact negative of its partner's w (the
+    // middle plane of an odd count takes 0), and every rounding below commutes
+    // with negating w
+    const double wm = wh0 + (double)(n_planes - 1 - plane) * whs;
+    if (fabs(wh + wm) <= 1e-12 * (fabs(wh0) + fabs(whs) * (double)(n_planes - 1))) {
+      if (2 * plane + 1 == n_planes) wh = 0.0;
+      else if (2 * plane + 1 < n_planes) wh = -wm;
+    }
+  }
   for (int k = threadIdx.x; k < S; k += blockDim.x) {
     const double d = (double)(k - S / 2 + 1) - (double)s / (double)O;
     double re = 0.0, im = 0.0;
     if (fabs(d) < 0.5 * S) {
-      for (int j = 0; j < M; ++j) {
+      // the samples at nu and -nu summed together:
+      //   exp(-i pi (w nu^2 + 2 d nu)) + exp(-i pi (w nu^2 - 2 d nu)) = 2 cos(2 pi d nu) exp(-i pi w nu^2)
+      for (int j = 0; j < M / 2; ++j) {
         const double nu = ((double)j + 0.5) / (double)M - 0.5;
+        const double a = wh * nu * nu;
         double sn, cs;
-        sincospi(wh * nu * nu + 2.0 * d * nu, &sn, &cs);   // exp(-i pi a) = cos - i sin
-        re += taper[j] * cs;
-        im -= taper[j] * sn;
+        sincospi(fabs(a), &sn, &cs);
+        if (a < 0.0) sn = -sn;
+        const double t = 2.0 * taper[j] * cospi(2.0 * d * nu);
+        re += t * cs;                                       // exp(-i pi a) = cos - i sin
+        im -= t * sn;
       }
+      if (M & 1) re += taper[M / 2];                        // nu = 0
       re *= c;
       im *= c;
     }

@@ -158,31 +158,65 @@ def test_grid_points_mfma(R, S, P, seg):
 # table needs (complex W taps, O = 8; 160 KiB of LDS):
 #   wave form, gapped table (rows of W entries, W = 48 at S = 32, 32 at S = 16, plus
 #   a lead of W - S), triple entries (12 B) or (Re, Im) pairs (8 B), + one slice of
-#   32 pair records per wave (16 waves at S = 32, 12 at S = 16; P = 4: 2816 B with
-#   triples, 3840 B with pairs; P = 1: 1280 B / 1536 B);
+#   32 pair records per wave (16 waves at S = 32, 12 at S = 16; P = 4: 2944 B with
+#   triples, 3968 B with pairs; P = 1: 1408 B / 1664 B);
 #   block form, rows of S + 2 entries, triple: table + 12,800 B (P = 4) / 6,656 B (P = 1);
 #   block form, (Re, Im) pairs: pair table + 12,288 B (P = 4).
 # At S = 32, 40 planes (320 rows) at P = 4 take the triple block form, 60 planes (480
 # rows) the pair block form, 48 planes (384 rows) at P = 1 the triple block form.
 # Wave form table kinds: at S = 32, P = 4, 5 planes fit triple entries, 32 planes
 # (256 rows, the full-shape table) only pairs; at P = 1, 36 planes (288 rows) take
-# pairs; at S = 16, P = 4, 48 planes (384 rows) take pairs.  Integer visibilities and
-# taps keep every sum exact, so each kind must equal the FP64 oracle bit for bit.
-@pytest.mark.parametrize("S,P,planes,rg", [(32, 4, 5, 0), (32, 4, 32, 0), (32, 4, 32, 4), (32, 1, 36, 0),
-                                           (16, 4, 5, 0), (16, 4, 48, 0), (16, 4, 48, 4)])
-def test_wave_form_table_kinds_bit_exact(R, S, P, planes, rg):
-    _say(f"wave form table kinds, integer inputs, S={S} P={P} planes={planes} row groups={rg}")
+# pairs; at S = 16, P = 4, 48 planes (384 rows) take pairs.  A pair table whose
+# planes are conjugate pairs (plane n - 1 - p the conjugate of plane p, as a W
+# kernel's at w symmetric about 0) is read through the mirror plane; `mirror`
+# builds such a table.  Integer visibilities and taps keep every sum exact, so
+# each kind must equal the FP64 oracle bit for bit.
+@pytest.mark.parametrize("S,P,planes,rg,mirror", [(32, 4, 5, 0, False), (32, 4, 32, 0, False),
+                                                  (32, 4, 32, 4, False), (32, 1, 36, 0, False),
+                                                  (16, 4, 5, 0, False), (16, 4, 48, 0, False),
+                                                  (16, 4, 48, 4, False), (32, 4, 32, 0, True),
+                                                  (32, 4, 31, 3, True), (32, 1, 36, 0, True),
+                                                  (16, 4, 48, 0, True)])
+def test_wave_form_table_kinds_bit_exact(R, S, P, planes, rg, mirror):
+    _say(f"wave form table kinds, integer inputs, S={S} P={P} planes={planes} row groups={rg} mirror={mirror}")
     rng = np.random.default_rng(S * 100 + planes + P)
     wl = random_point_workload(3000, P, 120, 104, S, 8, seed=planes + S, n_planes=planes, margin=4,
                                weights=False, kernel="wsep")
     wl.vis = (rng.integers(-2, 3, (wl.n_vis, P)) + 1j * rng.integers(-2, 3, (wl.n_vis, P))).astype(np.complex64)
     taps = rng.integers(-1, 2, (planes, 8, S)) + 1j * rng.integers(-1, 2, (planes, 8, S))
+    if mirror:
+        half = planes // 2
+        taps[planes - half:] = np.conj(taps[:half][::-1])
+        if planes & 1:
+            taps[half] = taps[half].real
+        assert np.array_equal(taps, np.conj(taps[::-1]))
     taps_np = np.stack([taps.real, taps.imag], axis=-1)
     g = _custom_taps_run(R, wl, taps_np, R.tuning(0, 0, 0, rg, 0, variant=2))
     ref, dropped = _oracle_grid(wl, taps)
     assert wl.n_vis - dropped > 2000
     assert np.abs(ref).max() < 2 ** 20
     np.testing.assert_array_equal(g.astype(np.complex128), ref)
+
+
+@pytest.mark.parametrize("S,planes,dt", [(32, 32, "f32"), (16, 32, "f32"), (16, 7, "f64"), (8, 1, "f32")])
+def test_wkernel_table_planes_conjugate(R, S, planes, dt):
+    """gr_make_wkernel_table at w values symmetric about 0 gives mirror planes
+    that are exact complex conjugates (the table form the gridder reads through
+    the mirror plane), and stays within 1e-12 of the FP64 oracle's taps."""
+    from paper_1605_07023_amd import binding as B
+    _say(f"W table conjugate planes S={S} planes={planes} dtype={dt}")
+    wh = np.linspace(-1.5 * S, 1.5 * S, planes) if planes > 1 else np.zeros(1)
+    step = float(wh[1] - wh[0]) if planes > 1 else 0.0
+    tdt, code = {"f32": (torch.float32, B.GR_F32), "f64": (torch.float64, B.GR_F64)}[dt]
+    out = torch.empty((planes, 8, S, 2), dtype=tdt, device=DEV)
+    B.gr_make_wkernel_table(S, 8, planes, float(wh[0]), step, max(S - 2, 1), 2.0 * S / 4, 0, code, out, None)
+    t = out.cpu().numpy().astype(np.float64)
+    z = t[..., 0] + 1j * t[..., 1]
+    np.testing.assert_array_equal(z, np.conj(z[::-1]))
+    assert np.abs(z).max() > 0.01
+    if dt == "f64":
+        ref = G.wkernel_table(S, 8, float(wh[0]) + step * np.arange(planes), max(S - 2, 1), 2.0 * S / 4)
+        assert np.abs(z - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
 @pytest.mark.parametrize("P,planes,seg", [(4, 40, 0), (4, 40, 77), (4, 60, 0), (1, 48, 9)])
