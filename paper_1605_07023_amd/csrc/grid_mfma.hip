@@ -39,7 +39,9 @@
 //    LDS slice, each visibility as the LDS addresses of its two tap rows and
 //    each pair as the mask of D tiles it touches (decoded once, not per use).
 //    Its table is gapped (zeros around every row of taps, so that operand
-//    reads need no clamp), with (-Im, Re, Im) entries where they fit.
+//    reads need no clamp), with (-Im, Re, Im) entries where they fit, else
+//    (Re, Im) entries, with -Im read from the mirror plane when the planes are
+//    conjugate pairs.
 //  * grid_mfma_kernel: one 256-thread block per segment, its 4 waves sharing
 //    the segment's window rows (the form used when the table leaves too little
 //    LDS for 16 wave slices).
@@ -373,15 +375,16 @@ __device__ __forceinline__ void wave_batch(const int4* __restrict__ b_inf, const
 // ---- wave form with a gapped tap table -------------------------------------
 // The wave form's table holds every row of S taps followed by WR - S zero
 // entries, after a lead of WR - S zeros: entry e = lead + row * WR + t for tap t
-// of a row.  A window-relative tap index lies in [-(WR - S - 1), WR - 1] (the
+// of LDS row s * n_planes + plane (phase-major).  A window-relative tap index lies in [-(WR - S - 1), WR - 1] (the
 // footprint origin is in the tile, WR - S cells, and the operand columns or rows
 // in the window), so every operand read of a row lands on its taps or on the
 // zeros around them: the address is the visibility's row start plus lane and
 // group constants, with no clamp (the constants go into the LDS instruction's
 // offset field).  Entries of complex taps are ES = 12 bytes, the triple
 // (-Im, Re, Im), where the table fits in LDS with that many wave slices, else
-// ES = 8 bytes (Re, Im), when the B operand of one lane class takes a sign flip
-// and the A operand two lane-constant factors; real taps are 4 bytes.
+// ES = 8 bytes (Re, Im), when the B operand of one lane class needs -Im (a sign
+// flip, or Im of the mirror plane) and the A operand two lane-constant
+// factors; real taps are 4 bytes.
 template <bool CPLX, bool TRI>
 constexpr int gap_es() { return CPLX ? (TRI ? 12 : 8) : 4; }
 
