@@ -239,7 +239,8 @@ __device__ __forceinline__ void stage_taps_wave(float* __restrict__ lds, const v
 }
 
 // Stage up to 64 visibilities of a segment batch (one per lane, lanes < n live)
-// for the wave form, in pairing order (pair_rank).  Per visibility: {B start,
+// for the block form with triple entries (each wave a quarter of the block's
+// batch), in pairing order (pair_rank).  Per visibility: {B start,
 // B row, A start, A row}, LDS byte addresses of its G^u and G^v rows (row =
 // first entry, start = row - ES * its window-relative x0 or y0), and its
 // visibilities.  Per pair: the row groups (bits 0..15) and column groups (bits
