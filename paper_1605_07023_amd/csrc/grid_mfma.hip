@@ -979,6 +979,7 @@ grid_mfma_waves(const Record* __restrict__ rec, const float2* __restrict__ wvis,
 // sort per segment (one block each; the order within a class is arbitrary):
 // order[begin + k] is the k-th entry of segment [begin, begin + len).
 constexpr int kMaxBoxClasses = 128;
+constexpr int kMaxCachedSeg = 65536;   // longest segment whose classes the ordering keeps in LDS
 __device__ __forceinline__ int box_class(const Record r, int win_x0, int win_y0, int S, int lg_rg, int nc) {
   const int xr = rec_x0(r) - win_x0, yr = rec_y0(r) - win_y0;
   const int rg = 1 << lg_rg;
@@ -987,11 +988,16 @@ __device__ __forceinline__ int box_class(const Record r, int win_x0, int win_y0,
   return (((yr >> lg_rg) * nc + (xr >> 3)) * 2 + dc) * 2 + dg;
 }
 
+// CACHE: each entry's class is kept in LDS (one byte per entry of the longest
+// segment, dynamic) between the counting and the placing pass, instead of
+// reading the record again.
+template <bool CACHE>
 __global__ void __launch_bounds__(256)
 order_segments_kernel(const Record* __restrict__ rec, const int4* __restrict__ segs,
                       const int32_t* __restrict__ n_segs_p, int S, int lg_rg, int tile, int n_tx,
                       int32_t* __restrict__ order) {
   __shared__ int s_at[kMaxBoxClasses];
+  extern __shared__ unsigned char s_cls[];
   const int seg = blockIdx.x;
   if (seg >= *n_segs_p) return;                       // uniform over the block
   const int4 sg = segs[seg];
@@ -1000,8 +1006,11 @@ order_segments_kernel(const Record* __restrict__ rec, const int4* __restrict__ s
   const int nc = ((tile - 1) >> 3) + 1;
   for (int c = threadIdx.x; c < kMaxBoxClasses; c += blockDim.x) s_at[c] = 0;
   __syncthreads();
-  for (int i = threadIdx.x; i < len; i += blockDim.x)
-    atomicAdd(&s_at[box_class(rec[begin + i], win_x0, win_y0, S, lg_rg, nc)], 1);
+  for (int i = threadIdx.x; i < len; i += blockDim.x) {
+    const int c = box_class(rec[begin + i], win_x0, win_y0, S, lg_rg, nc);
+    if constexpr (CACHE) s_cls[i] = (unsigned char)c;
+    atomicAdd(&s_at[c], 1);
+  }
   __syncthreads();
   if (threadIdx.x < 64) {                             // exclusive scan, two classes per lane
     const int lane = threadIdx.x;
@@ -1018,7 +1027,7 @@ order_segments_kernel(const Record* __restrict__ rec, const int4* __restrict__ s
   }
   __syncthreads();
   for (int i = threadIdx.x; i < len; i += blockDim.x) {
-    const int c = box_class(rec[begin + i], win_x0, win_y0, S, lg_rg, nc);
+    const int c = CACHE ? (int)s_cls[i] : box_class(rec[begin + i], win_x0, win_y0, S, lg_rg, nc);
     order[begin + atomicAdd(&s_at[c], 1)] = begin + i;
   }
 }
@@ -1273,8 +1282,12 @@ gr_status launch_mfma(const void* bins, const BinLayout& L, int n_pol, const gr_
     const int lg_rg = n_pol == 4 ? 2 : 4;
     const int nc = ((L.tile - 1) >> 3) + 1, ng0 = ((L.tile - 1) >> lg_rg) + 1;
     if (nc * ng0 * 4 > kMaxBoxClasses) return fail(GR_EUNSUPPORTED, "gr_grid_binned: binning tile too large");
-    order_segments_kernel<<<(unsigned)nb, 256, 0, stream>>>(rec, segs, nsegs, k.support, lg_rg, L.tile, L.n_tx,
-                                                            order);
+    if (L.seg_len <= kMaxCachedSeg)
+      order_segments_kernel<true><<<(unsigned)nb, 256, (size_t)L.seg_len, stream>>>(rec, segs, nsegs, k.support,
+                                                                                     lg_rg, L.tile, L.n_tx, order);
+    else
+      order_segments_kernel<false><<<(unsigned)nb, 256, 0, stream>>>(rec, segs, nsegs, k.support, lg_rg, L.tile,
+                                                                     L.n_tx, order);
     zero_counter<<<1, 64, 0, stream>>>(counter);
     const int64_t items = nb * wave_parts(n_pol, wr, wc.ng);
     const int waves = wc.threads / 64;
