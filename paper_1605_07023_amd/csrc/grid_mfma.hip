@@ -979,7 +979,7 @@ grid_mfma_waves(const Record* __restrict__ rec, const float2* __restrict__ wvis,
 // sort per segment (one block each; the order within a class is arbitrary):
 // order[begin + k] is the k-th entry of segment [begin, begin + len).
 constexpr int kMaxBoxClasses = 128;
-constexpr int kMaxCachedSeg = 65536;   // longest segment whose classes the ordering keeps in LDS
+constexpr int kMaxCachedSeg = 32768;   // longest segment whose classes the ordering keeps in LDS
 __device__ __forceinline__ int box_class(const Record r, int win_x0, int win_y0, int S, int lg_rg, int nc) {
   const int xr = rec_x0(r) - win_x0, yr = rec_y0(r) - win_y0;
   const int rg = 1 << lg_rg;
