@@ -350,12 +350,14 @@ def _box_class(xr, yr, S, rg, tile):
     return (((yr // rg) * nc + xr // 8) * 2 + dc) * 2 + dg
 
 
-@pytest.mark.parametrize("S,P,seg", [(32, 4, 300), (16, 4, 4096), (32, 1, 77), (8, 4, 1000)])
+@pytest.mark.parametrize("S,P,seg", [(32, 4, 300), (16, 4, 4096), (32, 1, 77), (8, 4, 1000), (32, 4, 32768),
+                                     (16, 4, 40000)])
 def test_pairing_order_is_a_class_sort_of_each_segment(R, S, P, seg):
     """gr_grid_binned's pairing order (the last region of the bins buffer): per
     segment a permutation of the segment's entries, their D-tile classes
     non-decreasing (entries of one class may come in any order); and the grid
-    equals the FP64 oracle's."""
+    equals the FP64 oracle's.  Segment lengths up to 32768 keep the classes in
+    LDS between the ordering's two passes, longer ones read the records again."""
     from paper_1605_07023_amd import binding as B
     _say(f"pairing order S={S} P={P} seg_len={seg}")
     rng = np.random.default_rng(S + P + seg)
