@@ -332,12 +332,27 @@ prebin_count_kernel(prep::PreArgs a, int tile, int n_tx, int32_t* __restrict__ c
   prep::add_block_counts(n_ok, n_drop, stats);
 }
 
+// Pass 2 of the fused binning, by blocks of kScatterBlock consecutive
+// visibilities: the block groups its entries by tile (a table of its distinct
+// tiles in LDS), reserves each tile's run in the list with one atomic, stages
+// the entries in LDS run by run, and then writes them so that consecutive
+// lanes write consecutive list slots.  Within a run, the entries of one wave
+// (64 consecutive visibilities) keep their input order.
+constexpr int kScatterBlock = 512;
 template <int VDT, int P>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kScatterBlock)
 prebin_scatter_kernel(prep::PreArgs a, int tile, int n_tx, int32_t* __restrict__ cursor,
                       Record* __restrict__ out_rec, float2* __restrict__ out_wvis,
                       unsigned long long* __restrict__ stats) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  constexpr int T = kScatterBlock, HS = kScatterBlock;     // at most T distinct tiles per block
+  __shared__ int s_key[HS], s_len[HS], s_start[HS], s_base[HS];
+  __shared__ Record s_rec[T];
+  __shared__ float2 s_vis[T * P];
+  __shared__ short s_slot[T];
+  __shared__ int s_wave_tot[T / 64];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t i = (int64_t)blockIdx.x * T + t;
+  for (int h = t; h < HS; h += T) { s_key[h] = -1; s_len[h] = 0; }
   int key = -1;
   Record r{0, 0};
   if (i < a.n) {
@@ -347,14 +362,77 @@ prebin_scatter_kernel(prep::PreArgs a, int tile, int n_tx, int32_t* __restrict__
   float2 vw[P];
   bool bad = false;
   if (key >= 0) bad = !prep::weighted_vis<VDT, P>(i, a, vw);
-  const int pos = reserve_grouped(key, cursor);
-  if (key >= 0) {
-    out_rec[pos] = r;
+  // the wave's lanes grouped by tile: group leader, rank in the group, group size
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  int leader = lane, rank = 0, count = 0;
+  {
+    uint64_t todo = __ballot(key >= 0);
+    while (todo) {
+      const int l = __ffsll((unsigned long long)todo) - 1;
+      const int k = __shfl(key, l);
+      const uint64_t same = __ballot(key == k);
+      if (key == k) {
+        leader = l;
+        rank = (int)__popcll(same & below);
+        count = (int)__popcll(same);
+      }
+      todo &= ~same;
+    }
+  }
+  __syncthreads();                                   // the table is cleared
+  // each group's leader finds (or claims) its tile's slot and takes the group's
+  // offset in the block's run of that tile
+  int slot = 0, off = 0;
+  if (key >= 0 && lane == leader) {
+    int h = (int)(((uint32_t)key * 2654435761u) >> 23) & (HS - 1);
+    for (;;) {
+      const int prev = atomicCAS(&s_key[h], -1, key);
+      if (prev == -1 || prev == key) break;
+      h = (h + 1) & (HS - 1);
+    }
+    slot = h;
+    off = atomicAdd(&s_len[h], count);
+  }
+  slot = __shfl(slot, leader);
+  off = __shfl(off, leader) + rank;
+  __syncthreads();                                   // every run length is final
+  // block-local run starts (exclusive scan of the run lengths over the slots,
+  // HS / T slots per thread) and one reservation per run in the tile's list
+  {
+    const int len = s_len[t];
+    int incl = len;
 #pragma unroll
-    for (int p = 0; p < P; ++p) out_wvis[(int64_t)pos * P + p] = vw[p];
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(incl, o);
+      if (lane >= o) incl += v;
+    }
+    if (lane == 63) s_wave_tot[w] = incl;
+    __syncthreads();
+    int before = 0;
+    for (int q = 0; q < w; ++q) before += s_wave_tot[q];
+    s_start[t] = before + incl - len;
+    if (len > 0) s_base[t] = atomicAdd(&cursor[s_key[t]], len);
+  }
+  __syncthreads();
+  int n_kept = 0;
+  for (int q = 0; q < T / 64; ++q) n_kept += s_wave_tot[q];
+  if (key >= 0) {
+    const int local = s_start[slot] + off;
+    s_rec[local] = r;
+#pragma unroll
+    for (int p = 0; p < P; ++p) s_vis[local * P + p] = vw[p];
+    s_slot[local] = (short)slot;
+  }
+  __syncthreads();
+  if (t < n_kept) {
+    const int h = s_slot[t];
+    const int64_t pos = (int64_t)s_base[h] + (t - s_start[h]);
+    out_rec[pos] = s_rec[t];
+#pragma unroll
+    for (int p = 0; p < P; ++p) out_wvis[pos * P + p] = s_vis[t * P + p];
   }
   const uint64_t n_bad = __ballot(bad);
-  if (n_bad != 0 && (threadIdx.x & 63) == 0 && stats != nullptr) {
+  if (n_bad != 0 && lane == 0 && stats != nullptr) {
     const unsigned long long nb = (unsigned long long)__popcll(n_bad);
     atomicAdd(&stats[0], 0ull - nb);                // modular: subtracts nb
     atomicAdd(&stats[1], nb);
@@ -482,7 +560,8 @@ gr_status launch_preprocess_bin(const double* uvw, const void* vis, int vis_dtyp
     Fn fn;
     if (n_pol == 4) fn = vis_dtype == GR_F32 ? prebin_scatter_kernel<GR_F32, 4> : prebin_scatter_kernel<GR_F16, 4>;
     else fn = vis_dtype == GR_F32 ? prebin_scatter_kernel<GR_F32, 1> : prebin_scatter_kernel<GR_F16, 1>;
-    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(256), 0, stream, a, L.tile, L.n_tx, cursor, orec, owv, st);
+    hipLaunchKernelGGL(fn, dim3((unsigned)((n_vis + kScatterBlock - 1) / kScatterBlock)), dim3(kScatterBlock), 0,
+                       stream, a, L.tile, L.n_tx, cursor, orec, owv, st);
   }
   return check_launch("gr_preprocess_bin");
 }
