@@ -230,6 +230,32 @@ def test_grid_points_mfma_block_forms(R, P, planes, seg):
     assert _rel_l2(g, ref) <= 1e-5
 
 
+@pytest.mark.parametrize("n,P", [(3000, 1), (1537, 4)])
+def test_fused_binning_many_tiles_per_block_bit_exact(R, n, P):
+    """The fused binning's scatter groups each block of 512 visibilities by
+    tile in a 512-slot table: on a 2048^2 grid of 16-cell tiles nearly every
+    visibility of a block has a tile of its own (the table nearly full), and a
+    ragged last block.  Integer values and taps: the grid of gr_grid (fused
+    binning, MFMA gridder) equals the FP64 oracle's bit for bit, statistics too."""
+    from paper_1605_07023_amd import binding as B
+    _say(f"fused binning, many tiles per block, n={n} P={P}")
+    rng = np.random.default_rng(n + P)
+    S, H, W = 16, 2048, 2048
+    wl = random_point_workload(n, P, H, W, S, 8, seed=n + 3 * P, n_planes=2, margin=4, weights=False,
+                               kernel="wsep")
+    wl.vis = (rng.integers(-2, 3, (wl.n_vis, P)) + 1j * rng.integers(-2, 3, (wl.n_vis, P))).astype(np.complex64)
+    taps = rng.integers(-1, 2, (2, 8, S)) + 1j * rng.integers(-1, 2, (2, 8, S))
+    t = torch.from_numpy(np.ascontiguousarray(np.stack([taps.real, taps.imag], axis=-1), dtype=np.float32)).to(DEV)
+    dw = R.upload(wl, DEV, taps=t)
+    dw.kernel = B.make_kernel(t, S, 8, 2, taps_complex=True, w_min=wl.w_min, inv_dw=wl.inv_dw)
+    stats = torch.zeros(2, dtype=torch.int64, device=DEV)
+    g = R.grid(dw, tune=R.tuning(vis_per_wg=64, variant=2), stats=stats).cpu().numpy()
+    ref, dropped = _oracle_grid(wl, taps)
+    assert stats.cpu().tolist() == [wl.n_vis - dropped, dropped]
+    assert wl.n_vis - dropped > n // 2
+    np.testing.assert_array_equal(g.astype(np.complex128), ref)
+
+
 @pytest.mark.parametrize("P,seg", [(4, 0), (1, 45)])
 def test_preprocess_bin_equals_separate_calls(R, P, seg):
     """gr_preprocess_bin (fused) + gr_grid_binned against gr_preprocess + gr_bin +
