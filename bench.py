@@ -42,10 +42,13 @@ def log(msg: str) -> None:
 
 
 def source_hash(variant: int) -> str:
+    """sha256[:16] over the kernel's source and the hipcc flags it is compiled with."""
+    from paper_1605_07023_amd.build import HIPCC_FLAGS, SOURCE_FLAGS
     h = hashlib.sha256()
     for f in KERNEL_SOURCES[variant]:
         with open(f, "rb") as fh:
             h.update(fh.read())
+        h.update(" ".join(HIPCC_FLAGS + SOURCE_FLAGS.get(os.path.basename(f), [])).encode())
     return h.hexdigest()[:16]
 
 

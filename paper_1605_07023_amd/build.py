@@ -18,6 +18,10 @@ HIPCC_FLAGS = [
     "-munsafe-fp-atomics",
     "-Wno-unused-command-line-argument",
 ]
+# per-source additions: the MFMA gridders schedule with LLVM's AMDGPU
+# "max-memory-clause" strategy (measured 0.7 % and 0.8 % faster at S = 32 and
+# S = 16 than the default; the ILP and register-minimising strategies were not)
+SOURCE_FLAGS = {"grid_mfma.hip": ["-mllvm", "-amdgpu-sched-strategy=max-memory-clause"]}
 
 
 def build(verbose: bool = False, jobs: int = 8) -> str:
@@ -29,8 +33,8 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     for src in SOURCES:
         obj = os.path.join(obj_dir, src.replace(".hip", ".o"))
         objs.append(obj)
-        cmd = [hipcc, *[f for f in HIPCC_FLAGS if f != "-shared"], "-c", "-I", os.path.join(ROOT, "include"),
-               "-o", obj, os.path.join(CSRC, src)]
+        cmd = [hipcc, *[f for f in HIPCC_FLAGS if f != "-shared"], *SOURCE_FLAGS.get(src, []), "-c", "-I",
+               os.path.join(ROOT, "include"), "-o", obj, os.path.join(CSRC, src)]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
