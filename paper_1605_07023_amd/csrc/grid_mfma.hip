@@ -1006,10 +1006,25 @@ order_segments_kernel(const Record* __restrict__ rec, const int4* __restrict__ s
   const int nc = ((tile - 1) >> 3) + 1;
   for (int c = threadIdx.x; c < kMaxBoxClasses; c += blockDim.x) s_at[c] = 0;
   __syncthreads();
-  for (int i = threadIdx.x; i < len; i += blockDim.x) {
-    const int c = box_class(rec[begin + i], win_x0, win_y0, S, lg_rg, nc);
-    if constexpr (CACHE) s_cls[i] = (unsigned char)c;
-    atomicAdd(&s_at[c], 1);
+  // kOrderIlp entries per thread and step, their record loads issued together
+  constexpr int kOrderIlp = 4;
+  const int step = kOrderIlp * (int)blockDim.x;
+  for (int i0 = threadIdx.x; i0 < len; i0 += step) {
+    Record r[kOrderIlp];
+#pragma unroll
+    for (int k = 0; k < kOrderIlp; ++k) {
+      const int i = i0 + k * (int)blockDim.x;
+      r[k] = i < len ? rec[begin + i] : Record{0, 0};
+    }
+#pragma unroll
+    for (int k = 0; k < kOrderIlp; ++k) {
+      const int i = i0 + k * (int)blockDim.x;
+      if (i < len) {
+        const int c = box_class(r[k], win_x0, win_y0, S, lg_rg, nc);
+        if constexpr (CACHE) s_cls[i] = (unsigned char)c;
+        atomicAdd(&s_at[c], 1);
+      }
+    }
   }
   __syncthreads();
   if (threadIdx.x < 64) {                             // exclusive scan, two classes per lane
@@ -1026,9 +1041,17 @@ order_segments_kernel(const Record* __restrict__ rec, const int4* __restrict__ s
     s_at[2 * lane + 1] = excl + a;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < len; i += blockDim.x) {
-    const int c = CACHE ? (int)s_cls[i] : box_class(rec[begin + i], win_x0, win_y0, S, lg_rg, nc);
-    order[begin + atomicAdd(&s_at[c], 1)] = begin + i;
+  for (int i0 = threadIdx.x; i0 < len; i0 += step) {
+    int c[kOrderIlp];
+#pragma unroll
+    for (int k = 0; k < kOrderIlp; ++k) {
+      const int i = i0 + k * (int)blockDim.x;
+      c[k] = i < len ? (CACHE ? (int)s_cls[i] : box_class(rec[begin + i], win_x0, win_y0, S, lg_rg, nc)) : -1;
+    }
+#pragma unroll
+    for (int k = 0; k < kOrderIlp; ++k) {
+      if (c[k] >= 0) order[begin + atomicAdd(&s_at[c[k]], 1)] = begin + i0 + k * (int)blockDim.x;
+    }
   }
 }
 
