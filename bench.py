@@ -23,6 +23,7 @@ import hashlib
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -497,7 +498,7 @@ def batch_leg(dev, stream, reps: int) -> dict:
     from synth import batch_workload
     wls = batch_workload()
     dws = [runner.upload(wl, dev) for wl in wls]
-    memo = autotune.Memo(os.path.join(ROOT, "gpurun_out", "bench_batch_memo.json"))
+    memo = autotune.Memo(os.path.join(tempfile.gettempdir(), "gridder_bench_batch_memo.json"))
     segs = autotune.batch_seg_lens(dws, memo)
     grids = [torch.zeros((wl.n_pol, wl.height, wl.width), dtype=torch.complex64, device=dev) for wl in wls]
     stats = [torch.zeros(2, dtype=torch.int64, device=dev) for _ in wls]
