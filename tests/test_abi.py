@@ -391,3 +391,28 @@ def test_tuning_memo_round_trip(lib):
     assert B.gr_tuning_memo_get(4, k, 64, 64, 0) is None
     assert B.gr_tuning_memo_get(4, k, 64, 64, 1) is None
     assert B.gr_grid_workspace_bytes(1000, 4, k, 64, 64) == binned
+
+
+def test_per_source_flags_name_built_sources():
+    """Every per-source hipcc addition names a source the library is built from,
+    and every HIP translation unit is built with packed FP32 instructions off."""
+    from paper_1605_07023_amd import build
+    assert set(build.SOURCE_FLAGS) <= set(build.SOURCES)
+    flags = " ".join(build.HIPCC_FLAGS)
+    assert "-Xclang -target-feature -Xclang -packed-fp32-ops" in flags
+    for src in build.SOURCES:
+        assert os.path.exists(os.path.join(build.CSRC, src)), src
+
+
+def test_traffic_record_hash_covers_the_compile_flags(monkeypatch):
+    """The hash that ties the stored HBM byte counts to the gridder changes with
+    the kernel's compile flags as well as with its source."""
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_1605_07023_amd import build
+    h0 = bench.source_hash(2)
+    monkeypatch.setitem(build.SOURCE_FLAGS, "grid_mfma.hip", ["-O2"])
+    assert bench.source_hash(2) != h0
+    monkeypatch.undo()
+    assert bench.source_hash(2) == h0
